@@ -1,0 +1,165 @@
+"""Seeded synthetic workloads: geometry, physical parameters and initial fields.
+
+This module is shared by the GPU path's tests and benchmark and by the oracle's tests, so it holds
+none of the method's arithmetic: only problem descriptions (sizes, walls, Ra/Pr/Ma or relaxation
+times) and initial macroscopic fields drawn from seeded generators
+(``numpy.random.default_rng(seed)``, PCG64) or written in closed form.  Each side maps the
+description onto its own interface.
+
+A workload is a dict::
+
+    {"name": str, "nx": int, "ny": int, "T0": float,
+     "edges": {"west"|"east"|"south"|"north": (kind, ux_w, uy_w, T_w)},   # kind: periodic|dirichlet|adiabatic
+     "physics": {"Ra", "Pr", "Ma", "H", "dT"}  or  "taus": {"tau_nu", "tau_alpha", "g_beta"},
+     "fields": {"rho", "ux", "uy", "T"}  (float64 arrays of shape (ny, nx), or None for a default)}
+
+Walls sit on nodes, so a wall-bounded extent of N nodes has length H = N - 1.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+PERIODIC = ("periodic", 0.0, 0.0, 0.0)
+
+
+def _edges(west=PERIODIC, east=PERIODIC, south=PERIODIC, north=PERIODIC):
+    return {"west": west, "east": east, "south": south, "north": north}
+
+
+def taylor_green(n=64, U0=0.01, T0=1.0, Tamp=0.01, tau_nu=0.8, tau_alpha=0.7):
+    """Fully periodic n x n Taylor-Green vortex with a sinusoidal temperature mode and no buoyancy.
+
+    u = U0 sin(kx) cos(ky), v = -U0 cos(kx) sin(ky), k = 2 pi / n at node coordinates; the
+    density carries the vortex's pressure, rho = 1 + 3 p with p = (U0^2/4)(cos 2kx + cos 2ky), so
+    that no sound wave is launched; T = T0 + Tamp sin(kx) sin(ky), a function of the stream function
+    so that advection leaves it unchanged."""
+    k = 2.0 * math.pi / n
+    x = np.arange(n, dtype=np.float64)[None, :]
+    y = np.arange(n, dtype=np.float64)[:, None]
+    ux = U0 * np.sin(k * x) * np.cos(k * y)
+    uy = -U0 * np.cos(k * x) * np.sin(k * y)
+    p = (U0 * U0 / 4.0) * (np.cos(2 * k * x) + np.cos(2 * k * y))
+    rho = 1.0 + 3.0 * p
+    T = T0 + Tamp * np.sin(k * x) * np.sin(k * y)
+    return {"name": f"taylor_green_{n}x{n}", "nx": n, "ny": n, "T0": T0, "edges": _edges(),
+            "taus": {"tau_nu": tau_nu, "tau_alpha": tau_alpha, "g_beta": 0.0},
+            "fields": {"rho": rho, "ux": ux, "uy": uy, "T": T},
+            "k": k, "U0": U0, "Tamp": Tamp}
+
+
+def cavity(L=256, Ra=1e5, Pr=0.71, Ma=0.1, seed=2, noise=1e-4, T_hot=0.5, T_cold=-0.5):
+    """Differentially heated square cavity of L x L nodes: hot west wall, cold east wall (Dirichlet),
+    adiabatic south and north walls, all no-slip, gravity along -y, T0 = 0.  The initial state is
+    rest with T drawn from U(-noise, noise) on every node, then the hot and cold wall columns set to
+    their wall temperatures."""
+    rng = np.random.default_rng(seed)
+    T = rng.uniform(-noise, noise, size=(L, L))
+    T[:, 0] = T_hot
+    T[:, -1] = T_cold
+    return {"name": f"cavity_{L}x{L}_Ra{Ra:.3g}", "nx": L, "ny": L, "T0": 0.0,
+            "edges": _edges(west=("dirichlet", 0.0, 0.0, T_hot), east=("dirichlet", 0.0, 0.0, T_cold),
+                            south=("adiabatic", 0.0, 0.0, 0.0), north=("adiabatic", 0.0, 0.0, 0.0)),
+            "physics": {"Ra": Ra, "Pr": Pr, "Ma": Ma, "H": L - 1, "dT": T_hot - T_cold},
+            "fields": {"rho": None, "ux": None, "uy": None, "T": T}}
+
+
+def rayleigh_benard(nx=2048, ny=1024, Ra=1e6, Pr=0.71, Ma=0.3, seed=3, amp=1e-3,
+                    T_hot=0.5, T_cold=-0.5, T0=0.0):
+    """Rayleigh-Benard cell, periodic in x, hot south wall and cold north wall (Dirichlet, no-slip),
+    gravity along -y.  Initial state: rest, the conduction profile T = T_hot - (T_hot - T_cold) y/H
+    on nodes y = 0..H, plus U(-amp, amp) noise on the interior rows."""
+    rng = np.random.default_rng(seed)
+    H = ny - 1
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    T = np.broadcast_to(T_hot - (T_hot - T_cold) * y / H, (ny, nx)).copy()
+    T[1:-1, :] += rng.uniform(-amp, amp, size=(ny - 2, nx))
+    return {"name": f"rayleigh_benard_{nx}x{ny}_Ra{Ra:.3g}", "nx": nx, "ny": ny, "T0": T0,
+            "edges": _edges(south=("dirichlet", 0.0, 0.0, T_hot), north=("dirichlet", 0.0, 0.0, T_cold)),
+            "physics": {"Ra": Ra, "Pr": Pr, "Ma": Ma, "H": H, "dT": T_hot - T_cold},
+            "fields": {"rho": None, "ux": None, "uy": None, "T": T}}
+
+
+def rb_cell(Ra, L=60, H=30, Pr=0.71, Ma=0.3, T_hot=1.05, T_cold=0.95, amp=1e-3):
+    """The Rayleigh-Benard cell of the Nusselt table: L x H = 60 x 30 (nodes L x (H + 1), periodic
+    in x), T_hot = 1.05, T_cold = 0.95, T0 = 1.  Instead of a density bump the conduction profile is
+    perturbed by amp * cos(2 pi x / L) sin(pi y / H), which seeds the same one-wavelength pair of
+    rolls."""
+    ny = H + 1
+    x = np.arange(L, dtype=np.float64)[None, :]
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    T = T_hot - (T_hot - T_cold) * y / H + amp * np.cos(2 * math.pi * x / L) * np.sin(math.pi * y / H)
+    return {"name": f"rb_cell_{L}x{H}_Ra{Ra:g}", "nx": L, "ny": ny, "T0": 0.5 * (T_hot + T_cold),
+            "edges": _edges(south=("dirichlet", 0.0, 0.0, T_hot), north=("dirichlet", 0.0, 0.0, T_cold)),
+            "physics": {"Ra": Ra, "Pr": Pr, "Ma": Ma, "H": H, "dT": T_hot - T_cold},
+            "fields": {"rho": None, "ux": None, "uy": None, "T": T}}
+
+
+def poiseuille(nx=4, ny=33, tau_nu=0.8, Fx=1e-6, T0=0.0):
+    """Body-force-driven channel: periodic in x, no-slip walls on nodes y = 0 and y = ny - 1,
+    constant force density F_v = (Fx, 0), uniform T = T0 (no buoyancy)."""
+    return {"name": f"poiseuille_{nx}x{ny}", "nx": nx, "ny": ny, "T0": T0,
+            "edges": _edges(south=("dirichlet", 0.0, 0.0, T0), north=("dirichlet", 0.0, 0.0, T0)),
+            "taus": {"tau_nu": tau_nu, "tau_alpha": 0.8, "g_beta": 0.0},
+            "body_force": (Fx, 0.0),
+            "fields": {"rho": None, "ux": None, "uy": None, "T": None}}
+
+
+def random_periodic(nx, ny, seed, amp_u=0.05, amp_T=0.1, T0=0.0, g_beta=1e-3, tau_nu=0.7, tau_alpha=0.9):
+    """Periodic lattice with seeded random fields: rho = 1 + U(-0.01, 0.01), u = U(-amp_u, amp_u),
+    T = T0 + U(-amp_T, amp_T), and buoyancy on, so every term of the step is exercised."""
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + rng.uniform(-0.01, 0.01, size=(ny, nx))
+    ux = rng.uniform(-amp_u, amp_u, size=(ny, nx))
+    uy = rng.uniform(-amp_u, amp_u, size=(ny, nx))
+    T = T0 + rng.uniform(-amp_T, amp_T, size=(ny, nx))
+    return {"name": f"random_periodic_{nx}x{ny}_s{seed}", "nx": nx, "ny": ny, "T0": T0,
+            "edges": _edges(),
+            "taus": {"tau_nu": tau_nu, "tau_alpha": tau_alpha, "g_beta": g_beta},
+            "fields": {"rho": rho, "ux": ux, "uy": uy, "T": T}}
+
+
+def random_walled(nx, ny, seed, kinds=("dirichlet", "dirichlet", "adiabatic", "adiabatic"),
+                  amp_u=0.02, amp_T=0.1, g_beta=1e-3, tau_nu=0.7, tau_alpha=0.9, wall_u=0.0):
+    """Walled lattice with seeded random interior fields and, if wall_u != 0, moving and permeable
+    walls, so every branch of the wall step is exercised.  kinds = (west, east, south, north); a
+    periodic pair is allowed."""
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + rng.uniform(-0.01, 0.01, size=(ny, nx))
+    ux = rng.uniform(-amp_u, amp_u, size=(ny, nx))
+    uy = rng.uniform(-amp_u, amp_u, size=(ny, nx))
+    T = rng.uniform(-amp_T, amp_T, size=(ny, nx))
+    wu = rng.uniform(-wall_u, wall_u, size=(4, 2)) if wall_u else np.zeros((4, 2))
+    tw = (0.5, -0.5, 0.25, -0.25)
+    names = ("west", "east", "south", "north")
+    edges = {}
+    for i, (nm, kd) in enumerate(zip(names, kinds)):
+        edges[nm] = (kd, float(wu[i, 0]), float(wu[i, 1]), tw[i]) if kd != "periodic" else PERIODIC
+    return {"name": f"random_walled_{nx}x{ny}_s{seed}", "nx": nx, "ny": ny, "T0": 0.0,
+            "edges": edges,
+            "taus": {"tau_nu": tau_nu, "tau_alpha": tau_alpha, "g_beta": g_beta},
+            "fields": {"rho": rho, "ux": ux, "uy": uy, "T": T}}
+
+
+def batch_cavity_specs(n=512, seed=7, sizes=tuple(range(64, 513, 32)), Ra_range=(3.0, 6.0), Pr=0.71, Ma=0.1):
+    """The batched-cavity workload: side lengths drawn uniformly from {64, 96, ..., 512}, then
+    Ra = 10**U(3, 6), in that order, from default_rng(seed); cavity i has noise seed 1000 + i.
+    Returns (L, Ra, noise_seed) triples."""
+    rng = np.random.default_rng(seed)
+    Ls = rng.choice(np.array(sizes), n)
+    Ras = 10.0 ** rng.uniform(Ra_range[0], Ra_range[1], n)
+    return [(int(L), float(Ra), 1000 + i) for i, (L, Ra) in enumerate(zip(Ls, Ras))]
+
+
+def serving_requests(n=200, lam=1.0, seed=5, L_range=(32, 1024), Ra_range=(1e3, 1e6)):
+    """A Poisson stream of cavity requests: exponential inter-arrival times of mean 1/lam (seconds),
+    L = round(exp(U(ln L_min, ln L_max))), Ra log-uniform.  Returns dicts with arrival, L, Ra,
+    noise_seed."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / lam, n)
+    arrivals = np.cumsum(gaps)
+    Ls = np.rint(np.exp(rng.uniform(math.log(L_range[0]), math.log(L_range[1]), n))).astype(int)
+    Ras = np.exp(rng.uniform(math.log(Ra_range[0]), math.log(Ra_range[1]), n))
+    return [{"id": i, "arrival": float(a), "L": int(L), "Ra": float(Ra), "noise_seed": 5000 + i}
+            for i, (a, L, Ra) in enumerate(zip(arrivals, Ls, Ras))]

@@ -1,0 +1,307 @@
+"""Pins of the oracle's single-node algebra against the definitions and printed values of the paper.
+
+Each check reaches the expected value by a route other than the oracle's: the moment definitions
+of Eqs. 5 and 14 summed directly over the velocity set of Eq. 4, linear solves of the central-moment
+system built from those definitions, the matrices printed in Appendix A, and textbook special
+cases (D2Q9 weights, BGK, Zou-He without force).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+# Eq. 4, typed from the paper's two column vectors.
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
+# Exponents (m, n) of the simplified moment sets, Eq. 6 (D2Q9) and Eq. 15 (D2Q5).
+MN9 = [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (1, 1), (2, 1), (1, 2), (2, 2)]
+MN5 = [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2)]
+
+
+def central_matrix(ux, uy, mn, q):
+    """Row (m, n), column i: (e_ix - u_x)^m (e_iy - u_y)^n -- the definition of Eq. 5b / 14b."""
+    return np.array([[(EX[i] - ux) ** m * (EY[i] - uy) ** n for i in range(q)] for (m, n) in mn])
+
+
+def rand_f(rng, q=9):
+    return 0.05 + rng.random(q) * 0.2
+
+
+@pytest.fixture(scope="module")
+def lat():
+    L = O.OracleLattice(4, 4)
+    yield L
+    L.close()
+
+
+def test_raw_moments_match_definition():
+    """Gamma = M f (Eq. 7a) equals k_mn = sum_i f_i e_ix^m e_iy^n (Eq. 5a) over Eq. 6's set."""
+    rng = np.random.default_rng(11)
+    M = O.matrix_M()
+    for _ in range(20):
+        f = rand_f(rng)
+        direct = central_matrix(0.0, 0.0, MN9, 9) @ f
+        assert np.allclose(M @ f, direct, rtol=0, atol=1e-15)
+
+
+def test_central_moments_match_definition():
+    """N(u) M f (Eq. 7b) equals the central moments of Eq. 5b for random f and u.  This pins every
+    entry of the shift matrix, including the k~02 row whose printed sign is corrected."""
+    rng = np.random.default_rng(12)
+    M = O.matrix_M()
+    for _ in range(50):
+        f = rand_f(rng)
+        ux, uy = rng.uniform(-0.4, 0.4, 2)
+        direct = central_matrix(ux, uy, MN9, 9) @ f
+        assert np.allclose(O.matrix_N(ux, uy) @ (M @ f), direct, rtol=0, atol=2e-15)
+
+
+def test_printed_k02_sign_would_fail():
+    """The shift matrix as printed (+2 u_y in row k~02) does not reproduce Eq. 5b; the corrected
+    one does.  Guards the reading recorded for Eq. 7b."""
+    ux, uy = 0.1, 0.2
+    f = rand_f(np.random.default_rng(13))
+    N = O.matrix_N(ux, uy)
+    assert N[4, 2] == pytest.approx(-2 * uy)
+    Np = N.copy()
+    Np[4, 2] = +2 * uy
+    direct = central_matrix(ux, uy, MN9, 9) @ f
+    assert abs((Np @ O.matrix_M() @ f)[4] - direct[4]) > 1e-3
+
+
+def test_shift_inverse_is_negative_shift():
+    """N(u)^-1 = N(-u): shifting by u and back is the identity (translation of a polynomial basis)."""
+    rng = np.random.default_rng(14)
+    for _ in range(20):
+        ux, uy = rng.uniform(-0.5, 0.5, 2)
+        assert np.allclose(O.matrix_Ninv(ux, uy), O.matrix_N(-ux, -uy), rtol=0, atol=1e-15)
+        assert np.allclose(O.matrix_NTinv(ux, uy), O.matrix_NT(-ux, -uy), rtol=0, atol=1e-15)
+
+
+def test_Minv_exact(lat):
+    assert np.array_equal(lat.matrix_Minv() @ O.matrix_M(), np.eye(9))
+    assert np.array_equal(O.matrix_M() @ lat.matrix_Minv(), np.eye(9))
+
+
+def test_d2q5_moments_match_definition():
+    rng = np.random.default_rng(15)
+    MT = O.matrix_MT()
+    for _ in range(30):
+        g = rand_f(rng, 5)
+        ux, uy = rng.uniform(-0.4, 0.4, 2)
+        assert np.allclose(MT @ g, central_matrix(0, 0, MN5, 5) @ g, rtol=0, atol=1e-15)
+        assert np.allclose(O.matrix_NT(ux, uy) @ MT @ g, central_matrix(ux, uy, MN5, 5) @ g,
+                           rtol=0, atol=1e-15)
+
+
+def test_appendix_a_printed_matrices(lat):
+    """M_T^-1, N_T^-1, E_x and E_y equal the matrices printed in Appendix A."""
+    gold = json.load(open(os.path.join(GOLD, "appendix_a_matrices.json")))
+    assert np.array_equal(lat.matrix_MTinv(), np.array(gold["M_T_inv"], dtype=float))
+    rng = np.random.default_rng(16)
+    for _ in range(10):
+        ux, uy = rng.uniform(-0.5, 0.5, 2)
+        printed = np.array([[c * ux ** a * uy ** b for (c, a, b) in row] for row in gold["N_T_inv"]])
+        assert np.allclose(O.matrix_NTinv(ux, uy), printed, rtol=0, atol=1e-15)
+    MT, MTi = O.matrix_MT(), lat.matrix_MTinv()
+    Ex = MT @ np.diag(EX[:5]) @ MTi
+    Ey = MT @ np.diag(EY[:5]) @ MTi
+    assert np.array_equal(Ex, np.array(gold["E_x"], dtype=float))
+    assert np.array_equal(Ey, np.array(gold["E_y"], dtype=float))
+
+
+def test_equilibrium_rest_weights(lat):
+    """At u = 0 the generalised equilibrium is the textbook D2Q9 one, rho (4/9, 1/9 x4, 1/36 x4),
+    and the D2Q5 one with c_T^2 = 1/4 is T (1/2, 1/8 x4)."""
+    w9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    assert np.allclose(lat.feq(1.3, 0.0, 0.0), 1.3 * w9, rtol=0, atol=1e-16)
+    w5 = np.array([0.5] + [0.125] * 4)
+    assert np.allclose(lat.geq(0.7, 0.0, 0.0), 0.7 * w5, rtol=0, atol=1e-16)
+
+
+def test_equilibrium_central_moments(lat):
+    """The central moments of f^eq (summed directly, Eq. 5b) are Eq. 9, and those of g^eq are
+    Eq. 20 with c_{T,s}^2 = 1/4."""
+    rng = np.random.default_rng(17)
+    for _ in range(30):
+        rho = rng.uniform(0.8, 1.2)
+        T = rng.uniform(-1, 2)
+        ux, uy = rng.uniform(-0.3, 0.3, 2)
+        k = central_matrix(ux, uy, MN9, 9) @ lat.feq(rho, ux, uy)
+        assert np.allclose(k, [rho, 0, 0, rho / 3, rho / 3, 0, 0, 0, rho / 9], rtol=0, atol=1e-15)
+        kt = central_matrix(ux, uy, MN5, 5) @ lat.geq(T, ux, uy)
+        assert np.allclose(kt, [T, 0, 0, T / 4, T / 4], rtol=0, atol=1e-15)
+
+
+def test_equilibrium_product_form(lat):
+    """f^eq = rho psi(e_x, u_x) psi(e_y, u_y), psi(0,u) = 2/3 - u^2, psi(+-1,u) = (1/3 +- u + u^2)/2
+    (the tensor-product structure of the continuous Maxwellian's central moments)."""
+    def psi(e, u):
+        return 2 / 3 - u * u if e == 0 else (1 / 3 + e * u + u * u) / 2
+
+    rng = np.random.default_rng(18)
+    for _ in range(20):
+        rho = rng.uniform(0.8, 1.2)
+        ux, uy = rng.uniform(-0.3, 0.3, 2)
+        prod = np.array([rho * psi(EX[i], ux) * psi(EY[i], uy) for i in range(9)])
+        assert np.allclose(lat.feq(rho, ux, uy), prod, rtol=0, atol=1e-15)
+
+
+def reference_collide9(f, Fx, Fy, rates):
+    """Eq. 8 through the definitions only: K = central-moment matrix of Eq. 5b at the Eq. 13
+    velocity; Gamma~* = (I - S) K f + S Gamma~eq + (I - S/2) C; f* = K^-1 Gamma~* by a linear solve."""
+    s_nu, s_b, s3, s4 = rates
+    rho = f.sum()
+    ux = ((f * EX).sum() + Fx / 2) / rho
+    uy = ((f * EY).sum() + Fy / 2) / rho
+    K = central_matrix(ux, uy, MN9, 9)
+    S = np.zeros((9, 9))
+    S[3, 3] = S[4, 4] = (s_b + s_nu) / 2
+    S[3, 4] = S[4, 3] = (s_b - s_nu) / 2
+    S[5, 5], S[6, 6], S[7, 7], S[8, 8] = s_nu, s3, s3, s4
+    geq = np.array([rho, 0, 0, rho / 3, rho / 3, 0, 0, 0, rho / 9])
+    C = np.array([0, Fx, Fy, 0, 0, 0, Fy / 3, Fx / 3, 0])
+    I = np.eye(9)
+    post = (I - S) @ (K @ f) + S @ geq + (I - S / 2) @ C
+    return np.linalg.solve(K, post)
+
+
+def test_collision_against_definition_route():
+    """The oracle's collision (printed M, N; forward substitution; precomputed M^-1) equals Eq. 8
+    evaluated through the moment definitions and a generic linear solve, for random rates."""
+    rng = np.random.default_rng(19)
+    L = O.OracleLattice(3, 3)
+    for _ in range(30):
+        tau_nu = rng.uniform(0.51, 2.0)
+        s_b, s3, s4 = rng.uniform(0.3, 1.9, 3)
+        L.set_params(tau_nu, 0.8, 0.0)
+        L.set_relaxation(s_b, s3, s4, 1.0)
+        f = rand_f(rng)
+        Fx, Fy = rng.uniform(-1e-2, 1e-2, 2)
+        ref = reference_collide9(f, Fx, Fy, (1 / tau_nu, s_b, s3, s4))
+        assert np.allclose(L.collide9(f, Fx, Fy), ref, rtol=0, atol=5e-15)
+    L.close()
+
+
+def test_d2q5_collision_against_definition_route():
+    rng = np.random.default_rng(20)
+    L = O.OracleLattice(3, 3)
+    for _ in range(30):
+        tau_a = rng.uniform(0.51, 2.0)
+        lam2 = rng.uniform(0.3, 1.9)
+        L.set_params(0.8, tau_a, 0.0)
+        L.set_relaxation(1.0, 1.0, 1.0, lam2)
+        g = rand_f(rng, 5)
+        ux, uy = rng.uniform(-0.3, 0.3, 2)
+        K = central_matrix(ux, uy, MN5, 5)
+        T = g.sum()
+        S = np.diag([1.0, 1 / tau_a, 1 / tau_a, lam2, lam2])
+        post = (np.eye(5) - S) @ (K @ g) + S @ np.array([T, 0, 0, T / 4, T / 4])
+        assert np.allclose(L.collide5(g, ux, uy), np.linalg.solve(K, post), rtol=0, atol=5e-15)
+    L.close()
+
+
+def test_equal_rates_reduce_to_bgk():
+    """With s_b = s_nu = s3 = s4 = omega the CLB collision is BGK towards the generalised
+    equilibrium plus (1 - omega/2) times the population-space forcing term whose central moments
+    are C (Eq. 11).  With lambda1 = lambda2 the D2Q5 collision is BGK towards g^eq."""
+    rng = np.random.default_rng(21)
+    L = O.OracleLattice(3, 3)
+
+    def psi(e, u):
+        return 2 / 3 - u * u if e == 0 else (1 / 3 + e * u + u * u) / 2
+
+    for _ in range(20):
+        w = rng.uniform(0.6, 1.9)
+        L.set_params(1 / w, 1 / w, 0.0)
+        L.set_relaxation(w, w, w, w)
+        f = rand_f(rng)
+        Fx, Fy = rng.uniform(-1e-2, 1e-2, 2)
+        rho = f.sum()
+        ux = ((f * EX).sum() + Fx / 2) / rho
+        uy = ((f * EY).sum() + Fy / 2) / rho
+        feq = np.array([rho * psi(EX[i], ux) * psi(EY[i], uy) for i in range(9)])
+        K = central_matrix(ux, uy, MN9, 9)
+        R = np.linalg.solve(K, np.array([0, Fx, Fy, 0, 0, 0, Fy / 3, Fx / 3, 0]))
+        bgk = f - w * (f - feq) + (1 - w / 2) * R
+        assert np.allclose(L.collide9(f, Fx, Fy), bgk, rtol=0, atol=5e-15)
+        g = rand_f(rng, 5)
+        T = g.sum()
+        cT2 = 0.25
+        geq = np.array([T * (1 - 2 * cT2 - ux * ux - uy * uy), T * (cT2 + ux + ux * ux) / 2,
+                        T * (cT2 + uy + uy * uy) / 2, T * (cT2 - ux + ux * ux) / 2,
+                        T * (cT2 - uy + uy * uy) / 2])
+        assert np.allclose(L.collide5(g, ux, uy), g - w * (g - geq), rtol=0, atol=5e-15)
+    L.close()
+
+
+def test_equilibrium_is_fixed_point():
+    """Without force the collision leaves f^eq and g^eq unchanged, for any rates."""
+    rng = np.random.default_rng(22)
+    L = O.OracleLattice(3, 3)
+    L.set_params(0.63, 0.77, 0.0)
+    L.set_relaxation(1.3, 0.7, 1.6, 0.9)
+    for _ in range(20):
+        rho = rng.uniform(0.9, 1.1)
+        ux, uy = rng.uniform(-0.2, 0.2, 2)
+        fe = L.feq(rho, ux, uy)
+        assert np.allclose(L.collide9(fe), fe, rtol=0, atol=1e-15)
+        ge = L.geq(0.3, ux, uy)
+        assert np.allclose(L.collide5(ge, ux, uy), ge, rtol=0, atol=1e-15)
+    L.close()
+
+
+def test_forcing_moments_after_collision():
+    """Pre-collision sum f e = rho u - F/2 (Eq. 13); after collision sum f* e = rho u + F/2, i.e.
+    the first central moments go from -F/2 to +F/2, and mass is unchanged."""
+    rng = np.random.default_rng(23)
+    L = O.OracleLattice(3, 3)
+    L.set_params(0.7, 0.8, 0.0)
+    L.set_relaxation(1.2, 0.9, 1.1, 1.0)
+    for _ in range(20):
+        f = rand_f(rng)
+        Fx, Fy = rng.uniform(-1e-2, 1e-2, 2)
+        fs = L.collide9(f, Fx, Fy)
+        rho = f.sum()
+        jx, jy = (f * EX).sum(), (f * EY).sum()
+        assert fs.sum() == pytest.approx(rho, abs=1e-15)
+        assert (fs * EX).sum() == pytest.approx(jx + Fx, abs=1e-15)
+        assert (fs * EY).sum() == pytest.approx(jy + Fy, abs=1e-15)
+
+
+@pytest.mark.parametrize("normal", [(0, 1), (-1, 0), (0, -1), (1, 0)])
+def test_zou_he_constraints(normal):
+    """After the force-corrected Zou-He closure: sum f e = rho u_w - F/2 with rho = sum f, and the
+    normal population's non-equilibrium part is bounced back: f(n) - f(-n) = rho u_n (2/3 - u_t^2)."""
+    rng = np.random.default_rng(24)
+    nx_, ny_ = normal
+    for _ in range(20):
+        f = rand_f(rng)
+        uw = rng.uniform(-0.05, 0.05, 2)
+        F = rng.uniform(-1e-3, 1e-3, 2)
+        out = O.zou_he(f, normal, tuple(uw), tuple(F))
+        e_dot_n = EX * nx_ + EY * ny_
+        assert np.array_equal(out[e_dot_n <= 0], f[e_dot_n <= 0])  # known ones untouched
+        rho = out.sum()
+        assert (out * EX).sum() == pytest.approx(rho * uw[0] - F[0] / 2, abs=1e-15)
+        assert (out * EY).sum() == pytest.approx(rho * uw[1] - F[1] / 2, abs=1e-15)
+        i_n = [i for i in range(9) if EX[i] == nx_ and EY[i] == ny_][0]
+        i_m = [i for i in range(9) if EX[i] == -nx_ and EY[i] == -ny_][0]
+        un = uw[0] * nx_ + uw[1] * ny_
+        ut = uw[0] * ny_ - uw[1] * nx_
+        assert out[i_n] - out[i_m] == pytest.approx(rho * un * (2 / 3 - ut * ut), abs=1e-15)
+
+
+def test_zou_he_textbook_case():
+    """With u_w = 0 and F = 0 the closure on a south wall is the textbook one: f2 = f4,
+    f5 = f7 - (f1 - f3)/2, f6 = f8 + (f1 - f3)/2."""
+    f = rand_f(np.random.default_rng(25))
+    out = O.zou_he(f, (0, 1))
+    assert out[2] == pytest.approx(f[4], abs=1e-16)
+    assert out[5] == pytest.approx(f[7] - (f[1] - f[3]) / 2, abs=1e-16)
+    assert out[6] == pytest.approx(f[8] + (f[1] - f[3]) / 2, abs=1e-16)
