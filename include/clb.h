@@ -1,0 +1,176 @@
+/*
+ * clb.h -- C ABI of libclb, the MI355X (gfx950) implementation of the central-moment lattice
+ * Boltzmann (CLB) method for incompressible thermal flow of Fei, Luo, Lin and Li
+ * (arXiv 1710.10569).
+ *
+ * One time step advances two populations on a 2D lattice in a single fused pass:
+ *   - D2Q9 flow populations f_i (Sec. 2.1): raw moments (Eqs. 6, 7a), central moments through the
+ *     shift matrix N(u) (Eq. 7b), relaxation with the block matrix S, equilibrium central moments
+ *     (Eq. 9) and consistent forcing C (Eq. 11) in Eq. 8, back-transform, streaming (Eq. 12);
+ *   - D2Q5 temperature populations g_i (Sec. 2.2): Eqs. 15-22, T from Eq. 23;
+ *   - coupling: F = -g beta (T - T0) + F_v with gravity along -y (Eq. 3), u from Eq. 13;
+ *   - walls on nodes: non-equilibrium bounce-back (Zou-He) for f and non-equilibrium
+ *     extrapolation for g (Sec. 3, boundary conditions).
+ *
+ * Conventions for every call:
+ *   - Host arrays are borrowed for the duration of the call, FP64, row-major with x fastest:
+ *     element (x, y) of an nx-by-ny field is at index y*nx + x.
+ *   - Return value: CLB_OK (0) or a negative error code; a message for the last error of the
+ *     calling thread is available from clb_last_error().  No call aborts the process.
+ *   - A handle owns its device memory (unless created with clb_create_external) and is used by
+ *     one host thread at a time.
+ *   - Work is enqueued on the handle's HIP stream.  clb_step does not block; calls that return
+ *     data to the host (clb_moments, clb_get_populations, clb_diagnostics) synchronise the stream.
+ *   - Edge order everywhere: west (x = 0), east (x = nx-1), south (y = 0), north (y = ny-1).
+ */
+#ifndef CLB_H
+#define CLB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+enum {
+    CLB_OK = 0,
+    CLB_EINVAL = -1,     /* invalid argument (NULL pointer, size, relaxation time, NaN ...) */
+    CLB_ENOMEM = -2,     /* device or host allocation failed, or a memory budget is exceeded */
+    CLB_EDEVICE = -3,    /* a HIP runtime call failed (no device, launch failure ...) */
+    CLB_ESTATE = -4,     /* call not valid in the handle's current state */
+    CLB_EDIVERGED = -5   /* a diagnostic found a non-finite density, velocity or temperature */
+};
+
+/* Storage and arithmetic precision of the populations. */
+enum {
+    CLB_FP64 = 0,        /* f_i, g_i stored and collided in FP64 */
+    CLB_FP32_DEV = 1,    /* stored and collided in FP32 as deviations f_i - w_i and g_i - w^T_i T0
+                            from the rest equilibrium (w: D2Q9 weights; w^T = (1/2, 1/8 x 4)) */
+    CLB_FP64_DEV = 2     /* the deviation algebra of CLB_FP32_DEV carried out in FP64 */
+};
+
+/* Kind of an edge of the domain.  West/east must both be periodic or both walls; same for
+ * south/north. */
+enum {
+    CLB_PERIODIC = 0,
+    CLB_WALL_DIRICHLET = 1,   /* wall with velocity (ux, uy) and temperature T */
+    CLB_WALL_ADIABATIC = 2    /* wall with velocity (ux, uy) and zero normal temperature gradient */
+};
+
+typedef struct {
+    int kind;          /* CLB_PERIODIC, CLB_WALL_DIRICHLET or CLB_WALL_ADIABATIC */
+    double ux, uy;     /* wall velocity (a normal component makes the wall permeable) */
+    double T;          /* wall temperature (CLB_WALL_DIRICHLET only) */
+} clb_edge;
+
+typedef struct {
+    int nx, ny;        /* nodes; >= 3 each, >= 4 along the normal of an adiabatic wall pair */
+    int precision;     /* CLB_FP64, CLB_FP32_DEV or CLB_FP64_DEV */
+    clb_edge west, east, south, north;
+    double T0;         /* reference temperature of the Boussinesq force (Eq. 3) */
+    int prescribed_u;  /* reserved, must be 0 */
+} clb_desc;
+
+typedef struct clb_lattice clb_lattice;
+
+/* FP64 diagnostics of the current time step (Sec. 3 quantities).  All sums are over nodes. */
+typedef struct {
+    long long step;        /* time steps taken since clb_init */
+    double mass;           /* sum rho (Eq. 13) */
+    double heat;           /* sum T (Eq. 23) */
+    double mom_x, mom_y;   /* sum rho u (Eq. 13) */
+    double sum_w;          /* sum of the averaging weights w(x, y) = wx(x) wy(y), with w = 1/2 on
+                              wall nodes of a non-periodic direction and 1 elsewhere */
+    double sum_w_ux_T;     /* sum w u_x T  -> <u_x T> = sum_w_ux_T / sum_w (Eq. 29) */
+    double sum_w_uy_T;     /* sum w u_y T */
+    double wall_flux[4];   /* per edge W, E, S, N: sum over the edge's nodes with trapezoid weights
+                              of (3 T_b - 4 T_1 + T_2)/2, the second-order inward-normal gradient of
+                              T with the sign of heat entering the domain; 0 for periodic edges */
+    double u_max;          /* max |u| */
+    double du_max;         /* max over nodes of max(|ux - ux_snap|, |uy - uy_snap|); -1 if no snapshot */
+    double dT_max;         /* max |T - T_snap|; -1 if no snapshot */
+    int nonfinite;         /* 1 if any rho, u or T is NaN or infinite */
+} clb_diag;
+
+/* ---------------------------------------------------------------------------------------------
+ * Core calls.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Create a lattice on the current HIP device.  hip_stream: a hipStream_t to enqueue work on, or
+ * NULL for a stream owned by the handle.  Allocates two population buffers (ping-pong), each
+ * 14 planes of nx*ny values, and sets the defaults: rho = 1, u = 0, T = T0 everywhere, all
+ * relaxation rates 1 (tau = 1), g*beta = 0, no body force.
+ * Errors: CLB_EINVAL (NULL desc/out, bad sizes or kinds, prescribed_u != 0), CLB_ENOMEM,
+ * CLB_EDEVICE. */
+int clb_create(const clb_desc* desc, void* hip_stream, clb_lattice** out);
+
+/* Relaxation times and buoyancy.  tau_nu = 1/s_nu, nu = (tau_nu - 1/2)/3 (Sec. 2.1);
+ * tau_alpha = 1/lambda1, alpha = (tau_alpha - 1/2)/4 with c_{T,s}^2 = 1/4 (Sec. 2.2, Sec. 3);
+ * g_beta: the Boussinesq coefficient of Eq. 3, F_y = g_beta (T - T0).  Ma is informational
+ * (the flow's Mach number u_c/c_s of Sec. 3.3) and is kept for reporting only.
+ * Errors: CLB_EINVAL if a tau <= 1/2 or any value is not finite. */
+int clb_set_params(clb_lattice* h, double tau_nu, double tau_alpha, double g_beta, double Ma);
+
+/* Advance n >= 0 time steps (wall step, macroscopic quantities, both collisions, streaming).
+ * Asynchronous on the handle's stream. */
+int clb_step(clb_lattice* h, long long n);
+
+/* rho, u and T of the current time step (the wall step and Eqs. 3, 13, 23 applied to the
+ * post-streaming populations).  rho, T: nx*ny each; u: 2*nx*ny, the u_x plane then the u_y plane.
+ * Any pointer may be NULL.  Synchronises the stream. */
+int clb_moments(clb_lattice* h, double* rho, double* u, double* T);
+
+/* Release the handle and its device memory.  NULL-safe. */
+void clb_destroy(clb_lattice* h);
+
+/* ---------------------------------------------------------------------------------------------
+ * Extensions.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Initial state from FP64 fields (NULL: rho = 1, u = 0, T = T0).  u as in clb_moments.  The
+ * populations are set to the equilibria whose central moments are Eq. 9 and Eq. 20, at the
+ * velocity u - F/(2 rho) for f (F from T by Eq. 3) and u for g, so that clb_moments returns the
+ * given fields at interior nodes.  Resets the step counter and the residual snapshot. */
+int clb_init(clb_lattice* h, const double* rho, const double* u, const double* T);
+
+/* The tunable rates (Sec. 2.1 matrix S, Sec. 2.2 matrix S_T): bulk rate s_b (bulk viscosity
+ * xi = (1/s_b - 1/2)/3), third-order rate s3, fourth-order rate s4, D2Q5 second-order rate
+ * lambda2.  Defaults 1.  Errors: CLB_EINVAL unless each is in (0, 2). */
+int clb_set_relaxation(clb_lattice* h, double s_b, double s3, double s4, double lambda2);
+
+/* Constant external force density F_v of Eq. 3. */
+int clb_set_body_force(clb_lattice* h, double Fvx, double Fvy);
+
+/* FP64 diagnostics of the current step; if snapshot != 0, the current u and T become the new
+ * residual snapshot after the residual is measured.  Returns CLB_EDIVERGED (with *out filled)
+ * if any value is non-finite.  Synchronises the stream. */
+int clb_diagnostics(clb_lattice* h, int snapshot, clb_diag* out);
+
+/* The post-streaming populations of the current step (before the wall step), as full FP64
+ * values: f as 9 planes and g as 5 planes of nx*ny, direction order of Eq. 4.  A population
+ * whose streaming source lies outside the domain is unknown and returned as NaN.  Either pointer
+ * may be NULL.  Synchronises the stream. */
+int clb_get_populations(clb_lattice* h, double* f, double* g);
+
+/* Physical parameters -> relaxation times (Sec. 3.3): nu = Ma c_s H sqrt(Pr/Ra), alpha = nu/Pr,
+ * g*beta = Ra nu alpha / (dT H^3), tau_nu = 3 nu + 1/2, tau_alpha = 4 alpha + 1/2.
+ * Host-only.  Errors: CLB_EINVAL for non-positive or non-finite inputs or NULL outputs. */
+int clb_params_from_physics(double Ra, double Pr, double Ma, double H, double dT,
+                            double* tau_nu, double* tau_alpha, double* g_beta);
+
+/* Time n steps on the handle's stream with HIP events (inputs already on the device); writes the
+ * elapsed milliseconds of the n launches.  Synchronises the stream. */
+int clb_time_steps(clb_lattice* h, long long n, double* ms);
+
+/* Wait for the handle's stream. */
+int clb_synchronize(clb_lattice* h);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* clb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLB_H */

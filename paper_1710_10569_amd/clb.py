@@ -1,0 +1,237 @@
+"""Thin ctypes binding to libclb (include/clb.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of ``libclb.so``; nothing here computes.  The
+library must have been built (``python -m paper_1710_10569_amd.build``); importing this module
+without it raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libclb.so")
+
+if not os.path.exists(LIBPATH):
+    raise ImportError(f"libclb.so is not built ({LIBPATH}); run `python -m paper_1710_10569_amd.build`")
+
+# PyTorch ships its own HIP runtime under the same soname; load it first so that libclb binds to
+# the same runtime instance and torch streams and device memory can be handed to the library.
+try:
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover - torch is optional for the library itself
+    torch = None
+
+_lib = ctypes.CDLL(LIBPATH)
+
+# enums of clb.h
+CLB_OK, CLB_EINVAL, CLB_ENOMEM, CLB_EDEVICE, CLB_ESTATE, CLB_EDIVERGED = 0, -1, -2, -3, -4, -5
+CLB_FP64, CLB_FP32_DEV, CLB_FP64_DEV = 0, 1, 2
+CLB_PERIODIC, CLB_WALL_DIRICHLET, CLB_WALL_ADIABATIC = 0, 1, 2
+PRECISIONS = {"fp64": CLB_FP64, "fp32": CLB_FP32_DEV, "fp32_dev": CLB_FP32_DEV, "fp64_dev": CLB_FP64_DEV}
+KINDS = {"periodic": CLB_PERIODIC, "dirichlet": CLB_WALL_DIRICHLET, "adiabatic": CLB_WALL_ADIABATIC}
+
+
+class clb_edge(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("ux", ctypes.c_double), ("uy", ctypes.c_double), ("T", ctypes.c_double)]
+
+
+class clb_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("precision", ctypes.c_int),
+                ("west", clb_edge), ("east", clb_edge), ("south", clb_edge), ("north", clb_edge),
+                ("T0", ctypes.c_double), ("prescribed_u", ctypes.c_int)]
+
+
+class clb_diag(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_longlong), ("mass", ctypes.c_double), ("heat", ctypes.c_double),
+                ("mom_x", ctypes.c_double), ("mom_y", ctypes.c_double), ("sum_w", ctypes.c_double),
+                ("sum_w_ux_T", ctypes.c_double), ("sum_w_uy_T", ctypes.c_double),
+                ("wall_flux", ctypes.c_double * 4), ("u_max", ctypes.c_double),
+                ("du_max", ctypes.c_double), ("dT_max", ctypes.c_double), ("nonfinite", ctypes.c_int)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "wall_flux"}
+        d["wall_flux"] = list(self.wall_flux)
+        return d
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_H = ctypes.c_void_p
+
+
+def _sig(name, res, args):
+    fn = getattr(_lib, name)
+    fn.restype = res
+    fn.argtypes = args
+    return fn
+
+
+_sig("clb_create", ctypes.c_int, [ctypes.POINTER(clb_desc), _vp, ctypes.POINTER(_H)])
+_sig("clb_set_params", ctypes.c_int, [_H, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double])
+_sig("clb_step", ctypes.c_int, [_H, ctypes.c_longlong])
+_sig("clb_moments", ctypes.c_int, [_H, _dp, _dp, _dp])
+_sig("clb_destroy", None, [_H])
+_sig("clb_init", ctypes.c_int, [_H, _dp, _dp, _dp])
+_sig("clb_set_relaxation", ctypes.c_int, [_H] + [ctypes.c_double] * 4)
+_sig("clb_set_body_force", ctypes.c_int, [_H, ctypes.c_double, ctypes.c_double])
+_sig("clb_diagnostics", ctypes.c_int, [_H, ctypes.c_int, ctypes.POINTER(clb_diag)])
+_sig("clb_get_populations", ctypes.c_int, [_H, _dp, _dp])
+_sig("clb_params_from_physics", ctypes.c_int, [ctypes.c_double] * 5 + [_dp, _dp, _dp])
+_sig("clb_time_steps", ctypes.c_int, [_H, ctypes.c_longlong, _dp])
+_sig("clb_synchronize", ctypes.c_int, [_H])
+_sig("clb_last_error", ctypes.c_char_p, [])
+
+
+class CLBError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"clb error {code}: {msg}")
+        self.code = code
+
+
+def last_error() -> str:
+    return (_lib.clb_last_error() or b"").decode()
+
+
+def _check(rc):
+    if rc != CLB_OK:
+        raise CLBError(rc, last_error())
+    return rc
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _f64(a, n):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def params_from_physics(Ra, Pr, Ma, H, dT):
+    """(tau_nu, tau_alpha, g_beta) from (Ra, Pr, Ma, H, dT) through clb_params_from_physics."""
+    t = [ctypes.c_double() for _ in range(3)]
+    _check(_lib.clb_params_from_physics(Ra, Pr, Ma, H, dT, *[ctypes.byref(v) for v in t]))
+    return tuple(v.value for v in t)
+
+
+def make_desc(nx, ny, precision="fp64", edges=None, T0=0.0):
+    """clb_desc from sizes, a precision name or code, and {edge: (kind, ux, uy, T)}."""
+    d = clb_desc()
+    d.nx, d.ny = int(nx), int(ny)
+    d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    edges = edges or {}
+    for name in ("west", "east", "south", "north"):
+        kind, ux, uy, T = edges.get(name, ("periodic", 0.0, 0.0, 0.0))
+        setattr(d, name, clb_edge(KINDS[kind] if isinstance(kind, str) else int(kind), ux, uy, T))
+    d.T0 = float(T0)
+    d.prescribed_u = 0
+    return d
+
+
+class Lattice:
+    """One lattice on the current HIP device (clb_create ... clb_destroy)."""
+
+    def __init__(self, nx, ny, precision="fp64", edges=None, T0=0.0, stream=None):
+        self.desc = make_desc(nx, ny, precision, edges, T0)
+        self.nx, self.ny = int(nx), int(ny)
+        h = _H()
+        _check(_lib.clb_create(ctypes.byref(self.desc), None if stream is None else _vp(int(stream)),
+                               ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.clb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_params(self, tau_nu, tau_alpha, g_beta=0.0, Ma=0.0):
+        _check(_lib.clb_set_params(self._h, tau_nu, tau_alpha, g_beta, Ma))
+
+    def set_relaxation(self, s_b=1.0, s3=1.0, s4=1.0, lambda2=1.0):
+        _check(_lib.clb_set_relaxation(self._h, s_b, s3, s4, lambda2))
+
+    def set_body_force(self, Fvx, Fvy):
+        _check(_lib.clb_set_body_force(self._h, Fvx, Fvy))
+
+    def init(self, rho=None, ux=None, uy=None, T=None):
+        n = self.nx * self.ny
+        u = None
+        if ux is not None or uy is not None:
+            u = np.zeros(2 * n)
+            if ux is not None:
+                u[:n] = np.ravel(np.broadcast_to(ux, (self.ny, self.nx)))
+            if uy is not None:
+                u[n:] = np.ravel(np.broadcast_to(uy, (self.ny, self.nx)))
+        r = None if rho is None else _f64(np.broadcast_to(rho, (self.ny, self.nx)), n)
+        t = None if T is None else _f64(np.broadcast_to(T, (self.ny, self.nx)), n)
+        _check(_lib.clb_init(self._h, _ptr(r), _ptr(u), _ptr(t)))
+
+    def step(self, n=1):
+        _check(_lib.clb_step(self._h, int(n)))
+
+    def time_steps(self, n):
+        ms = ctypes.c_double()
+        _check(_lib.clb_time_steps(self._h, int(n), ctypes.byref(ms)))
+        return ms.value
+
+    def synchronize(self):
+        _check(_lib.clb_synchronize(self._h))
+
+    def moments(self):
+        """(rho, ux, uy, T), each (ny, nx) float64."""
+        n = self.nx * self.ny
+        rho, u, T = np.empty(n), np.empty(2 * n), np.empty(n)
+        _check(_lib.clb_moments(self._h, _ptr(rho), _ptr(u), _ptr(T)))
+        s = (self.ny, self.nx)
+        return rho.reshape(s), u[:n].reshape(s), u[n:].reshape(s), T.reshape(s)
+
+    def populations(self):
+        """Post-streaming populations (f: (9, ny, nx), g: (5, ny, nx)); NaN where unknown."""
+        f = np.empty((9, self.ny, self.nx))
+        g = np.empty((5, self.ny, self.nx))
+        _check(_lib.clb_get_populations(self._h, _ptr(f), _ptr(g)))
+        return f, g
+
+    def diagnostics(self, snapshot=False, raise_on_diverged=True):
+        d = clb_diag()
+        rc = _lib.clb_diagnostics(self._h, int(bool(snapshot)), ctypes.byref(d))
+        if rc != CLB_OK and (rc != CLB_EDIVERGED or raise_on_diverged):
+            raise CLBError(rc, last_error())
+        return d.as_dict()
+
+
+def lattice_from_workload(w, precision="fp64", stream=None):
+    """A Lattice set up and initialised from a workload description (see workloads.py)."""
+    lat = Lattice(w["nx"], w["ny"], precision, w["edges"], w["T0"], stream=stream)
+    if "taus" in w:
+        t = w["taus"]
+        lat.set_params(t["tau_nu"], t["tau_alpha"], t["g_beta"], 0.0)
+    else:
+        p = w["physics"]
+        tn, ta, gb = params_from_physics(p["Ra"], p["Pr"], p["Ma"], p["H"], p["dT"])
+        lat.set_params(tn, ta, gb, p["Ma"])
+    if "body_force" in w:
+        lat.set_body_force(*w["body_force"])
+    fl = w["fields"]
+    lat.init(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    return lat

@@ -1,0 +1,656 @@
+// clb.hip -- single-lattice kernels and the C ABI of libclb (include/clb.h).
+//
+// Kernels (all one thread per node):
+//   step_kernel      the fused time step: pull, wall step, macroscopic, D2Q9 + D2Q5 collision,
+//                    store (Sec. 2.1 Eq. 8, Sec. 2.2 Eq. 19, Eq. 3, Eq. 13, Eq. 23, Sec. 3 walls).
+//   init_kernel      equilibrium populations from FP64 fields, scattered to where the next pull
+//                    reads them (Eqs. 9 and 20 through the generalised equilibria).
+//   moments_kernel   pull + wall step + macroscopic quantities -> FP64 rho, u, T.
+//   populations_kernel  pull -> FP64 post-streaming populations, NaN where unknown.
+//   diag_reduce_kernel / diag_final_kernel  FP64 sums and maxima of the moment fields, with a
+//                    fixed reduction order (64-lane wavefront shuffles, then block, then a single
+//                    block over the per-block partials), so repeated runs agree bitwise.
+#include "clb_internal.h"
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+namespace clb {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+int validate_desc(const clb_desc* d)
+{
+    if (!d) { set_error("desc is NULL"); return CLB_EINVAL; }
+    if (d->precision != CLB_FP64 && d->precision != CLB_FP32_DEV && d->precision != CLB_FP64_DEV) {
+        set_error("unknown precision %d", d->precision);
+        return CLB_EINVAL;
+    }
+    const clb_edge* e[4] = {&d->west, &d->east, &d->south, &d->north};
+    for (int i = 0; i < 4; ++i) {
+        if (e[i]->kind < CLB_PERIODIC || e[i]->kind > CLB_WALL_ADIABATIC) {
+            set_error("edge %d: unknown kind %d", i, e[i]->kind);
+            return CLB_EINVAL;
+        }
+        if (!std::isfinite(e[i]->ux) || !std::isfinite(e[i]->uy) || !std::isfinite(e[i]->T)) {
+            set_error("edge %d: non-finite wall data", i);
+            return CLB_EINVAL;
+        }
+        if (e[i]->kind != CLB_PERIODIC && (std::fabs(e[i]->ux) >= 0.5 || std::fabs(e[i]->uy) >= 0.5)) {
+            set_error("edge %d: wall speed must be below 0.5 lattice units", i);
+            return CLB_EINVAL;
+        }
+    }
+    if ((d->west.kind == CLB_PERIODIC) != (d->east.kind == CLB_PERIODIC) ||
+        (d->south.kind == CLB_PERIODIC) != (d->north.kind == CLB_PERIODIC)) {
+        set_error("west/east and south/north must each be both periodic or both walls");
+        return CLB_EINVAL;
+    }
+    const int minx = (d->west.kind == CLB_WALL_ADIABATIC || d->east.kind == CLB_WALL_ADIABATIC) ? 4 : 3;
+    const int miny = (d->south.kind == CLB_WALL_ADIABATIC || d->north.kind == CLB_WALL_ADIABATIC) ? 4 : 3;
+    if (d->nx < minx || d->ny < miny) {
+        set_error("lattice %dx%d too small (need at least %dx%d)", d->nx, d->ny, minx, miny);
+        return CLB_EINVAL;
+    }
+    if ((long long)d->nx * d->ny > (1LL << 30) || d->nx > (1 << 20) || d->ny > (1 << 20)) {
+        set_error("lattice %dx%d too large", d->nx, d->ny);
+        return CLB_EINVAL;
+    }
+    if (!std::isfinite(d->T0)) { set_error("T0 not finite"); return CLB_EINVAL; }
+    if (d->prescribed_u != 0) { set_error("prescribed_u is reserved and must be 0"); return CLB_EINVAL; }
+    return CLB_OK;
+}
+
+Geo make_geo(const clb_desc& d, int pitch, long long plane)
+{
+    Geo G;
+    G.nx = d.nx;
+    G.ny = d.ny;
+    G.pitch = pitch;
+    G.plane = plane;
+    G.perx = d.west.kind == CLB_PERIODIC;
+    G.pery = d.south.kind == CLB_PERIODIC;
+    G.kind[0] = d.west.kind;
+    G.kind[1] = d.east.kind;
+    G.kind[2] = d.south.kind;
+    G.kind[3] = d.north.kind;
+    return G;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Kernels.
+
+constexpr int TX = 64, TY = 4;   // one 64-lane wavefront per row segment, 4 rows per workgroup
+
+template <typename Real, bool DEV>
+__global__ __launch_bounds__(TX * TY) void step_kernel(const Real* __restrict__ src, Real* __restrict__ dst,
+                                                     Geo G, Par<Real> P)
+{
+    const int x = blockIdx.x * TX + threadIdx.x;
+    const int y = blockIdx.y * TY + threadIdx.y;
+    if (x >= G.nx || y >= G.ny) return;
+    Real f[9], g[5];
+    pull(src, G, x, y, f, g);
+    if (on_wall(G, x, y)) wall_step<Real, DEV>(src, G, P, x, y, f, g);
+    const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
+    collide_f<Real, DEV>(f, m, P);
+    collide_g<Real, DEV>(g, m, P);
+    const long long PL = G.plane;
+    const int o = y * G.pitch + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dst[i * PL + o] = f[i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) dst[(9 + i) * PL + o] = g[i];
+}
+
+// Lattice directions of Eq. 4 for the host-side and init/export kernels.
+__device__ constexpr int EXd[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int EYd[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr double W9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+__device__ constexpr double W5[5] = {0.5, 0.125, 0.125, 0.125, 0.125};
+
+// Source node x - e_i of direction i, or false if it lies outside the domain.
+__device__ __forceinline__ bool source_of(const Geo& G, int x, int y, int i, int& sx, int& sy)
+{
+    sx = x - EXd[i];
+    sy = y - EYd[i];
+    if (G.perx) sx = (sx + G.nx) % G.nx;
+    if (G.pery) sy = (sy + G.ny) % G.ny;
+    return sx >= 0 && sx < G.nx && sy >= 0 && sy < G.ny;
+}
+
+// Equilibria in FP64: f_i^eq = rho psi(e_ix, v_x) psi(e_iy, v_y) and
+// g_i^eq = T (c_T^2 +- u + u^2)/2 on the axes, T (1 - 2 c_T^2 - |u|^2) at rest, c_T^2 = 1/4.
+__device__ inline double psi(int e, double v) { return e == 0 ? 2.0 / 3.0 - v * v : 0.5 * (1.0 / 3.0 + e * v + v * v); }
+
+template <typename Real, bool DEV>
+__global__ void init_kernel(Real* __restrict__ buf, Geo G, const double* __restrict__ fields,
+                            double g_beta, double T0, double Fvx, double Fvy, double TR)
+{
+    const int x = blockIdx.x * TX + threadIdx.x;
+    const int y = blockIdx.y * TY + threadIdx.y;
+    if (x >= G.nx || y >= G.ny) return;
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)y * G.nx + x;
+    const double rho = fields[k], ux = fields[n + k], uy = fields[2 * n + k], T = fields[3 * n + k];
+    const double Fx = Fvx, Fy = Fvy + g_beta * (T - T0);
+    const double vx = ux - 0.5 * Fx / rho, vy = uy - 0.5 * Fy / rho;
+    for (int i = 0; i < 9; ++i) {
+        // f_i(x) is read by the next pull from the node x - e_i... so store at the source of x.
+        int sx, sy;
+        if (!source_of(G, x, y, i, sx, sy)) continue;
+        double v = rho * psi(EXd[i], vx) * psi(EYd[i], vy);
+        if (DEV) v -= W9[i];
+        buf[i * G.plane + (long long)sy * G.pitch + sx] = Real(v);
+    }
+    const double gq[5] = {T * (0.5 - ux * ux - uy * uy), 0.5 * T * (0.25 + ux + ux * ux),
+                          0.5 * T * (0.25 + uy + uy * uy), 0.5 * T * (0.25 - ux + ux * ux),
+                          0.5 * T * (0.25 - uy + uy * uy)};
+    for (int i = 0; i < 5; ++i) {
+        int sx, sy;
+        if (!source_of(G, x, y, i, sx, sy)) continue;
+        double v = gq[i];
+        if (DEV) v -= W5[i] * TR;
+        buf[(9 + i) * G.plane + (long long)sy * G.pitch + sx] = Real(v);
+    }
+}
+
+template <typename Real, bool DEV>
+__global__ __launch_bounds__(TX * TY) void moments_kernel(const Real* __restrict__ src, Geo G, Par<Real> P,
+                                                        double* __restrict__ fields)
+{
+    const int x = blockIdx.x * TX + threadIdx.x;
+    const int y = blockIdx.y * TY + threadIdx.y;
+    if (x >= G.nx || y >= G.ny) return;
+    Real f[9], g[5];
+    pull(src, G, x, y, f, g);
+    if (on_wall(G, x, y)) wall_step<Real, DEV>(src, G, P, x, y, f, g);
+    const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)y * G.nx + x;
+    fields[k] = double(m.rho);
+    fields[n + k] = double(m.ux);
+    fields[2 * n + k] = double(m.uy);
+    fields[3 * n + k] = double(P.TR) + double(m.dT);
+}
+
+template <typename Real, bool DEV>
+__global__ void populations_kernel(const Real* __restrict__ src, Geo G, double TR, double* __restrict__ fo,
+                                   double* __restrict__ go)
+{
+    const int x = blockIdx.x * TX + threadIdx.x;
+    const int y = blockIdx.y * TY + threadIdx.y;
+    if (x >= G.nx || y >= G.ny) return;
+    Real f[9], g[5];
+    pull(src, G, x, y, f, g);
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)y * G.nx + x;
+    for (int i = 0; i < 9; ++i) {
+        int sx, sy;
+        const bool known = source_of(G, x, y, i, sx, sy);
+        if (fo) fo[i * n + k] = known ? double(f[i]) + (DEV ? W9[i] : 0.0) : __builtin_nan("");
+        if (i < 5 && go) go[i * n + k] = known ? double(g[i]) + (DEV ? W5[i] * TR : 0.0) : __builtin_nan("");
+    }
+}
+
+// Block-wide reductions of DIAG_SLOTS doubles: slots [0, DIAG_SUMS) are summed, the rest maxed.
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int NT>
+__device__ inline void block_reduce(double (&v)[DIAG_SLOTS], double* out)
+{
+    __shared__ double red[NT / 64][DIAG_SLOTS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 0; s < DIAG_SLOTS; ++s) {
+        const double r = s < DIAG_SUMS ? wave_sum(v[s]) : wave_max(v[s]);
+        if (lane == 0) red[wave][s] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < DIAG_SLOTS) {
+        const int s = threadIdx.x;
+        double r = red[0][s];
+        for (int w = 1; w < NT / 64; ++w) r = s < DIAG_SUMS ? r + red[w][s] : fmax(r, red[w][s]);
+        out[s] = r;
+    }
+}
+
+constexpr int RED_NT = 256;
+
+// Per-node contributions from the FP64 moment fields (dense [4][ny][nx]).
+__global__ __launch_bounds__(RED_NT) void diag_reduce_kernel(const double* __restrict__ fields,
+                                                            const double* __restrict__ snap, int has_snap,
+                                                            Geo G, double* __restrict__ partials)
+{
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)blockIdx.x * RED_NT + threadIdx.x;
+    double v[DIAG_SLOTS];
+#pragma unroll
+    for (int s = 0; s < DIAG_SLOTS; ++s) v[s] = 0.0;
+    v[DIAG_SUMS + 1] = v[DIAG_SUMS + 2] = has_snap ? 0.0 : -1.0;
+    if (k < n) {
+        const int x = int(k % G.nx), y = int(k / G.nx);
+        const double rho = fields[k], ux = fields[n + k], uy = fields[2 * n + k], T = fields[3 * n + k];
+        const double wx = (!G.perx && (x == 0 || x == G.nx - 1)) ? 0.5 : 1.0;
+        const double wy = (!G.pery && (y == 0 || y == G.ny - 1)) ? 0.5 : 1.0;
+        const double w = wx * wy;
+        v[0] = rho;
+        v[1] = T;
+        v[2] = rho * ux;
+        v[3] = rho * uy;
+        v[4] = w;
+        v[5] = w * ux * T;
+        v[6] = w * uy * T;
+        // wall heat flux: (3 T_b - 4 T_1 + T_2)/2 along the inward normal, trapezoid weight along the wall
+        const double* Tf = fields + 3 * n;
+        if (!G.perx && x == 0) v[7] = wy * 0.5 * (3.0 * T - 4.0 * Tf[k + 1] + Tf[k + 2]);
+        if (!G.perx && x == G.nx - 1) v[8] = wy * 0.5 * (3.0 * T - 4.0 * Tf[k - 1] + Tf[k - 2]);
+        if (!G.pery && y == 0) v[9] = wx * 0.5 * (3.0 * T - 4.0 * Tf[k + G.nx] + Tf[k + 2 * G.nx]);
+        if (!G.pery && y == G.ny - 1) v[10] = wx * 0.5 * (3.0 * T - 4.0 * Tf[k - G.nx] + Tf[k - 2 * G.nx]);
+        v[DIAG_SUMS + 0] = sqrt(ux * ux + uy * uy);
+        if (has_snap) {
+            v[DIAG_SUMS + 1] = fmax(fabs(ux - snap[k]), fabs(uy - snap[n + k]));
+            v[DIAG_SUMS + 2] = fabs(T - snap[2 * n + k]);
+        }
+        v[DIAG_SUMS + 3] = (__builtin_isfinite(rho) && __builtin_isfinite(ux) && __builtin_isfinite(uy) && __builtin_isfinite(T)) ? 0.0 : 1.0;
+    }
+    block_reduce<RED_NT>(v, partials + (long long)blockIdx.x * DIAG_SLOTS);
+}
+
+__global__ __launch_bounds__(RED_NT) void diag_final_kernel(const double* __restrict__ partials, int nblocks,
+                                                           double* __restrict__ out)
+{
+    double v[DIAG_SLOTS];
+#pragma unroll
+    for (int s = 0; s < DIAG_SLOTS; ++s) v[s] = (s < DIAG_SUMS) ? 0.0 : -1.0;
+    for (int b = threadIdx.x; b < nblocks; b += RED_NT) {
+#pragma unroll
+        for (int s = 0; s < DIAG_SLOTS; ++s)
+            v[s] = s < DIAG_SUMS ? v[s] + partials[(long long)b * DIAG_SLOTS + s]
+                                 : fmax(v[s], partials[(long long)b * DIAG_SLOTS + s]);
+    }
+    block_reduce<RED_NT>(v, out);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Launch helpers.
+
+static dim3 node_grid(const Geo& G) { return dim3((G.nx + TX - 1) / TX, (G.ny + TY - 1) / TY); }
+
+static int launch_step(clb_lattice* h, long long n)
+{
+    const clb_desc& d = h->desc;
+    const Geo G = make_geo(d, h->pitch, h->plane);
+    const dim3 grid = node_grid(G), block(TX, TY);
+    for (long long s = 0; s < n; ++s) {
+        const void* src = h->buf[h->cur];
+        void* dst = h->buf[h->cur ^ 1];
+        switch (d.precision) {
+        case CLB_FP64:
+            step_kernel<double, false><<<grid, block, 0, h->stream>>>((const double*)src, (double*)dst, G,
+                                                                      make_par<double>(d, h->par));
+            break;
+        case CLB_FP64_DEV:
+            step_kernel<double, true><<<grid, block, 0, h->stream>>>((const double*)src, (double*)dst, G,
+                                                                     make_par<double>(d, h->par));
+            break;
+        default:
+            step_kernel<float, true><<<grid, block, 0, h->stream>>>((const float*)src, (float*)dst, G,
+                                                                    make_par<float>(d, h->par));
+            break;
+        }
+        CLB_HIP(hipGetLastError());
+        h->cur ^= 1;
+        h->steps += 1;
+    }
+    return CLB_OK;
+}
+
+static int launch_moments(clb_lattice* h)
+{
+    const clb_desc& d = h->desc;
+    const Geo G = make_geo(d, h->pitch, h->plane);
+    const dim3 grid = node_grid(G), block(TX, TY);
+    const void* src = h->buf[h->cur];
+    switch (d.precision) {
+    case CLB_FP64:
+        moments_kernel<double, false><<<grid, block, 0, h->stream>>>((const double*)src, G, make_par<double>(d, h->par), h->d_fields);
+        break;
+    case CLB_FP64_DEV:
+        moments_kernel<double, true><<<grid, block, 0, h->stream>>>((const double*)src, G, make_par<double>(d, h->par), h->d_fields);
+        break;
+    default:
+        moments_kernel<float, true><<<grid, block, 0, h->stream>>>((const float*)src, G, make_par<float>(d, h->par), h->d_fields);
+        break;
+    }
+    CLB_HIP(hipGetLastError());
+    return CLB_OK;
+}
+
+static int check_params(double tau_nu, double tau_alpha, double g_beta, double Ma)
+{
+    if (!std::isfinite(tau_nu) || !std::isfinite(tau_alpha) || !std::isfinite(g_beta) || !std::isfinite(Ma)) {
+        set_error("parameters must be finite");
+        return CLB_EINVAL;
+    }
+    if (tau_nu <= 0.5 || tau_alpha <= 0.5) {
+        set_error("relaxation times must exceed 1/2 (tau_nu=%g, tau_alpha=%g)", tau_nu, tau_alpha);
+        return CLB_EINVAL;
+    }
+    return CLB_OK;
+}
+
+}  // namespace clb
+
+using namespace clb;
+
+// ---------------------------------------------------------------------------------------------
+// C ABI.
+
+extern "C" const char* clb_last_error(void) { return g_err; }
+
+extern "C" int clb_params_from_physics(double Ra, double Pr, double Ma, double H, double dT, double* tau_nu,
+                                       double* tau_alpha, double* g_beta)
+{
+    clear_error();
+    if (!tau_nu || !tau_alpha || !g_beta) { set_error("NULL output"); return CLB_EINVAL; }
+    const double in[5] = {Ra, Pr, Ma, H, dT};
+    for (double v : in)
+        if (!std::isfinite(v) || v <= 0.0) { set_error("physical parameters must be positive and finite"); return CLB_EINVAL; }
+    const double cs = 1.0 / std::sqrt(3.0);
+    const double nu = Ma * cs * H * std::sqrt(Pr / Ra);
+    const double alpha = nu / Pr;
+    *tau_nu = 3.0 * nu + 0.5;
+    *tau_alpha = alpha / 0.25 + 0.5;
+    *g_beta = Ra * nu * alpha / (dT * H * H * H);
+    return CLB_OK;
+}
+
+extern "C" void clb_destroy(clb_lattice* h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->buf[0]);
+    (void)hipFree(h->buf[1]);
+    (void)hipFree(h->d_fields);
+    (void)hipFree(h->d_snap);
+    (void)hipFree(h->d_partials);
+    (void)hipFree(h->d_diag);
+    if (h->ev[0]) (void)hipEventDestroy(h->ev[0]);
+    if (h->ev[1]) (void)hipEventDestroy(h->ev[1]);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+static int create_impl(const clb_desc* desc, void* hip_stream, clb_lattice** out)
+{
+    int rc = validate_desc(desc);
+    if (rc) return rc;
+    clb_lattice* h = new (std::nothrow) clb_lattice;
+    if (!h) { set_error("host allocation failed"); return CLB_ENOMEM; }
+    *out = h;
+    h->desc = *desc;
+    CLB_HIP(hipGetDevice(&h->device));
+    if (hip_stream) {
+        h->stream = (hipStream_t)hip_stream;
+    } else {
+        CLB_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        h->own_stream = true;
+    }
+    const size_t eb = elem_bytes(desc->precision);
+    h->pitch = row_pitch(desc->nx, eb);
+    h->plane = (long long)h->pitch * desc->ny;
+    h->buf_bytes = size_t(14) * h->plane * eb;
+    const size_t n = size_t(desc->nx) * desc->ny;
+    if (hipMalloc(&h->buf[0], h->buf_bytes) != hipSuccess || hipMalloc(&h->buf[1], h->buf_bytes) != hipSuccess ||
+        hipMalloc((void**)&h->d_fields, 4 * n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("device allocation of %zu bytes failed", 2 * h->buf_bytes + 4 * n * sizeof(double));
+        return CLB_ENOMEM;
+    }
+    CLB_HIP(hipMemsetAsync(h->buf[0], 0, h->buf_bytes, h->stream));
+    CLB_HIP(hipMemsetAsync(h->buf[1], 0, h->buf_bytes, h->stream));
+    CLB_HIP(hipEventCreate(&h->ev[0]));
+    CLB_HIP(hipEventCreate(&h->ev[1]));
+    return clb_init(h, nullptr, nullptr, nullptr);
+}
+
+extern "C" int clb_create(const clb_desc* desc, void* hip_stream, clb_lattice** out)
+{
+    clear_error();
+    if (!out) { set_error("out is NULL"); return CLB_EINVAL; }
+    *out = nullptr;
+    clb_lattice* h = nullptr;
+    const int rc = create_impl(desc, hip_stream, &h);
+    if (rc) {
+        clb_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return CLB_OK;
+}
+
+extern "C" int clb_set_params(clb_lattice* h, double tau_nu, double tau_alpha, double g_beta, double Ma)
+{
+    clear_error();
+    if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
+    const int rc = check_params(tau_nu, tau_alpha, g_beta, Ma);
+    if (rc) return rc;
+    h->par.tau_nu = tau_nu;
+    h->par.tau_alpha = tau_alpha;
+    h->par.g_beta = g_beta;
+    h->par.Ma = Ma;
+    return CLB_OK;
+}
+
+extern "C" int clb_set_relaxation(clb_lattice* h, double s_b, double s3, double s4, double lambda2)
+{
+    clear_error();
+    if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
+    const double v[4] = {s_b, s3, s4, lambda2};
+    for (double r : v)
+        if (!std::isfinite(r) || r <= 0.0 || r >= 2.0) { set_error("relaxation rates must lie in (0, 2)"); return CLB_EINVAL; }
+    h->par.s_b = s_b;
+    h->par.s3 = s3;
+    h->par.s4 = s4;
+    h->par.lam2 = lambda2;
+    return CLB_OK;
+}
+
+extern "C" int clb_set_body_force(clb_lattice* h, double Fvx, double Fvy)
+{
+    clear_error();
+    if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
+    if (!std::isfinite(Fvx) || !std::isfinite(Fvy)) { set_error("body force must be finite"); return CLB_EINVAL; }
+    h->par.Fvx = Fvx;
+    h->par.Fvy = Fvy;
+    return CLB_OK;
+}
+
+extern "C" int clb_init(clb_lattice* h, const double* rho, const double* u, const double* T)
+{
+    clear_error();
+    if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
+    const clb_desc& d = h->desc;
+    const size_t n = size_t(d.nx) * d.ny;
+    // Stage the fields in pinned-free host memory, then one upload.
+    double* host = (double*)malloc(4 * n * sizeof(double));
+    if (!host) { set_error("host allocation failed"); return CLB_ENOMEM; }
+    for (size_t k = 0; k < n; ++k) {
+        host[k] = rho ? rho[k] : 1.0;
+        host[n + k] = u ? u[k] : 0.0;
+        host[2 * n + k] = u ? u[n + k] : 0.0;
+        host[3 * n + k] = T ? T[k] : d.T0;
+    }
+    for (size_t k = 0; k < 4 * n; ++k)
+        if (!std::isfinite(host[k]) || (k < n && host[k] <= 0.0)) {
+            free(host);
+            set_error("initial fields must be finite with rho > 0");
+            return CLB_EINVAL;
+        }
+    hipError_t e = hipMemcpyAsync(h->d_fields, host, 4 * n * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    free(host);
+    if (e != hipSuccess) { set_error("upload of initial fields failed: %s", hipGetErrorString(e)); return CLB_EDEVICE; }
+    const Geo G = make_geo(d, h->pitch, h->plane);
+    const double TR = is_dev(d.precision) ? d.T0 : 0.0;
+    const dim3 grid = node_grid(G), block(TX, TY);
+    h->cur = 0;
+    switch (d.precision) {
+    case CLB_FP64:
+        init_kernel<double, false><<<grid, block, 0, h->stream>>>((double*)h->buf[0], G, h->d_fields, h->par.g_beta, d.T0, h->par.Fvx, h->par.Fvy, TR);
+        break;
+    case CLB_FP64_DEV:
+        init_kernel<double, true><<<grid, block, 0, h->stream>>>((double*)h->buf[0], G, h->d_fields, h->par.g_beta, d.T0, h->par.Fvx, h->par.Fvy, TR);
+        break;
+    default:
+        init_kernel<float, true><<<grid, block, 0, h->stream>>>((float*)h->buf[0], G, h->d_fields, h->par.g_beta, d.T0, h->par.Fvx, h->par.Fvy, TR);
+        break;
+    }
+    CLB_HIP(hipGetLastError());
+    h->steps = 0;
+    h->has_snap = false;
+    return CLB_OK;
+}
+
+extern "C" int clb_step(clb_lattice* h, long long n)
+{
+    clear_error();
+    if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
+    if (n < 0) { set_error("negative step count"); return CLB_EINVAL; }
+    return launch_step(h, n);
+}
+
+extern "C" int clb_time_steps(clb_lattice* h, long long n, double* ms)
+{
+    clear_error();
+    if (!h || !ms) { set_error("NULL argument"); return CLB_EINVAL; }
+    if (n <= 0) { set_error("step count must be positive"); return CLB_EINVAL; }
+    CLB_HIP(hipEventRecord(h->ev[0], h->stream));
+    const int rc = launch_step(h, n);
+    if (rc) return rc;
+    CLB_HIP(hipEventRecord(h->ev[1], h->stream));
+    CLB_HIP(hipEventSynchronize(h->ev[1]));
+    float t = 0.0f;
+    CLB_HIP(hipEventElapsedTime(&t, h->ev[0], h->ev[1]));
+    *ms = t;
+    return CLB_OK;
+}
+
+extern "C" int clb_synchronize(clb_lattice* h)
+{
+    clear_error();
+    if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
+    CLB_HIP(hipStreamSynchronize(h->stream));
+    return CLB_OK;
+}
+
+extern "C" int clb_moments(clb_lattice* h, double* rho, double* u, double* T)
+{
+    clear_error();
+    if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
+    int rc = launch_moments(h);
+    if (rc) return rc;
+    const size_t n = size_t(h->desc.nx) * h->desc.ny;
+    if (rho) CLB_HIP(hipMemcpyAsync(rho, h->d_fields, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    if (u) CLB_HIP(hipMemcpyAsync(u, h->d_fields + n, 2 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    if (T) CLB_HIP(hipMemcpyAsync(T, h->d_fields + 3 * n, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    CLB_HIP(hipStreamSynchronize(h->stream));
+    return CLB_OK;
+}
+
+extern "C" int clb_get_populations(clb_lattice* h, double* f, double* g)
+{
+    clear_error();
+    if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
+    const clb_desc& d = h->desc;
+    const size_t n = size_t(d.nx) * d.ny;
+    double* dev = nullptr;
+    CLB_HIP(hipMalloc((void**)&dev, 14 * n * sizeof(double)));
+    const Geo G = make_geo(d, h->pitch, h->plane);
+    const double TR = is_dev(d.precision) ? d.T0 : 0.0;
+    const dim3 grid = node_grid(G), block(TX, TY);
+    const void* src = h->buf[h->cur];
+    switch (d.precision) {
+    case CLB_FP64: populations_kernel<double, false><<<grid, block, 0, h->stream>>>((const double*)src, G, TR, dev, dev + 9 * n); break;
+    case CLB_FP64_DEV: populations_kernel<double, true><<<grid, block, 0, h->stream>>>((const double*)src, G, TR, dev, dev + 9 * n); break;
+    default: populations_kernel<float, true><<<grid, block, 0, h->stream>>>((const float*)src, G, TR, dev, dev + 9 * n); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && f) e = hipMemcpyAsync(f, dev, 9 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && g) e = hipMemcpyAsync(g, dev + 9 * n, 5 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(dev);
+    if (e != hipSuccess) { set_error("population export failed: %s", hipGetErrorString(e)); return CLB_EDEVICE; }
+    return CLB_OK;
+}
+
+extern "C" int clb_diagnostics(clb_lattice* h, int snapshot, clb_diag* out)
+{
+    clear_error();
+    if (!h || !out) { set_error("NULL argument"); return CLB_EINVAL; }
+    const clb_desc& d = h->desc;
+    const size_t n = size_t(d.nx) * d.ny;
+    const int nblocks = int((n + RED_NT - 1) / RED_NT);
+    if (!h->d_snap) CLB_HIP(hipMalloc((void**)&h->d_snap, 3 * n * sizeof(double)));
+    if (!h->d_diag) CLB_HIP(hipMalloc((void**)&h->d_diag, DIAG_SLOTS * sizeof(double)));
+    if (h->partials_cap < nblocks) {
+        (void)hipFree(h->d_partials);
+        h->d_partials = nullptr;
+        CLB_HIP(hipMalloc((void**)&h->d_partials, size_t(nblocks) * DIAG_SLOTS * sizeof(double)));
+        h->partials_cap = nblocks;
+    }
+    int rc = launch_moments(h);
+    if (rc) return rc;
+    const Geo G = make_geo(d, h->pitch, h->plane);
+    diag_reduce_kernel<<<nblocks, RED_NT, 0, h->stream>>>(h->d_fields, h->d_snap, h->has_snap ? 1 : 0, G, h->d_partials);
+    CLB_HIP(hipGetLastError());
+    diag_final_kernel<<<1, RED_NT, 0, h->stream>>>(h->d_partials, nblocks, h->d_diag);
+    CLB_HIP(hipGetLastError());
+    double r[DIAG_SLOTS];
+    CLB_HIP(hipMemcpyAsync(r, h->d_diag, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    if (snapshot) {
+        CLB_HIP(hipMemcpyAsync(h->d_snap, h->d_fields + n, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    }
+    CLB_HIP(hipStreamSynchronize(h->stream));
+    if (snapshot) h->has_snap = true;
+    out->step = h->steps;
+    out->mass = r[0];
+    out->heat = r[1];
+    out->mom_x = r[2];
+    out->mom_y = r[3];
+    out->sum_w = r[4];
+    out->sum_w_ux_T = r[5];
+    out->sum_w_uy_T = r[6];
+    for (int i = 0; i < 4; ++i) out->wall_flux[i] = r[7 + i];
+    out->u_max = r[DIAG_SUMS + 0];
+    out->du_max = r[DIAG_SUMS + 1];
+    out->dT_max = r[DIAG_SUMS + 2];
+    out->nonfinite = r[DIAG_SUMS + 3] > 0.0 ? 1 : 0;
+    if (out->nonfinite) {
+        set_error("non-finite density, velocity or temperature at step %lld", h->steps);
+        return CLB_EDIVERGED;
+    }
+    return CLB_OK;
+}

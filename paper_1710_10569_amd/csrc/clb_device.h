@@ -1,0 +1,378 @@
+// clb_device.h -- per-node device code of the CLB thermal lattice Boltzmann step for gfx950.
+//
+// One node update = pull streaming (Eqs. 12, 22 in pull form) -> wall step on wall nodes
+// (Sec. 3 boundary conditions) -> macroscopic quantities (Eqs. 3, 13, 23) -> D2Q9 CLB collision
+// (Sec. 2.1, Eq. 8) -> D2Q5 CLB collision (Sec. 2.2, Eq. 19) -> store at the node itself.
+//
+// Storage: structure of arrays.  A population buffer holds 14 planes (f0..f8, then g0..g4), each
+// `plane` elements long; node (x, y) of a plane is at y*pitch + x.  The buffer read by a step holds
+// post-collision values of the previous step at their source node, so f_i(x, t) = buf_i(x - e_i).
+//
+// Two storage forms share this code through the template flag DEV:
+//   DEV = false: buf holds f_i and g_i.
+//   DEV = true : buf holds f_i - w_i and g_i - w^T_i T0 (w: D2Q9 rest weights, w^T = (1/2, 1/8 x4)).
+//               All moments below are then formed as deviations from the rest state, so no value
+//               of order one is ever added to a small one; this is what makes FP32 storage usable.
+// The algebra is the same for both: R0 (rest density) and TR (rest temperature) are 1 and T0 for
+// DEV, 0 and 0 otherwise; "dr" is rho - R0 and "dT" is T - TR.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace clb {
+
+enum { K_PERIODIC = 0, K_DIRICHLET = 1, K_ADIABATIC = 2 };
+enum { WEST = 0, EAST = 1, SOUTH = 2, NORTH = 3 };
+
+// Geometry of one lattice (kernel argument, or an entry of the batch table).
+struct Geo {
+    int nx, ny;          // nodes
+    int pitch;           // elements per row in a plane
+    int perx, pery;      // 1 if the x (resp. y) direction is periodic
+    long long plane;     // elements per plane
+    int kind[4];         // W, E, S, N
+};
+
+// Per-lattice physical parameters in the arithmetic type.
+template <typename Real>
+struct Par {
+    Real om_nu, om_b, om_3, om_4;   // 1 - s for s_nu, s_b, s3, s4
+    Real c3;                        // (1 - s3/2) / 3: forcing weight of k~21, k~12 (Eq. 11)
+    Real om_l1, om_l2;              // 1 - lambda1, 1 - lambda2
+    Real g_beta, Fvx, Fvy;          // Eq. 3
+    Real Toff;                      // TR - T0, so that T - T0 = dT + Toff
+    Real TR;                        // rest temperature of the storage form
+    Real uw[4][2];                  // wall velocities, W E S N
+    Real dTw[4];                    // wall temperatures minus TR
+};
+
+template <typename Real> __device__ __forceinline__ Real R0v();
+template <> __device__ __forceinline__ float R0v<float>() { return 1.0f; }
+template <> __device__ __forceinline__ double R0v<double>() { return 1.0; }
+
+// Select one of four values by a runtime index without indexing a kernel-argument array (which
+// would make the compiler copy the argument block to private memory).
+template <typename T>
+__device__ __forceinline__ T sel4(T v0, T v1, T v2, T v3, int i)
+{
+    return i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : v3));
+}
+
+// ---------------------------------------------------------------------------------------------
+// Pull: the 14 post-streaming populations of node (x, y).  Periodic directions wrap; in a
+// walled direction a source outside the domain is clamped to the edge -- the value read is then
+// meaningless and is replaced by the wall step.
+template <typename Real>
+__device__ __forceinline__ void pull(const Real* __restrict__ src, const Geo& G, int x, int y,
+                                     Real f[9], Real g[5])
+{
+    const int xm = x > 0 ? x - 1 : (G.perx ? G.nx - 1 : 0);
+    const int xp = x < G.nx - 1 ? x + 1 : (G.perx ? 0 : G.nx - 1);
+    const int ym = y > 0 ? y - 1 : (G.pery ? G.ny - 1 : 0);
+    const int yp = y < G.ny - 1 ? y + 1 : (G.pery ? 0 : G.ny - 1);
+    const int rc = y * G.pitch, rm = ym * G.pitch, rp = yp * G.pitch;
+    const long long P = G.plane;
+    f[0] = src[0 * P + rc + x];
+    f[1] = src[1 * P + rc + xm];
+    f[2] = src[2 * P + rm + x];
+    f[3] = src[3 * P + rc + xp];
+    f[4] = src[4 * P + rp + x];
+    f[5] = src[5 * P + rm + xm];
+    f[6] = src[6 * P + rm + xp];
+    f[7] = src[7 * P + rp + xp];
+    f[8] = src[8 * P + rp + xm];
+    g[0] = src[9 * P + rc + x];
+    g[1] = src[10 * P + rc + xm];
+    g[2] = src[11 * P + rm + x];
+    g[3] = src[12 * P + rc + xp];
+    g[4] = src[13 * P + rp + x];
+}
+
+template <typename Real>
+__device__ __forceinline__ void pull_g(const Real* __restrict__ src, const Geo& G, int x, int y, Real g[5])
+{
+    const int xm = x > 0 ? x - 1 : (G.perx ? G.nx - 1 : 0);
+    const int xp = x < G.nx - 1 ? x + 1 : (G.perx ? 0 : G.nx - 1);
+    const int ym = y > 0 ? y - 1 : (G.pery ? G.ny - 1 : 0);
+    const int yp = y < G.ny - 1 ? y + 1 : (G.pery ? 0 : G.ny - 1);
+    const long long P = G.plane;
+    g[0] = src[9 * P + y * G.pitch + x];
+    g[1] = src[10 * P + y * G.pitch + xm];
+    g[2] = src[11 * P + ym * G.pitch + x];
+    g[3] = src[12 * P + y * G.pitch + xp];
+    g[4] = src[13 * P + yp * G.pitch + x];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Macroscopic quantities of a node: T (Eq. 23), F (Eq. 3), rho and u (Eq. 13).
+template <typename Real, bool DEV>
+struct Macro {
+    Real dr, rho, jx, jy, dT, Fx, Fy, ux, uy;
+};
+
+template <typename Real, bool DEV>
+__device__ __forceinline__ Macro<Real, DEV> macro(const Real f[9], const Real g[5], const Par<Real>& P)
+{
+    Macro<Real, DEV> m;
+    m.dT = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+    m.Fx = P.Fvx;
+    m.Fy = P.Fvy + P.g_beta * (m.dT + P.Toff);
+    m.dr = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    m.rho = (DEV ? R0v<Real>() : Real(0)) + m.dr;
+    m.jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    m.jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const Real inv = Real(1) / m.rho;
+    m.ux = (m.jx + Real(0.5) * m.Fx) * inv;
+    m.uy = (m.jy + Real(0.5) * m.Fy) * inv;
+    return m;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Wall step.
+//
+// psi(e, v): the 1D factor of the D2Q9 equilibrium whose central moments are Eq. 9,
+// f_i^eq = rho psi(e_ix, v_x) psi(e_iy, v_y), psi(0, v) = 2/3 - v^2, psi(+-1, v) = (1/3 +- v + v^2)/2.
+template <typename Real>
+__device__ __forceinline__ void psi3(Real v, Real p[3])   // p[0]: e = 0, p[1]: e = +1, p[2]: e = -1
+{
+    const Real v2 = v * v;
+    p[0] = Real(2.0 / 3.0) - v2;
+    p[1] = Real(0.5) * (Real(1.0 / 3.0) + v + v2);
+    p[2] = Real(0.5) * (Real(1.0 / 3.0) - v + v2);
+}
+
+// Difference of the product-form equilibria at two velocities, per unit density, in Eq. 4 order.
+template <typename Real>
+__device__ __forceinline__ void feq_diff(Real ax, Real ay, Real bx, Real by, Real d[9])
+{
+    Real pax[3], pay[3], pbx[3], pby[3];
+    psi3(ax, pax); psi3(ay, pay); psi3(bx, pbx); psi3(by, pby);
+    // direction i -> (index of e_x in psi3, index of e_y in psi3)
+    d[0] = pax[0] * pay[0] - pbx[0] * pby[0];
+    d[1] = pax[1] * pay[0] - pbx[1] * pby[0];
+    d[2] = pax[0] * pay[1] - pbx[0] * pby[1];
+    d[3] = pax[2] * pay[0] - pbx[2] * pby[0];
+    d[4] = pax[0] * pay[2] - pbx[0] * pby[2];
+    d[5] = pax[1] * pay[1] - pbx[1] * pby[1];
+    d[6] = pax[2] * pay[1] - pbx[2] * pby[1];
+    d[7] = pax[2] * pay[2] - pbx[2] * pby[2];
+    d[8] = pax[1] * pay[2] - pbx[1] * pby[2];
+}
+
+// Lattice directions of Eq. 4 as compile-time constants.
+__host__ __device__ constexpr int ex_of(int i) { return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0); }
+__host__ __device__ constexpr int ey_of(int i) { return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0); }
+
+// Force-corrected non-equilibrium bounce-back on an edge node of a straight wall with inward
+// normal n = (nx, ny) and tangent t = (ny, -nx) ((t, n) right-handed).  In the wall's frame a
+// direction has components (a, b) = (e.t, e.n); the three with b = +1 are unknown and are rebuilt
+// so that sum f = rho, sum f e = rho u_w - F/2 (so Eq. 13 returns u_w) and the normal population's
+// non-equilibrium part is bounced back:
+//   rho = (sum_{b=0} f + 2 sum_{b=-1} f - F_n/2) / (1 - u_n),  D = rho u_n (2/3 - u_t^2),
+//   f(0,1) = f(0,-1) + D,
+//   f(+-1,1) = f(-+1,-1) -+ (f(1,0) - f(-1,0))/2 +- (rho u_t - F_t/2)/2 + (rho u_n - F_n/2 - D)/2.
+// The loops run over compile-time directions and select by the runtime normal, so f stays in
+// registers (no indexing of f by a runtime value).
+template <typename Real, bool DEV>
+__device__ __forceinline__ void zou_he(Real f[9], int nx, int ny, Real uwx, Real uwy, Real Fx, Real Fy)
+{
+    const int tx = ny, ty = -nx;
+    const Real un = uwx * Real(nx) + uwy * Real(ny);
+    const Real ut = uwx * Real(tx) + uwy * Real(ty);
+    const Real Fn = Fx * Real(nx) + Fy * Real(ny);
+    const Real Ft = Fx * Real(tx) + Fy * Real(ty);
+    Real K0 = Real(0), Km = Real(0), d0 = Real(0), fZM = Real(0), fPM = Real(0), fMM = Real(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int a = ex_of(i) * tx + ey_of(i) * ty, b = ex_of(i) * nx + ey_of(i) * ny;
+        K0 += b == 0 ? f[i] : Real(0);
+        Km += b == -1 ? f[i] : Real(0);
+        d0 += b == 0 ? Real(a) * f[i] : Real(0);          // f(1,0) - f(-1,0)
+        fZM = (b == -1 && a == 0) ? f[i] : fZM;
+        fPM = (b == -1 && a == 1) ? f[i] : fPM;
+        fMM = (b == -1 && a == -1) ? f[i] : fMM;
+    }
+    // the rest weights over b = 0 plus twice those over b = -1 sum to 1
+    const Real rho = ((DEV ? Real(1) : Real(0)) + K0 + Real(2) * Km - Real(0.5) * Fn) / (Real(1) - un);
+    const Real D = rho * un * (Real(2.0 / 3.0) - ut * ut);
+    const Real half_t = Real(0.5) * (rho * ut - Real(0.5) * Ft);
+    const Real half_n = Real(0.5) * (rho * un - Real(0.5) * Fn - D);
+    const Real nZP = fZM + D;
+    const Real nPP = fMM - Real(0.5) * d0 + half_t + half_n;
+    const Real nMP = fPM + Real(0.5) * d0 - half_t + half_n;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int a = ex_of(i) * tx + ey_of(i) * ty, b = ex_of(i) * nx + ey_of(i) * ny;
+        f[i] = b == 1 ? (a == 0 ? nZP : (a == 1 ? nPP : nMP)) : f[i];
+    }
+}
+
+// Wall step at node (x, y), which must lie on a wall.  f, g hold the pulled populations on entry
+// (unknown ones meaningless) and the reconstructed ones on exit.
+//   1. g: non-equilibrium extrapolation from the inner neighbour x_f (diagonal one at corners):
+//      g_i = g_i^eq(T_b, u_w) + g_i(x_f) - g_i^eq(T_f, u_f), T_b = T_w (Dirichlet) or
+//      (4 T_f - T_ff)/3 (adiabatic; x_ff the second inner node).
+//   2. F at the node from T_b.
+//   3. f: Zou-He on edges; at corners non-equilibrium extrapolation from x_f with x_f's density,
+//      at the equilibrium velocities u_w - F_b/(2 rho_f) and u_f - F_f/(2 rho_f).
+// Corner data: velocity of the west/east wall; temperature of a Dirichlet wall if one meets
+// there, the west/east wall's otherwise.
+template <typename Real, bool DEV>
+__device__ __forceinline__ void wall_step(const Real* __restrict__ src, const Geo& G, const Par<Real>& P,
+                                       int x, int y, Real f[9], Real g[5])
+{
+    const bool onW = !G.perx && x == 0, onE = !G.perx && x == G.nx - 1;
+    const bool onS = !G.pery && y == 0, onN = !G.pery && y == G.ny - 1;
+    const int xw = onW ? WEST : (onE ? EAST : -1);
+    const int yw = onS ? SOUTH : (onN ? NORTH : -1);
+    const int dx = onW ? 1 : (onE ? -1 : 0);
+    const int dy = onS ? 1 : (onN ? -1 : 0);
+    const bool corner = xw >= 0 && yw >= 0;
+    const int vw = xw >= 0 ? xw : yw;
+    const int kx = xw >= 0 ? sel4(G.kind[0], G.kind[1], G.kind[2], G.kind[3], xw) : K_PERIODIC;
+    const int ky = yw >= 0 ? sel4(G.kind[0], G.kind[1], G.kind[2], G.kind[3], yw) : K_PERIODIC;
+    const int tw = (corner && kx != K_DIRICHLET && ky == K_DIRICHLET) ? yw : vw;
+    const int tkind = tw == xw ? kx : ky;
+    const Real uwx = sel4(P.uw[0][0], P.uw[1][0], P.uw[2][0], P.uw[3][0], vw);
+    const Real uwy = sel4(P.uw[0][1], P.uw[1][1], P.uw[2][1], P.uw[3][1], vw);
+
+    Real ff[9], gf[5];
+    pull(src, G, x + dx, y + dy, ff, gf);
+    const Macro<Real, DEV> mf = macro<Real, DEV>(ff, gf, P);
+
+    Real dTb;
+    if (tkind == K_DIRICHLET) {
+        dTb = sel4(P.dTw[0], P.dTw[1], P.dTw[2], P.dTw[3], tw);
+    } else {
+        Real gff[5];
+        pull_g(src, G, x + 2 * dx, y + 2 * dy, gff);
+        const Real dTff = (gff[0] + gff[1]) + (gff[2] + gff[3]) + gff[4];
+        dTb = (Real(4) * mf.dT - dTff) * Real(1.0 / 3.0);
+    }
+    // g^eq_i(T, u) = T phi_i(u): phi_0 = 1/2 - |u|^2, phi_{1,3} = (1/4 +- u_x + u_x^2)/2,
+    // phi_{2,4} = (1/4 +- u_y + u_y^2)/2.  T_b phi(u_w) - T_f phi(u_f) is formed as
+    // (T_b - T_f) phi(u_w) + T_f (phi(u_w) - phi(u_f)) so that no O(1) terms cancel.
+    {
+        const Real Tf = P.TR + mf.dT;
+        const Real dTbf = dTb - mf.dT;
+        const Real ax = uwx, ay = uwy, bx = mf.ux, by = mf.uy;
+        const Real pw1 = Real(0.5) * (Real(0.25) + ax + ax * ax), pw3 = Real(0.5) * (Real(0.25) - ax + ax * ax);
+        const Real pw2 = Real(0.5) * (Real(0.25) + ay + ay * ay), pw4 = Real(0.5) * (Real(0.25) - ay + ay * ay);
+        const Real pw0 = Real(0.5) - (ax * ax + ay * ay);
+        const Real d0 = (bx * bx + by * by) - (ax * ax + ay * ay);
+        const Real sx = (ax - bx) + (ax * ax - bx * bx), sxm = (bx - ax) + (ax * ax - bx * bx);
+        const Real sy = (ay - by) + (ay * ay - by * by), sym = (by - ay) + (ay * ay - by * by);
+        g[0] = gf[0] + dTbf * pw0 + Tf * d0;
+        g[1] = gf[1] + dTbf * pw1 + Tf * Real(0.5) * sx;
+        g[2] = gf[2] + dTbf * pw2 + Tf * Real(0.5) * sy;
+        g[3] = gf[3] + dTbf * pw3 + Tf * Real(0.5) * sxm;
+        g[4] = gf[4] + dTbf * pw4 + Tf * Real(0.5) * sym;
+    }
+    const Real Fxb = P.Fvx;
+    const Real Fyb = P.Fvy + P.g_beta * (dTb + P.Toff);
+
+    if (!corner) {
+        zou_he<Real, DEV>(f, dx, dy, uwx, uwy, Fxb, Fyb);
+    } else {
+        const Real ir = Real(1) / mf.rho;
+        Real d[9];
+        feq_diff(uwx - Real(0.5) * Fxb * ir, uwy - Real(0.5) * Fyb * ir,
+                 mf.ux - Real(0.5) * mf.Fx * ir, mf.uy - Real(0.5) * mf.Fy * ir, d);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = ff[i] + mf.rho * d[i];
+    }
+}
+
+__device__ __forceinline__ bool on_wall(const Geo& G, int x, int y)
+{
+    return (!G.perx && (x == 0 || x == G.nx - 1)) || (!G.pery && (y == 0 || y == G.ny - 1));
+}
+
+// ---------------------------------------------------------------------------------------------
+// Collisions.  Inputs: the node's post-wall-step populations (storage form) and its macroscopic
+// quantities; outputs overwrite f and g with the post-collision populations (storage form).
+//
+// D2Q9, Eq. 8.  With Gamma = M f (Eq. 7a) and Gamma~ = N(u) Gamma (Eq. 7b), only the
+// non-equilibrium parts n = Gamma~ - Gamma~^eq are relaxed: n* = (I - S) n + (I - S/2) C.  S acts on
+// the pair (k~20, k~02) as s_b on their sum and s_nu on their difference, and as s_nu, s3, s3,
+// s4 on k~11, k~21, k~12, k~22; the first central moments go from -F/2 to +F/2.  The raw
+// post-collision moments are N(-u) Gamma~* (N(u)^-1 = N(-u)), and f* = M^-1 Gamma*.
+template <typename Real, bool DEV>
+__device__ __forceinline__ void collide_f(Real f[9], const Macro<Real, DEV>& m, const Par<Real>& P)
+{
+    const Real R0 = DEV ? Real(1) : Real(0);
+    const Real third = Real(1.0 / 3.0), ninth = Real(1.0 / 9.0);
+    const Real ux = m.ux, uy = m.uy, rho = m.rho, dr = m.dr, jx = m.jx, jy = m.jy;
+    // raw moments of the stored populations (Eq. 6 order), relative to the rest state
+    const Real m20 = (f[1] + f[3]) + ((f[5] + f[6]) + (f[7] + f[8]));
+    const Real m02 = (f[2] + f[4]) + ((f[5] + f[6]) + (f[7] + f[8]));
+    const Real m11 = (f[5] - f[6]) + (f[7] - f[8]);
+    const Real m21 = (f[5] + f[6]) - (f[7] + f[8]);
+    const Real m12 = (f[5] - f[6]) - (f[7] - f[8]);
+    const Real m22 = (f[5] + f[6]) + (f[7] + f[8]);
+    const Real ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+    const Real k20 = m20 + R0 * third, k02 = m02 + R0 * third;   // full k20, k02
+    // non-equilibrium central moments
+    const Real c20 = (m20 - dr * third) - Real(2) * ux * jx + ux2 * rho;
+    const Real c02 = (m02 - dr * third) - Real(2) * uy * jy + uy2 * rho;
+    const Real c11 = m11 - ux * jy - uy * jx + uxy * rho;
+    const Real c21 = m21 - Real(2) * ux * m11 - uy * k20 + Real(2) * uxy * jx + ux2 * jy - ux2 * uy * rho;
+    const Real c12 = m12 - Real(2) * uy * m11 - ux * k02 + Real(2) * uxy * jy + uy2 * jx - ux * uy2 * rho;
+    const Real c22 = (m22 - dr * ninth) - Real(2) * ux * m12 - Real(2) * uy * m21 + Real(4) * uxy * m11
+                   + uy2 * k20 + ux2 * k02 - Real(2) * ux * uy2 * jx - Real(2) * uy * ux2 * jy + ux2 * uy2 * rho;
+    // relaxation (Eq. 8)
+    const Real sum_s = P.om_b * (c20 + c02), dif_s = P.om_nu * (c20 - c02);
+    const Real c20s = Real(0.5) * (sum_s + dif_s), c02s = Real(0.5) * (sum_s - dif_s);
+    const Real c11s = P.om_nu * c11;
+    const Real c21s = P.om_3 * c21 + P.c3 * m.Fy;
+    const Real c12s = P.om_3 * c12 + P.c3 * m.Fx;
+    const Real c22s = P.om_4 * c22;
+    const Real hx = Real(0.5) * m.Fx, hy = Real(0.5) * m.Fy;   // k~10*, k~01*
+    // back to raw moments, N(-u) Gamma~* (Gamma~*_20 = rho/3 + c20s, ..., Gamma~*_22 = rho/9 + c22s)
+    const Real t20 = rho * third + c20s, t02 = rho * third + c02s;
+    const Real K10 = ux * rho + hx, K01 = uy * rho + hy;
+    const Real D20 = dr * third + c20s + Real(2) * ux * hx + ux2 * rho;
+    const Real D02 = dr * third + c02s + Real(2) * uy * hy + uy2 * rho;
+    const Real K11 = c11s + ux * hy + uy * hx + uxy * rho;
+    const Real K21 = c21s + Real(2) * ux * c11s + uy * t20 + Real(2) * uxy * hx + ux2 * hy + ux2 * uy * rho;
+    const Real K12 = c12s + Real(2) * uy * c11s + ux * t02 + Real(2) * uxy * hy + uy2 * hx + ux * uy2 * rho;
+    const Real D22 = dr * ninth + c22s + Real(2) * ux * c12s + Real(2) * uy * c21s + Real(4) * uxy * c11s
+                   + uy2 * t20 + ux2 * t02 + Real(2) * ux * uy2 * hx + Real(2) * uy * ux2 * hy + ux2 * uy2 * rho;
+    // f* = M^-1 Gamma* (relative to the rest state)
+    f[0] = dr - D20 - D02 + D22;
+    f[1] = Real(0.5) * (K10 + D20 - K12 - D22);
+    f[2] = Real(0.5) * (K01 + D02 - K21 - D22);
+    f[3] = Real(0.5) * (-K10 + D20 + K12 - D22);
+    f[4] = Real(0.5) * (-K01 + D02 + K21 - D22);
+    f[5] = Real(0.25) * (K11 + K21 + K12 + D22);
+    f[6] = Real(0.25) * (-K11 + K21 - K12 + D22);
+    f[7] = Real(0.25) * (K11 - K21 - K12 + D22);
+    f[8] = Real(0.25) * (-K11 - K21 + K12 + D22);
+}
+
+// D2Q5, Eq. 19: the first central moments relax with lambda1, the second with lambda2, towards
+// Eq. 20's [T, 0, 0, T/4, T/4]; back-transform with N_T(-u) and M_T^-1 (Eq. 21).
+template <typename Real, bool DEV>
+__device__ __forceinline__ void collide_g(Real g[5], const Macro<Real, DEV>& m, const Par<Real>& P)
+{
+    const Real ux = m.ux, uy = m.uy, dT = m.dT;
+    const Real T = P.TR + dT;
+    const Real kx = g[1] - g[3], ky = g[2] - g[4];
+    const Real m20 = g[1] + g[3], m02 = g[2] + g[4];
+    const Real cx = kx - ux * T, cy = ky - uy * T;
+    const Real c20 = (m20 - Real(0.25) * dT) - Real(2) * ux * kx + ux * ux * T;
+    const Real c02 = (m02 - Real(0.25) * dT) - Real(2) * uy * ky + uy * uy * T;
+    const Real cxs = P.om_l1 * cx, cys = P.om_l1 * cy;
+    const Real c20s = P.om_l2 * c20, c02s = P.om_l2 * c02;
+    const Real Kx = cxs + ux * T, Ky = cys + uy * T;
+    const Real D20 = Real(0.25) * dT + c20s + Real(2) * ux * cxs + ux * ux * T;
+    const Real D02 = Real(0.25) * dT + c02s + Real(2) * uy * cys + uy * uy * T;
+    g[0] = dT - D20 - D02;
+    g[1] = Real(0.5) * (Kx + D20);
+    g[2] = Real(0.5) * (Ky + D02);
+    g[3] = Real(0.5) * (-Kx + D20);
+    g[4] = Real(0.5) * (-Ky + D02);
+}
+
+}  // namespace clb

@@ -1,0 +1,71 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function include/clb.h declares,
+and rejects invalid descriptions on the host before touching a device.  No compute call is made."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "clb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(clb_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_core_calls():
+    names = header_functions()
+    for core in ("clb_create", "clb_set_params", "clb_step", "clb_moments", "clb_destroy"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1710_10569_amd import clb
+    lib = ctypes.CDLL(clb.LIBPATH)
+    missing = [n for n in header_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_params_from_physics_matches_sec33_relations():
+    """nu = Ma c_s H sqrt(Pr/Ra), alpha = nu/Pr, g beta = Ra nu alpha/(dT H^3) (Sec. 3.3), tau_nu =
+    3 nu + 1/2 (Sec. 2.1), tau_alpha = 4 alpha + 1/2 (Sec. 2.2 with c_T^2 = 1/4)."""
+    from paper_1710_10569_amd import clb
+    tn, ta, gb = clb.params_from_physics(1e5, 0.71, 0.1, 255.0, 1.0)
+    nu = 0.1 / math.sqrt(3) * 255 * math.sqrt(0.71 / 1e5)
+    alpha = nu / 0.71
+    assert tn == pytest.approx(3 * nu + 0.5, rel=1e-15)
+    assert ta == pytest.approx(4 * alpha + 0.5, rel=1e-15)
+    assert gb == pytest.approx(1e5 * nu * alpha / 255 ** 3, rel=1e-14)
+    # the resulting characteristic velocity sqrt(g beta dT H) is Ma c_s
+    assert math.sqrt(gb * 255) == pytest.approx(0.1 / math.sqrt(3), rel=1e-14)
+    with pytest.raises(clb.CLBError):
+        clb.params_from_physics(-1.0, 0.71, 0.1, 255.0, 1.0)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=2, ny=10),
+    dict(nx=10, ny=10, edges={"west": ("dirichlet", 0, 0, 1)}),            # west wall, east periodic
+    dict(nx=10, ny=3, edges={"south": ("adiabatic", 0, 0, 0), "north": ("adiabatic", 0, 0, 0)}),
+    dict(nx=10, ny=10, precision=7),
+    dict(nx=10, ny=10, edges={"south": ("dirichlet", 0.6, 0, 0), "north": ("dirichlet", 0, 0, 0)}),
+    dict(nx=10, ny=10, T0=float("nan")),
+])
+def test_create_rejects_bad_descriptions_on_host(bad):
+    from paper_1710_10569_amd import clb
+    d = clb.make_desc(bad["nx"], bad["ny"], bad.get("precision", "fp64"), bad.get("edges"), bad.get("T0", 0.0))
+    h = ctypes.c_void_p()
+    rc = clb._lib.clb_create(ctypes.byref(d), None, ctypes.byref(h))
+    assert rc == clb.CLB_EINVAL
+    assert not h.value
+    assert clb.last_error()
+
+
+def test_null_arguments():
+    from paper_1710_10569_amd import clb
+    assert clb._lib.clb_create(None, None, None) == clb.CLB_EINVAL
+    clb._lib.clb_destroy(None)   # NULL-safe
+    assert clb._lib.clb_step(None, 1) == clb.CLB_EINVAL
+    assert clb._lib.clb_moments(None, None, None, None) == clb.CLB_EINVAL

@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle on the same seeded
+inputs.  FP64 (plain and deviation storage) must agree to 1e-12 relative; FP32 deviation storage
+to 1e-5 relative in u and T.  Sizes span several 64 x 4 workgroup tiles with ragged tails; the
+full-size case is the 2048 x 1024 Rayleigh-Benard cell in the launch configuration the benchmark
+times."""
+import numpy as np
+import pytest
+
+from paper_1710_10569_amd import workloads as W
+from tests.helpers import field_errors, oracle_from_workload, rel_err
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def _clb():
+    from paper_1710_10569_amd import clb
+    return clb
+
+
+def run_pair(w, precision, steps, chunks=1):
+    clb = _clb()
+    print(f"[parity] {w['name']} {precision} steps={steps}", flush=True)
+    g = clb.lattice_from_workload(w, precision)
+    o = oracle_from_workload(w)
+    errs = []
+    for _ in range(chunks):
+        g.step(steps // chunks)
+        o.step(steps // chunks)
+        errs.append(field_errors(g.moments(), o.moments(), w["T0"]))
+    return g, o, errs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp64_dev"])
+def test_taylor_green_fp64(gpu, precision):
+    """Periodic 64 x 64 Taylor-Green vortex + temperature mode, 1000 steps."""
+    w = W.taylor_green(64)
+    g, o, errs = run_pair(w, precision, 1000, chunks=4)
+    for e in errs:
+        assert max(e.values()) < FP64_TOL, e
+    fg, gg = g.populations()
+    fo, go = o.get_state()
+    assert np.abs(fg - fo).max() < 1e-14 and np.abs(gg - go).max() < 1e-14
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp64_dev"])
+@pytest.mark.parametrize("shape", [(37, 29), (130, 9), (5, 70)])
+def test_random_periodic_fp64(gpu, precision, shape):
+    """Random fields with buoyancy and a body force on ragged periodic lattices."""
+    w = W.random_periodic(*shape, seed=shape[0] * 7 + shape[1], T0=0.3)
+    w["body_force"] = (1e-5, -3e-5)
+    _, _, errs = run_pair(w, precision, 300, chunks=3)
+    for e in errs:
+        assert max(e.values()) < FP64_TOL, e
+
+
+WALLS = {
+    "cavity": ("dirichlet", "dirichlet", "adiabatic", "adiabatic"),
+    "all_dirichlet": ("dirichlet", "dirichlet", "dirichlet", "dirichlet"),
+    "all_adiabatic": ("adiabatic", "adiabatic", "adiabatic", "adiabatic"),
+    "channel": ("periodic", "periodic", "dirichlet", "adiabatic"),
+    "side_walls": ("adiabatic", "dirichlet", "periodic", "periodic"),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp64_dev"])
+@pytest.mark.parametrize("walls", sorted(WALLS))
+def test_walls_fp64(gpu, precision, walls):
+    """Every wall kind, corners of every kind pair, moving and permeable walls, buoyancy."""
+    w = W.random_walled(67, 45, seed=len(walls), kinds=WALLS[walls], wall_u=0.03, g_beta=2e-3)
+    g, o, errs = run_pair(w, precision, 300, chunks=3)
+    for e in errs:
+        assert max(e.values()) < FP64_TOL, e
+    fg, gg = g.populations()
+    fo, go = o.get_state()
+    assert np.array_equal(np.isnan(fg), np.isnan(fo)) and np.array_equal(np.isnan(gg), np.isnan(go))
+    m = ~np.isnan(fo)
+    assert np.abs(fg[m] - fo[m]).max() < 1e-13
+    m = ~np.isnan(go)
+    assert np.abs(gg[m] - go[m]).max() < 1e-13
+
+
+def test_cavity_256_fp64(gpu):
+    """The differentially heated cavity at its full 256 x 256 size, shortened to 400 steps."""
+    w = W.cavity(256)
+    _, _, errs = run_pair(w, "fp64", 400, chunks=2)
+    for e in errs:
+        assert max(e.values()) < FP64_TOL, e
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_rayleigh_benard_full_size(gpu, precision, tol):
+    """2048 x 1024 Rayleigh-Benard at Ra = 1e6, Ma = 0.3, 4 steps, every node compared."""
+    w = W.rayleigh_benard()
+    _, _, errs = run_pair(w, precision, 4, chunks=2)
+    for e in errs:
+        assert e["u"] < tol and e["T"] < tol, e
+
+
+def test_fp32_taylor_green(gpu):
+    w = W.taylor_green(64)
+    _, _, errs = run_pair(w, "fp32", 1000, chunks=2)
+    for e in errs:
+        assert e["u"] < FP32_TOL and e["T"] < FP32_TOL, e
+
+
+def test_fp32_cavity(gpu):
+    """FP32 deviation storage on the 256 x 256 cavity, 3000 steps, against the FP64 oracle."""
+    w = W.cavity(256)
+    _, _, errs = run_pair(w, "fp32", 3000, chunks=3)
+    for e in errs:
+        assert e["u"] < FP32_TOL and e["T"] < FP32_TOL, e
+
+
+def test_diagnostics_match_oracle_fields(gpu):
+    """FP64 sums, weighted Nusselt sums and wall fluxes against the same reductions of the oracle's
+    moment fields (numpy, FP64)."""
+    w = W.random_walled(70, 50, seed=3, kinds=WALLS["cavity"], g_beta=2e-3)
+    g, o, _ = run_pair(w, "fp64", 50)
+    d = g.diagnostics()
+    r, ux, uy, T = o.moments()
+    wx = np.ones(70); wx[[0, -1]] = 0.5
+    wy = np.ones(50); wy[[0, -1]] = 0.5
+    wgt = wy[:, None] * wx[None, :]
+    ref = {"mass": r.sum(), "heat": T.sum(), "mom_x": (r * ux).sum(), "mom_y": (r * uy).sum(),
+           "sum_w": wgt.sum(), "sum_w_ux_T": (wgt * ux * T).sum(), "sum_w_uy_T": (wgt * uy * T).sum()}
+    for k, v in ref.items():
+        assert d[k] == pytest.approx(v, rel=1e-12, abs=1e-14), k
+    west = (wy * 0.5 * (3 * T[:, 0] - 4 * T[:, 1] + T[:, 2])).sum()
+    east = (wy * 0.5 * (3 * T[:, -1] - 4 * T[:, -2] + T[:, -3])).sum()
+    south = (wx * 0.5 * (3 * T[0] - 4 * T[1] + T[2])).sum()
+    north = (wx * 0.5 * (3 * T[-1] - 4 * T[-2] + T[-3])).sum()
+    assert np.allclose(d["wall_flux"], [west, east, south, north], rtol=1e-11, atol=1e-13)
+    assert d["u_max"] == pytest.approx(np.sqrt(ux ** 2 + uy ** 2).max(), rel=1e-12)
+    assert d["du_max"] == -1.0 and d["nonfinite"] == 0
+
+
+def test_residual_snapshot(gpu):
+    clb = _clb()
+    w = W.cavity(64, Ra=1e5)
+    g = clb.lattice_from_workload(w, "fp64")
+    g.step(100)
+    _, ux0, uy0, T0 = g.moments()
+    g.diagnostics(snapshot=True)
+    g.step(100)
+    _, ux1, uy1, T1 = g.moments()
+    d = g.diagnostics()
+    assert d["du_max"] == pytest.approx(max(np.abs(ux1 - ux0).max(), np.abs(uy1 - uy0).max()), rel=1e-14)
+    assert d["dT_max"] == pytest.approx(np.abs(T1 - T0).max(), rel=1e-14)
+    assert d["step"] == 200
+
+
+def test_deterministic(gpu):
+    clb = _clb()
+    outs = []
+    for _ in range(2):
+        g = clb.lattice_from_workload(W.random_walled(90, 70, seed=9, wall_u=0.02), "fp32")
+        g.step(200)
+        outs.append((g.moments(), g.diagnostics()))
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(a, b)
+    assert outs[0][1] == outs[1][1]
+
+
+def test_divergence_is_reported(gpu):
+    """An unstable run (tau_nu -> 1/2, large velocities) ends in non-finite values: diagnostics
+    return CLB_EDIVERGED instead of numbers."""
+    clb = _clb()
+    w = W.random_periodic(64, 64, seed=1, amp_u=0.45, tau_nu=0.5000001, tau_alpha=0.5000001)
+    g = clb.lattice_from_workload(w, "fp64")
+    g.step(3000)
+    d = g.diagnostics(raise_on_diverged=False)
+    assert d["nonfinite"] == 1
+    with pytest.raises(clb.CLBError) as ei:
+        g.diagnostics()
+    assert ei.value.code == clb.CLB_EDIVERGED
+
+
+def test_host_side_errors(gpu):
+    clb = _clb()
+    g = clb.Lattice(16, 16, "fp32")
+    for args in ((0.5, 0.8, 0.0, 0.1), (0.8, 0.4, 0.0, 0.1), (float("nan"), 0.8, 0.0, 0.0)):
+        with pytest.raises(clb.CLBError) as ei:
+            g.set_params(*args)
+        assert ei.value.code == clb.CLB_EINVAL
+    with pytest.raises(clb.CLBError):
+        g.set_relaxation(2.0, 1.0, 1.0, 1.0)
+    with pytest.raises(clb.CLBError):
+        g.step(-1)
+    with pytest.raises(clb.CLBError):
+        g.init(rho=np.zeros((16, 16)))
+    g.close()
+    g.close()
