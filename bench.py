@@ -132,6 +132,9 @@ def main():
     ap.add_argument("--no-control", action="store_true", help="skip the 8192x4096 control lattice")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
     ap.add_argument("--no-copy", action="store_true", help="skip the plain-copy bandwidth reference")
+    ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (the reference kernel for "
+                         "scaling hardware byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -144,6 +147,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_only:
+        nbytes = args.copy_only << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}), flush=True)
+        return
     from paper_1710_10569_amd import clb, workloads as W
     stream = torch.cuda.Stream()   # default priority
     w = W.rayleigh_benard()

@@ -6,12 +6,14 @@ times) and initial macroscopic fields drawn from seeded generators
 (``numpy.random.default_rng(seed)``, PCG64) or written in closed form.  Each side maps the
 description onto its own interface.
 
-A workload is a dict::
+A workload is a dict (``u_scale`` is the problem's characteristic velocity, the scale against
+which velocity errors are reported)::
 
     {"name": str, "nx": int, "ny": int, "T0": float,
      "edges": {"west"|"east"|"south"|"north": (kind, ux_w, uy_w, T_w)},   # kind: periodic|dirichlet|adiabatic
      "physics": {"Ra", "Pr", "Ma", "H", "dT"}  or  "taus": {"tau_nu", "tau_alpha", "g_beta"},
-     "fields": {"rho", "ux", "uy", "T"}  (float64 arrays of shape (ny, nx), or None for a default)}
+     "fields": {"rho", "ux", "uy", "T"}  (float64 arrays of shape (ny, nx), or None for a default),
+     "u_scale": float}
 
 Walls sit on nodes, so a wall-bounded extent of N nodes has length H = N - 1.
 """
@@ -46,7 +48,7 @@ def taylor_green(n=64, U0=0.01, T0=1.0, Tamp=0.01, tau_nu=0.8, tau_alpha=0.7):
     return {"name": f"taylor_green_{n}x{n}", "nx": n, "ny": n, "T0": T0, "edges": _edges(),
             "taus": {"tau_nu": tau_nu, "tau_alpha": tau_alpha, "g_beta": 0.0},
             "fields": {"rho": rho, "ux": ux, "uy": uy, "T": T},
-            "k": k, "U0": U0, "Tamp": Tamp}
+            "k": k, "U0": U0, "Tamp": Tamp, "u_scale": U0}
 
 
 def cavity(L=256, Ra=1e5, Pr=0.71, Ma=0.1, seed=2, noise=1e-4, T_hot=0.5, T_cold=-0.5):
@@ -62,6 +64,7 @@ def cavity(L=256, Ra=1e5, Pr=0.71, Ma=0.1, seed=2, noise=1e-4, T_hot=0.5, T_cold
             "edges": _edges(west=("dirichlet", 0.0, 0.0, T_hot), east=("dirichlet", 0.0, 0.0, T_cold),
                             south=("adiabatic", 0.0, 0.0, 0.0), north=("adiabatic", 0.0, 0.0, 0.0)),
             "physics": {"Ra": Ra, "Pr": Pr, "Ma": Ma, "H": L - 1, "dT": T_hot - T_cold},
+            "u_scale": Ma / math.sqrt(3.0),
             "fields": {"rho": None, "ux": None, "uy": None, "T": T}}
 
 
@@ -78,6 +81,7 @@ def rayleigh_benard(nx=2048, ny=1024, Ra=1e6, Pr=0.71, Ma=0.3, seed=3, amp=1e-3,
     return {"name": f"rayleigh_benard_{nx}x{ny}_Ra{Ra:.3g}", "nx": nx, "ny": ny, "T0": T0,
             "edges": _edges(south=("dirichlet", 0.0, 0.0, T_hot), north=("dirichlet", 0.0, 0.0, T_cold)),
             "physics": {"Ra": Ra, "Pr": Pr, "Ma": Ma, "H": H, "dT": T_hot - T_cold},
+            "u_scale": Ma / math.sqrt(3.0),
             "fields": {"rho": None, "ux": None, "uy": None, "T": T}}
 
 
@@ -93,6 +97,7 @@ def rb_cell(Ra, L=60, H=30, Pr=0.71, Ma=0.3, T_hot=1.05, T_cold=0.95, amp=1e-3):
     return {"name": f"rb_cell_{L}x{H}_Ra{Ra:g}", "nx": L, "ny": ny, "T0": 0.5 * (T_hot + T_cold),
             "edges": _edges(south=("dirichlet", 0.0, 0.0, T_hot), north=("dirichlet", 0.0, 0.0, T_cold)),
             "physics": {"Ra": Ra, "Pr": Pr, "Ma": Ma, "H": H, "dT": T_hot - T_cold},
+            "u_scale": Ma / math.sqrt(3.0),
             "fields": {"rho": None, "ux": None, "uy": None, "T": T}}
 
 
@@ -103,6 +108,7 @@ def poiseuille(nx=4, ny=33, tau_nu=0.8, Fx=1e-6, T0=0.0):
             "edges": _edges(south=("dirichlet", 0.0, 0.0, T0), north=("dirichlet", 0.0, 0.0, T0)),
             "taus": {"tau_nu": tau_nu, "tau_alpha": 0.8, "g_beta": 0.0},
             "body_force": (Fx, 0.0),
+            "u_scale": Fx * (ny - 1) ** 2 / (8.0 * (tau_nu - 0.5) / 3.0),
             "fields": {"rho": None, "ux": None, "uy": None, "T": None}}
 
 
@@ -117,6 +123,7 @@ def random_periodic(nx, ny, seed, amp_u=0.05, amp_T=0.1, T0=0.0, g_beta=1e-3, ta
     return {"name": f"random_periodic_{nx}x{ny}_s{seed}", "nx": nx, "ny": ny, "T0": T0,
             "edges": _edges(),
             "taus": {"tau_nu": tau_nu, "tau_alpha": tau_alpha, "g_beta": g_beta},
+            "u_scale": amp_u,
             "fields": {"rho": rho, "ux": ux, "uy": uy, "T": T}}
 
 
@@ -139,6 +146,7 @@ def random_walled(nx, ny, seed, kinds=("dirichlet", "dirichlet", "adiabatic", "a
     return {"name": f"random_walled_{nx}x{ny}_s{seed}", "nx": nx, "ny": ny, "T0": 0.0,
             "edges": edges,
             "taus": {"tau_nu": tau_nu, "tau_alpha": tau_alpha, "g_beta": g_beta},
+            "u_scale": amp_u,
             "fields": {"rho": rho, "ux": ux, "uy": uy, "T": T}}
 
 

@@ -32,11 +32,14 @@ def rel_err(x, ref, base=0.0):
     return float(np.abs(x - ref).max() / scale) if scale > 0 else float(np.abs(x - ref).max())
 
 
-def field_errors(gpu_m, orc_m, T0):
-    """Relative errors of (rho, ux, uy, T): rho against |rho|, u against max |u| (both components
-    together), T against max |T - T0|."""
+def field_errors(gpu_m, orc_m, T0, u_scale=0.0):
+    """Relative max-norm errors of (rho, u, T): rho against max |rho|; u (both components) against
+    U = max(max |u_ref|, u_scale), u_scale being the workload's characteristic velocity (a flow
+    started from rest has |u| far below its scale for many steps); T against max |T_ref - T0|."""
     r, ux, uy, T = gpu_m
     rr, rux, ruy, rT = orc_m
-    umax = max(np.abs(rux).max(), np.abs(ruy).max())
-    eu = max(np.abs(ux - rux).max(), np.abs(uy - ruy).max()) / umax if umax > 0 else np.abs(ux - rux).max()
+    if any(np.isnan(a).any() for a in (r, ux, uy, T)):
+        return {"rho": float("inf"), "u": float("inf"), "T": float("inf")}
+    U = max(np.abs(rux).max(), np.abs(ruy).max(), u_scale)
+    eu = max(np.abs(ux - rux).max(), np.abs(uy - ruy).max()) / U
     return {"rho": rel_err(r, rr), "u": float(eu), "T": rel_err(T, rT, T0)}

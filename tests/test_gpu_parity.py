@@ -1,6 +1,7 @@
 """GPU parity: the HIP path, called through the C ABI, against the FP64 oracle on the same seeded
 inputs.  FP64 (plain and deviation storage) must agree to 1e-12 relative; FP32 deviation storage
-to 1e-5 relative in u and T.  Sizes span several 64 x 4 workgroup tiles with ragged tails; the
+to 1e-5 relative in u and T.  Velocity errors are relative to the larger of max |u_ref| and the
+workload's characteristic velocity; temperature errors to max |T_ref - T0|.  Sizes span several 64 x 4 workgroup tiles with ragged tails; the
 full-size case is the 2048 x 1024 Rayleigh-Benard cell in the launch configuration the benchmark
 times."""
 import numpy as np
@@ -29,7 +30,7 @@ def run_pair(w, precision, steps, chunks=1):
     for _ in range(chunks):
         g.step(steps // chunks)
         o.step(steps // chunks)
-        errs.append(field_errors(g.moments(), o.moments(), w["T0"]))
+        errs.append(field_errors(g.moments(), o.moments(), w["T0"], w.get("u_scale", 0.0)))
     return g, o, errs
 
 
