@@ -163,6 +163,35 @@ int clb_params_from_physics(double Ra, double Pr, double Ma, double H, double dT
  * elapsed milliseconds of the n launches.  Synchronises the stream. */
 int clb_time_steps(clb_lattice* h, long long n, double* ms);
 
+/* ---------------------------------------------------------------------------------------------
+ * Launch shapes and the autotuner.  The step kernel is compiled for a fixed set of workgroup tile
+ * shapes (nodes per row segment tx, thread rows ty, nodes per thread spt stacked ty rows apart,
+ * non-temporal stores or not).  Results do not depend on the shape; only speed does.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Number of compiled tile shapes. */
+int clb_tile_shape_count(void);
+
+/* Geometry of shape `shape` (0 <= shape < clb_tile_shape_count()); any output may be NULL.
+ * Errors: CLB_EINVAL for an out-of-range shape. */
+int clb_tile_shape_info(int shape, int* tx, int* ty, int* spt, int* nontemporal);
+
+/* Select / read the shape used by clb_step.  A new handle starts with the shape the autotuner
+ * last chose in this process for the same precision and size class (ceil(log2 nx),
+ * ceil(log2 ny)), else shape 2. */
+int clb_set_tile_shape(clb_lattice* h, int shape);
+int clb_get_tile_shape(clb_lattice* h, int* shape);
+
+/* Time every shape for `launches_per_shape` launches on this lattice, select the fastest for the
+ * handle and record it for its size class.  The timed launches read the current state and write
+ * only the spare buffer, so the lattice state and step count are unchanged.  best_shape and
+ * best_us (average launch time of the winner, microseconds) may be NULL.  Synchronises. */
+int clb_autotune(clb_lattice* h, int launches_per_shape, int* best_shape, double* best_us);
+
+/* Average launch time in microseconds of `launches` step launches with shape `shape`, state
+ * unchanged as in clb_autotune.  Synchronises. */
+int clb_time_shape(clb_lattice* h, int shape, int launches, double* us);
+
 /* Wait for the handle's stream. */
 int clb_synchronize(clb_lattice* h);
 

@@ -83,6 +83,13 @@ _sig("clb_params_from_physics", ctypes.c_int, [ctypes.c_double] * 5 + [_dp, _dp,
 _sig("clb_time_steps", ctypes.c_int, [_H, ctypes.c_longlong, _dp])
 _sig("clb_synchronize", ctypes.c_int, [_H])
 _sig("clb_last_error", ctypes.c_char_p, [])
+_ip = ctypes.POINTER(ctypes.c_int)
+_sig("clb_tile_shape_count", ctypes.c_int, [])
+_sig("clb_tile_shape_info", ctypes.c_int, [ctypes.c_int, _ip, _ip, _ip, _ip])
+_sig("clb_set_tile_shape", ctypes.c_int, [_H, ctypes.c_int])
+_sig("clb_get_tile_shape", ctypes.c_int, [_H, _ip])
+_sig("clb_autotune", ctypes.c_int, [_H, ctypes.c_int, _ip, _dp])
+_sig("clb_time_shape", ctypes.c_int, [_H, ctypes.c_int, ctypes.c_int, _dp])
 
 
 class CLBError(RuntimeError):
@@ -119,6 +126,16 @@ def params_from_physics(Ra, Pr, Ma, H, dT):
     t = [ctypes.c_double() for _ in range(3)]
     _check(_lib.clb_params_from_physics(Ra, Pr, Ma, H, dT, *[ctypes.byref(v) for v in t]))
     return tuple(v.value for v in t)
+
+
+def tile_shapes():
+    """[(tx, ty, spt, nontemporal)] of the compiled step-kernel tile shapes."""
+    out = []
+    for i in range(_lib.clb_tile_shape_count()):
+        v = [ctypes.c_int() for _ in range(4)]
+        _check(_lib.clb_tile_shape_info(i, *[ctypes.byref(x) for x in v]))
+        out.append(tuple(x.value for x in v))
+    return out
 
 
 def make_desc(nx, ny, precision="fp64", edges=None, T0=0.0):
@@ -196,6 +213,27 @@ class Lattice:
 
     def synchronize(self):
         _check(_lib.clb_synchronize(self._h))
+
+    @property
+    def tile_shape(self):
+        v = ctypes.c_int()
+        _check(_lib.clb_get_tile_shape(self._h, ctypes.byref(v)))
+        return v.value
+
+    @tile_shape.setter
+    def tile_shape(self, shape):
+        _check(_lib.clb_set_tile_shape(self._h, int(shape)))
+
+    def autotune(self, launches_per_shape=20):
+        """Time every tile shape (state unchanged), keep the fastest; returns (shape, us/launch)."""
+        b, us = ctypes.c_int(), ctypes.c_double()
+        _check(_lib.clb_autotune(self._h, int(launches_per_shape), ctypes.byref(b), ctypes.byref(us)))
+        return b.value, us.value
+
+    def time_shape(self, shape, launches=20):
+        us = ctypes.c_double()
+        _check(_lib.clb_time_shape(self._h, int(shape), int(launches), ctypes.byref(us)))
+        return us.value
 
     def moments(self):
         """(rho, ux, uy, T), each (ny, nx) float64."""

@@ -11,11 +11,15 @@
 //                    fixed reduction order (64-lane wavefront shuffles, then block, then a single
 //                    block over the per-block partials), so repeated runs agree bitwise.
 #include "clb_internal.h"
+#include "clb_step.h"
 
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 
 namespace clb {
 
@@ -92,28 +96,7 @@ Geo make_geo(const clb_desc& d, int pitch, long long plane)
 // ---------------------------------------------------------------------------------------------
 // Kernels.
 
-constexpr int TX = 64, TY = 4;   // one 64-lane wavefront per row segment, 4 rows per workgroup
-
-template <typename Real, bool DEV>
-__global__ __launch_bounds__(TX * TY) void step_kernel(const Real* __restrict__ src, Real* __restrict__ dst,
-                                                     Geo G, Par<Real> P)
-{
-    const int x = blockIdx.x * TX + threadIdx.x;
-    const int y = blockIdx.y * TY + threadIdx.y;
-    if (x >= G.nx || y >= G.ny) return;
-    Real f[9], g[5];
-    pull(src, G, x, y, f, g);
-    if (on_wall(G, x, y)) wall_step<Real, DEV>(src, G, P, x, y, f, g);
-    const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
-    collide_f<Real, DEV>(f, m, P);
-    collide_g<Real, DEV>(g, m, P);
-    const long long PL = G.plane;
-    const int o = y * G.pitch + x;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) dst[i * PL + o] = f[i];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) dst[(9 + i) * PL + o] = g[i];
-}
+constexpr int TX = 64, TY = 4;   // init / moments / export kernels: 64 x 4 nodes per workgroup
 
 // Lattice directions of Eq. 4 for the host-side and init/export kernels.
 __device__ constexpr int EXd[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -298,33 +281,42 @@ __global__ __launch_bounds__(RED_NT) void diag_final_kernel(const double* __rest
 
 static dim3 node_grid(const Geo& G) { return dim3((G.nx + TX - 1) / TX, (G.ny + TY - 1) / TY); }
 
-static int launch_step(clb_lattice* h, long long n)
+static hipError_t launch_one_step(clb_lattice* h, int shape, const void* src, void* dst)
 {
     const clb_desc& d = h->desc;
     const Geo G = make_geo(d, h->pitch, h->plane);
-    const dim3 grid = node_grid(G), block(TX, TY);
+    switch (d.precision) {
+    case CLB_FP64: return launch_step_any<double, false>(shape, src, dst, G, make_par<double>(d, h->par), h->stream);
+    case CLB_FP64_DEV: return launch_step_any<double, true>(shape, src, dst, G, make_par<double>(d, h->par), h->stream);
+    default: return launch_step_any<float, true>(shape, src, dst, G, make_par<float>(d, h->par), h->stream);
+    }
+}
+
+static int launch_step(clb_lattice* h, long long n)
+{
     for (long long s = 0; s < n; ++s) {
-        const void* src = h->buf[h->cur];
-        void* dst = h->buf[h->cur ^ 1];
-        switch (d.precision) {
-        case CLB_FP64:
-            step_kernel<double, false><<<grid, block, 0, h->stream>>>((const double*)src, (double*)dst, G,
-                                                                      make_par<double>(d, h->par));
-            break;
-        case CLB_FP64_DEV:
-            step_kernel<double, true><<<grid, block, 0, h->stream>>>((const double*)src, (double*)dst, G,
-                                                                     make_par<double>(d, h->par));
-            break;
-        default:
-            step_kernel<float, true><<<grid, block, 0, h->stream>>>((const float*)src, (float*)dst, G,
-                                                                    make_par<float>(d, h->par));
-            break;
-        }
-        CLB_HIP(hipGetLastError());
+        CLB_HIP(launch_one_step(h, h->shape, h->buf[h->cur], h->buf[h->cur ^ 1]));
         h->cur ^= 1;
         h->steps += 1;
     }
     return CLB_OK;
+}
+
+// Autotuner cache: (precision, ceil(log2 nx), ceil(log2 ny)) -> fastest tile shape measured.
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, int> g_tune_cache;
+
+static int log2_class(int n) { int c = 0; while ((1 << c) < n) ++c; return c; }
+static std::tuple<int, int, int> tune_key(const clb_desc& d)
+{
+    return std::make_tuple(d.precision, log2_class(d.nx), log2_class(d.ny));
+}
+
+int default_shape(const clb_desc& d)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(tune_key(d));
+    return it == g_tune_cache.end() ? 2 : it->second;
 }
 
 static int launch_moments(clb_lattice* h)
@@ -411,6 +403,7 @@ static int create_impl(const clb_desc* desc, void* hip_stream, clb_lattice** out
     if (!h) { set_error("host allocation failed"); return CLB_ENOMEM; }
     *out = h;
     h->desc = *desc;
+    h->shape = default_shape(*desc);
     CLB_HIP(hipGetDevice(&h->device));
     if (hip_stream) {
         h->stream = (hipStream_t)hip_stream;
@@ -555,6 +548,87 @@ extern "C" int clb_time_steps(clb_lattice* h, long long n, double* ms)
     float t = 0.0f;
     CLB_HIP(hipEventElapsedTime(&t, h->ev[0], h->ev[1]));
     *ms = t;
+    return CLB_OK;
+}
+
+extern "C" int clb_tile_shape_count(void) { return kNumShapes; }
+
+extern "C" int clb_tile_shape_info(int shape, int* tx, int* ty, int* spt, int* nontemporal)
+{
+    clear_error();
+    if (shape < 0 || shape >= kNumShapes) { set_error("tile shape %d out of range", shape); return CLB_EINVAL; }
+    const TileShape sh = tile_shape(shape);
+    if (tx) *tx = sh.tx;
+    if (ty) *ty = sh.ty;
+    if (spt) *spt = sh.spt;
+    if (nontemporal) *nontemporal = sh.nt;
+    return CLB_OK;
+}
+
+extern "C" int clb_set_tile_shape(clb_lattice* h, int shape)
+{
+    clear_error();
+    if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
+    if (shape < 0 || shape >= kNumShapes) { set_error("tile shape %d out of range", shape); return CLB_EINVAL; }
+    h->shape = shape;
+    return CLB_OK;
+}
+
+extern "C" int clb_get_tile_shape(clb_lattice* h, int* shape)
+{
+    clear_error();
+    if (!h || !shape) { set_error("NULL argument"); return CLB_EINVAL; }
+    *shape = h->shape;
+    return CLB_OK;
+}
+
+extern "C" int clb_autotune(clb_lattice* h, int launches_per_shape, int* best_shape, double* best_us)
+{
+    clear_error();
+    if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
+    if (launches_per_shape <= 0) { set_error("launches_per_shape must be positive"); return CLB_EINVAL; }
+    // Every timed launch reads the current state and writes the other buffer, which holds no
+    // state; the lattice is left exactly as it was.
+    const void* src = h->buf[h->cur];
+    void* dst = h->buf[h->cur ^ 1];
+    int best = -1;
+    double best_t = 0.0;
+    for (int s = 0; s < kNumShapes; ++s) {
+        for (int w = 0; w < 2; ++w) CLB_HIP(launch_one_step(h, s, src, dst));
+        CLB_HIP(hipEventRecord(h->ev[0], h->stream));
+        for (int r = 0; r < launches_per_shape; ++r) CLB_HIP(launch_one_step(h, s, src, dst));
+        CLB_HIP(hipEventRecord(h->ev[1], h->stream));
+        CLB_HIP(hipEventSynchronize(h->ev[1]));
+        float ms = 0.0f;
+        CLB_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+        const double us = 1e3 * ms / launches_per_shape;
+        if (best < 0 || us < best_t) { best = s; best_t = us; }
+    }
+    h->shape = best;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[tune_key(h->desc)] = best;
+    }
+    if (best_shape) *best_shape = best;
+    if (best_us) *best_us = best_t;
+    return CLB_OK;
+}
+
+extern "C" int clb_time_shape(clb_lattice* h, int shape, int launches, double* us)
+{
+    clear_error();
+    if (!h || !us) { set_error("NULL argument"); return CLB_EINVAL; }
+    if (shape < 0 || shape >= kNumShapes || launches <= 0) { set_error("bad shape or launch count"); return CLB_EINVAL; }
+    const void* src = h->buf[h->cur];
+    void* dst = h->buf[h->cur ^ 1];
+    for (int w = 0; w < 2; ++w) CLB_HIP(launch_one_step(h, shape, src, dst));
+    CLB_HIP(hipEventRecord(h->ev[0], h->stream));
+    for (int r = 0; r < launches; ++r) CLB_HIP(launch_one_step(h, shape, src, dst));
+    CLB_HIP(hipEventRecord(h->ev[1], h->stream));
+    CLB_HIP(hipEventSynchronize(h->ev[1]));
+    float ms = 0.0f;
+    CLB_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+    *us = 1e3 * ms / launches;
     return CLB_OK;
 }
 

@@ -375,4 +375,31 @@ __device__ __forceinline__ void collide_g(Real g[5], const Macro<Real, DEV>& m, 
     g[4] = Real(0.5) * (-Ky + D02);
 }
 
+// ---------------------------------------------------------------------------------------------
+// The whole node update: pull, wall step (wall nodes only), macroscopic, both collisions, and the
+// store of the 14 post-collision populations at the node itself.  NT selects non-temporal stores.
+template <typename Real, bool DEV, bool NT>
+__device__ __forceinline__ void node_update(const Real* __restrict__ src, Real* __restrict__ dst, const Geo& G,
+                                            const Par<Real>& P, int x, int y)
+{
+    Real f[9], g[5];
+    pull(src, G, x, y, f, g);
+    if (on_wall(G, x, y)) wall_step<Real, DEV>(src, G, P, x, y, f, g);
+    const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
+    collide_f<Real, DEV>(f, m, P);
+    collide_g<Real, DEV>(g, m, P);
+    const long long PL = G.plane;
+    const int o = y * G.pitch + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        if (NT) __builtin_nontemporal_store(f[i], dst + i * PL + o);
+        else dst[i * PL + o] = f[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        if (NT) __builtin_nontemporal_store(g[i], dst + (9 + i) * PL + o);
+        else dst[(9 + i) * PL + o] = g[i];
+    }
+}
+
 }  // namespace clb

@@ -88,6 +88,7 @@ struct clb_lattice {
     size_t buf_bytes = 0;     // bytes per population buffer (14 planes)
     void* buf[2] = {nullptr, nullptr};
     int cur = 0;              // buffer holding the post-collision state of the last step
+    int shape = 2;            // tile shape of the step kernel (clb_step.h)
     clb::Params par;
     long long steps = 0;
     double* d_fields = nullptr;     // 4 FP64 planes of nx*ny: init input, moments output

@@ -1,0 +1,81 @@
+// clb_step.h -- the tiled step kernel and its launch shapes.
+//
+// A workgroup updates a tile of TXW x (TY * SPT) nodes: TXW consecutive nodes of a row per thread
+// row (TXW is a multiple of the 64-lane wavefront, so every wavefront reads and writes 64
+// consecutive elements of a plane), TY thread rows, and SPT nodes per thread stacked TY rows
+// apart.  Tiles are numbered row-major over the lattice and handed to workgroups XCD by XCD: the
+// dispatcher places workgroup b on XCD b mod 8, so workgroup b takes tile (b mod 8) * q + b / 8
+// (q = tiles per XCD).  Each XCD then sweeps one contiguous band of rows, and the cache line that
+// two neighbouring tiles share at their edge -- every plane with an x component is read one
+// element off alignment -- is fetched once into that XCD's L2 instead of once per XCD.
+#pragma once
+
+#include "clb_device.h"
+
+namespace clb {
+
+struct TileShape { int tx, ty, spt, nt; };
+
+// The compiled shapes (the autotuner chooses among them).
+constexpr int kNumShapes = 8;
+__host__ __device__ constexpr TileShape tile_shape(int i)
+{
+    return i == 0 ? TileShape{64, 4, 1, 0}
+         : i == 1 ? TileShape{128, 2, 1, 0}
+         : i == 2 ? TileShape{256, 1, 1, 0}
+         : i == 3 ? TileShape{256, 1, 2, 0}
+         : i == 4 ? TileShape{128, 4, 1, 0}
+         : i == 5 ? TileShape{256, 2, 1, 0}
+         : i == 6 ? TileShape{256, 1, 1, 1}
+                  : TileShape{64, 4, 2, 0};
+}
+
+inline int tiles_x_of(const Geo& G, const TileShape& s) { return (G.nx + s.tx - 1) / s.tx; }
+inline int tiles_y_of(const Geo& G, const TileShape& s) { return (G.ny + s.ty * s.spt - 1) / (s.ty * s.spt); }
+
+template <typename Real, bool DEV, int TXW, int TY, int SPT, bool NT>
+__global__ __launch_bounds__(TXW * TY) void step_tile_kernel(const Real* __restrict__ src, Real* __restrict__ dst,
+                                                            Geo G, Par<Real> P, int tiles_x, int ntiles)
+{
+    const int q = int(gridDim.x >> 3);
+    const int t = int(blockIdx.x & 7) * q + int(blockIdx.x >> 3);
+    if (t >= ntiles) return;
+    const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
+    const int x = txi * TXW + int(threadIdx.x % TXW);
+    const int y0 = tyi * (TY * SPT) + int(threadIdx.x / TXW);
+    if (x >= G.nx) return;
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+        const int y = y0 + s * TY;
+        if (y < G.ny) node_update<Real, DEV, NT>(src, dst, G, P, x, y);
+    }
+}
+
+// Enqueue one step from src into dst with shape S.
+template <typename Real, bool DEV, int S>
+hipError_t launch_step_shape(const void* src, void* dst, const Geo& G, const Par<Real>& P, hipStream_t st)
+{
+    constexpr TileShape sh = tile_shape(S);
+    const int tx = tiles_x_of(G, sh), ntiles = tx * tiles_y_of(G, sh);
+    const int q = (ntiles + 7) / 8;
+    step_tile_kernel<Real, DEV, sh.tx, sh.ty, sh.spt, sh.nt != 0><<<dim3(8 * q), dim3(sh.tx * sh.ty), 0, st>>>(
+        (const Real*)src, (Real*)dst, G, P, tx, ntiles);
+    return hipGetLastError();
+}
+
+template <typename Real, bool DEV>
+hipError_t launch_step_any(int shape, const void* src, void* dst, const Geo& G, const Par<Real>& P, hipStream_t st)
+{
+    switch (shape) {
+    case 0: return launch_step_shape<Real, DEV, 0>(src, dst, G, P, st);
+    case 1: return launch_step_shape<Real, DEV, 1>(src, dst, G, P, st);
+    case 2: return launch_step_shape<Real, DEV, 2>(src, dst, G, P, st);
+    case 3: return launch_step_shape<Real, DEV, 3>(src, dst, G, P, st);
+    case 4: return launch_step_shape<Real, DEV, 4>(src, dst, G, P, st);
+    case 5: return launch_step_shape<Real, DEV, 5>(src, dst, G, P, st);
+    case 6: return launch_step_shape<Real, DEV, 6>(src, dst, G, P, st);
+    default: return launch_step_shape<Real, DEV, 7>(src, dst, G, P, st);
+    }
+}
+
+}  // namespace clb
