@@ -198,6 +198,80 @@ int clb_synchronize(clb_lattice* h);
 /* Message for the last error on the calling thread ("" if none). */
 const char* clb_last_error(void);
 
+/* ---------------------------------------------------------------------------------------------
+ * Batches: many lattices of different sizes resident in one HBM pool and advanced together.
+ *
+ * A batch owns (or borrows) one device pool and carves it into per-lattice regions: two
+ * population buffers and an FP64 snapshot of (u_x, u_y, T) for the residual test.  Adding a lattice
+ * is admission: it fails with CLB_ENOMEM when its region does not fit in the pool's free space.
+ * All lattices of a batch use the batch's precision.  Every schedule below runs the same per-node
+ * update, so a lattice's results do not depend on the schedule or on which other lattices share
+ * the batch.  Work is enqueued on the batch's stream; calls returning data synchronise it.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct clb_batch clb_batch;
+
+/* Pool bytes one lattice of this description occupies in a batch. */
+int clb_batch_footprint(const clb_desc* desc, size_t* bytes);
+
+/* Create a batch of at most `capacity` lattices.  pool == NULL: the library allocates
+ * hbm_budget_bytes of device memory for the pool.  pool != NULL: [pool, pool + pool_bytes) is used
+ * (e.g. a framework-allocated tensor, 256-byte aligned; it must outlive the batch) and
+ * hbm_budget_bytes is ignored.  hip_stream as in clb_create.
+ * Errors: CLB_EINVAL, CLB_ENOMEM, CLB_EDEVICE. */
+int clb_batch_create(int capacity, int precision, size_t hbm_budget_bytes, void* pool, size_t pool_bytes,
+                     void* hip_stream, clb_batch** out);
+
+/* Admit a lattice (desc->precision must equal the batch's) with the parameters of
+ * clb_set_params; it starts at rest (rho = 1, u = 0, T = T0) with step count 0.  *slot receives its
+ * index.  Errors: CLB_EINVAL; CLB_ENOMEM if the batch is full or the pool lacks space. */
+int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, double tau_alpha, double g_beta, double Ma,
+                  int* slot);
+
+/* Per-slot counterparts of clb_set_relaxation, clb_set_body_force, clb_init, clb_moments,
+ * clb_diagnostics. */
+int clb_batch_set_relaxation(clb_batch* b, int slot, double s_b, double s3, double s4, double lambda2);
+int clb_batch_set_body_force(clb_batch* b, int slot, double Fvx, double Fvy);
+int clb_batch_init(clb_batch* b, int slot, const double* rho, const double* u, const double* T);
+int clb_batch_moments(clb_batch* b, int slot, double* rho, double* u, double* T);
+int clb_batch_diagnostics(clb_batch* b, int slot, int snapshot, clb_diag* out);
+
+/* Release a slot and its pool region (stream-ordered after the work already enqueued). */
+int clb_batch_remove(clb_batch* b, int slot);
+
+/* Advance every resident lattice n steps: one launch per step over all lattices' tiles. */
+int clb_batch_step(clb_batch* b, long long n);
+
+/* The same n steps with one launch per lattice per step (the one-lattice-at-a-time schedule). */
+int clb_batch_step_each(clb_batch* b, long long n);
+
+/* The same n steps in one cooperative persistent launch (per chunk of at most 4096 steps): each
+ * workgroup sweeps a fixed range of tiles every step, waiting per lattice for the previous step.
+ * A bounded wait turns an overrun into CLB_EDEVICE from clb_batch_check instead of a hang. */
+int clb_batch_step_persistent(clb_batch* b, long long n);
+
+/* Synchronise and report whether a persistent launch gave up waiting (CLB_EDEVICE). */
+int clb_batch_check(clb_batch* b);
+
+/* Time n steps of schedule mode (0 grouped, 1 one launch per lattice, 2 persistent) with HIP events
+ * on the batch's stream; writes the elapsed milliseconds.  Synchronises. */
+int clb_batch_time_steps(clb_batch* b, int mode, long long n, double* ms);
+
+/* Tile width (64, 128 or 256 nodes per row segment; 256 nodes per tile) of one lattice. */
+int clb_batch_set_tile_width(clb_batch* b, int slot, int tile_width);
+
+/* For each size class (ceil(log2 nx), ceil(log2 ny)) present, time the grouped step over that
+ * class's lattices with each tile width (state unchanged) and keep the fastest for the class;
+ * lattices added later take the class's choice.  Synchronises. */
+int clb_batch_autotune(clb_batch* b, int launches);
+
+/* Lattices resident, pool bytes in use, pool size, total nodes.  Any output may be NULL. */
+int clb_batch_info(clb_batch* b, int* count, size_t* used_bytes, size_t* budget_bytes, long long* sites);
+
+int clb_batch_synchronize(clb_batch* b);
+
+/* NULL-safe. */
+void clb_batch_destroy(clb_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -273,3 +273,168 @@ def lattice_from_workload(w, precision="fp64", stream=None):
     fl = w["fields"]
     lat.init(fl["rho"], fl["ux"], fl["uy"], fl["T"])
     return lat
+
+
+# ------------------------------------------------------------------------------------------------
+# Batches (clb_batch_*).
+
+_B = ctypes.c_void_p
+_sig("clb_batch_footprint", ctypes.c_int, [ctypes.POINTER(clb_desc), ctypes.POINTER(ctypes.c_size_t)])
+_sig("clb_batch_create", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp,
+                                        ctypes.POINTER(_B)])
+_sig("clb_batch_add", ctypes.c_int, [_B, ctypes.POINTER(clb_desc)] + [ctypes.c_double] * 4 + [ctypes.POINTER(ctypes.c_int)])
+_sig("clb_batch_set_relaxation", ctypes.c_int, [_B, ctypes.c_int] + [ctypes.c_double] * 4)
+_sig("clb_batch_set_body_force", ctypes.c_int, [_B, ctypes.c_int, ctypes.c_double, ctypes.c_double])
+_sig("clb_batch_init", ctypes.c_int, [_B, ctypes.c_int, _dp, _dp, _dp])
+_sig("clb_batch_moments", ctypes.c_int, [_B, ctypes.c_int, _dp, _dp, _dp])
+_sig("clb_batch_diagnostics", ctypes.c_int, [_B, ctypes.c_int, ctypes.c_int, ctypes.POINTER(clb_diag)])
+_sig("clb_batch_remove", ctypes.c_int, [_B, ctypes.c_int])
+_sig("clb_batch_step", ctypes.c_int, [_B, ctypes.c_longlong])
+_sig("clb_batch_step_each", ctypes.c_int, [_B, ctypes.c_longlong])
+_sig("clb_batch_step_persistent", ctypes.c_int, [_B, ctypes.c_longlong])
+_sig("clb_batch_check", ctypes.c_int, [_B])
+_sig("clb_batch_time_steps", ctypes.c_int, [_B, ctypes.c_int, ctypes.c_longlong, _dp])
+_sig("clb_batch_set_tile_width", ctypes.c_int, [_B, ctypes.c_int, ctypes.c_int])
+_sig("clb_batch_autotune", ctypes.c_int, [_B, ctypes.c_int])
+_sig("clb_batch_info", ctypes.c_int, [_B, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t),
+                                      ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_longlong)])
+_sig("clb_batch_synchronize", ctypes.c_int, [_B])
+_sig("clb_batch_destroy", None, [_B])
+
+MODES = {"grouped": 0, "each": 1, "persistent": 2}
+
+
+def footprint(nx, ny, precision="fp32", edges=None, T0=0.0):
+    """Pool bytes one lattice occupies in a batch (clb_batch_footprint)."""
+    d = make_desc(nx, ny, precision, edges, T0)
+    v = ctypes.c_size_t()
+    _check(_lib.clb_batch_footprint(ctypes.byref(d), ctypes.byref(v)))
+    return v.value
+
+
+class Batch:
+    """Many lattices resident in one device pool (clb_batch_create ... clb_batch_destroy).
+
+    pool: None (the library allocates `budget_bytes`) or a CUDA tensor whose memory becomes the
+    pool (kept alive by this object)."""
+
+    def __init__(self, capacity, precision="fp32", budget_bytes=1 << 30, pool=None, stream=None):
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self._pool = pool
+        h = _B()
+        if pool is not None:
+            ptr, nbytes = pool.data_ptr(), pool.numel() * pool.element_size()
+            rc = _lib.clb_batch_create(int(capacity), self.precision, 0, _vp(ptr), nbytes,
+                                       None if stream is None else _vp(int(stream)), ctypes.byref(h))
+        else:
+            rc = _lib.clb_batch_create(int(capacity), self.precision, int(budget_bytes), None, 0,
+                                       None if stream is None else _vp(int(stream)), ctypes.byref(h))
+        _check(rc)
+        self._h = h
+        self.shapes = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.clb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def add(self, nx, ny, edges=None, T0=0.0, tau_nu=1.0, tau_alpha=1.0, g_beta=0.0, Ma=0.0):
+        d = make_desc(nx, ny, self.precision, edges, T0)
+        s = ctypes.c_int()
+        _check(_lib.clb_batch_add(self._h, ctypes.byref(d), tau_nu, tau_alpha, g_beta, Ma, ctypes.byref(s)))
+        self.shapes[s.value] = (int(nx), int(ny))
+        return s.value
+
+    def try_add(self, *a, **k):
+        """add(), or None if the batch is full or the pool lacks space (CLB_ENOMEM)."""
+        try:
+            return self.add(*a, **k)
+        except CLBError as e:
+            if e.code == CLB_ENOMEM:
+                return None
+            raise
+
+    def add_workload(self, w):
+        """Admit and initialise a workload description (see workloads.py); returns the slot or None
+        when it does not fit."""
+        if "taus" in w:
+            t = w["taus"]
+            tn, ta, gb, Ma = t["tau_nu"], t["tau_alpha"], t["g_beta"], 0.0
+        else:
+            p = w["physics"]
+            tn, ta, gb = params_from_physics(p["Ra"], p["Pr"], p["Ma"], p["H"], p["dT"])
+            Ma = p["Ma"]
+        slot = self.try_add(w["nx"], w["ny"], w["edges"], w["T0"], tn, ta, gb, Ma)
+        if slot is None:
+            return None
+        if "body_force" in w:
+            _check(_lib.clb_batch_set_body_force(self._h, slot, *w["body_force"]))
+        fl = w["fields"]
+        self.init(slot, fl["rho"], fl["ux"], fl["uy"], fl["T"])
+        return slot
+
+    def init(self, slot, rho=None, ux=None, uy=None, T=None):
+        nx, ny = self.shapes[slot]
+        n = nx * ny
+        u = None
+        if ux is not None or uy is not None:
+            u = np.zeros(2 * n)
+            if ux is not None:
+                u[:n] = np.ravel(np.broadcast_to(ux, (ny, nx)))
+            if uy is not None:
+                u[n:] = np.ravel(np.broadcast_to(uy, (ny, nx)))
+        r = None if rho is None else _f64(np.broadcast_to(rho, (ny, nx)), n)
+        t = None if T is None else _f64(np.broadcast_to(T, (ny, nx)), n)
+        _check(_lib.clb_batch_init(self._h, int(slot), _ptr(r), _ptr(u), _ptr(t)))
+
+    def set_relaxation(self, slot, s_b=1.0, s3=1.0, s4=1.0, lambda2=1.0):
+        _check(_lib.clb_batch_set_relaxation(self._h, int(slot), s_b, s3, s4, lambda2))
+
+    def set_tile_width(self, slot, width):
+        _check(_lib.clb_batch_set_tile_width(self._h, int(slot), int(width)))
+
+    def remove(self, slot):
+        _check(_lib.clb_batch_remove(self._h, int(slot)))
+        self.shapes.pop(slot, None)
+
+    def step(self, n=1, mode="grouped"):
+        fn = {"grouped": _lib.clb_batch_step, "each": _lib.clb_batch_step_each,
+              "persistent": _lib.clb_batch_step_persistent}[mode]
+        _check(fn(self._h, int(n)))
+
+    def check(self):
+        _check(_lib.clb_batch_check(self._h))
+
+    def time_steps(self, n, mode="grouped"):
+        ms = ctypes.c_double()
+        _check(_lib.clb_batch_time_steps(self._h, MODES[mode], int(n), ctypes.byref(ms)))
+        return ms.value
+
+    def autotune(self, launches=5):
+        _check(_lib.clb_batch_autotune(self._h, int(launches)))
+
+    def synchronize(self):
+        _check(_lib.clb_batch_synchronize(self._h))
+
+    def info(self):
+        c, u, b, s = ctypes.c_int(), ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_longlong()
+        _check(_lib.clb_batch_info(self._h, ctypes.byref(c), ctypes.byref(u), ctypes.byref(b), ctypes.byref(s)))
+        return {"count": c.value, "used_bytes": u.value, "budget_bytes": b.value, "sites": s.value}
+
+    def moments(self, slot):
+        nx, ny = self.shapes[slot]
+        n = nx * ny
+        rho, u, T = np.empty(n), np.empty(2 * n), np.empty(n)
+        _check(_lib.clb_batch_moments(self._h, int(slot), _ptr(rho), _ptr(u), _ptr(T)))
+        s = (ny, nx)
+        return rho.reshape(s), u[:n].reshape(s), u[n:].reshape(s), T.reshape(s)
+
+    def diagnostics(self, slot, snapshot=False, raise_on_diverged=True):
+        d = clb_diag()
+        rc = _lib.clb_batch_diagnostics(self._h, int(slot), int(bool(snapshot)), ctypes.byref(d))
+        if rc != CLB_OK and (rc != CLB_EDIVERGED or raise_on_diverged):
+            raise CLBError(rc, last_error())
+        return d.as_dict()

@@ -11,6 +11,7 @@
 //                    fixed reduction order (64-lane wavefront shuffles, then block, then a single
 //                    block over the per-block partials), so repeated runs agree bitwise.
 #include "clb_internal.h"
+#include "clb_aux.h"
 #include "clb_step.h"
 
 #include <algorithm>
@@ -94,192 +95,8 @@ Geo make_geo(const clb_desc& d, int pitch, long long plane)
 }
 
 // ---------------------------------------------------------------------------------------------
-// Kernels.
-
-constexpr int TX = 64, TY = 4;   // init / moments / export kernels: 64 x 4 nodes per workgroup
-
-// Lattice directions of Eq. 4 for the host-side and init/export kernels.
-__device__ constexpr int EXd[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__device__ constexpr int EYd[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-__device__ constexpr double W9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-__device__ constexpr double W5[5] = {0.5, 0.125, 0.125, 0.125, 0.125};
-
-// Source node x - e_i of direction i, or false if it lies outside the domain.
-__device__ __forceinline__ bool source_of(const Geo& G, int x, int y, int i, int& sx, int& sy)
-{
-    sx = x - EXd[i];
-    sy = y - EYd[i];
-    if (G.perx) sx = (sx + G.nx) % G.nx;
-    if (G.pery) sy = (sy + G.ny) % G.ny;
-    return sx >= 0 && sx < G.nx && sy >= 0 && sy < G.ny;
-}
-
-// Equilibria in FP64: f_i^eq = rho psi(e_ix, v_x) psi(e_iy, v_y) and
-// g_i^eq = T (c_T^2 +- u + u^2)/2 on the axes, T (1 - 2 c_T^2 - |u|^2) at rest, c_T^2 = 1/4.
-__device__ inline double psi(int e, double v) { return e == 0 ? 2.0 / 3.0 - v * v : 0.5 * (1.0 / 3.0 + e * v + v * v); }
-
-template <typename Real, bool DEV>
-__global__ void init_kernel(Real* __restrict__ buf, Geo G, const double* __restrict__ fields,
-                            double g_beta, double T0, double Fvx, double Fvy, double TR)
-{
-    const int x = blockIdx.x * TX + threadIdx.x;
-    const int y = blockIdx.y * TY + threadIdx.y;
-    if (x >= G.nx || y >= G.ny) return;
-    const long long n = (long long)G.nx * G.ny;
-    const long long k = (long long)y * G.nx + x;
-    const double rho = fields[k], ux = fields[n + k], uy = fields[2 * n + k], T = fields[3 * n + k];
-    const double Fx = Fvx, Fy = Fvy + g_beta * (T - T0);
-    const double vx = ux - 0.5 * Fx / rho, vy = uy - 0.5 * Fy / rho;
-    for (int i = 0; i < 9; ++i) {
-        // f_i(x) is read by the next pull from the node x - e_i... so store at the source of x.
-        int sx, sy;
-        if (!source_of(G, x, y, i, sx, sy)) continue;
-        double v = rho * psi(EXd[i], vx) * psi(EYd[i], vy);
-        if (DEV) v -= W9[i];
-        buf[i * G.plane + (long long)sy * G.pitch + sx] = Real(v);
-    }
-    const double gq[5] = {T * (0.5 - ux * ux - uy * uy), 0.5 * T * (0.25 + ux + ux * ux),
-                          0.5 * T * (0.25 + uy + uy * uy), 0.5 * T * (0.25 - ux + ux * ux),
-                          0.5 * T * (0.25 - uy + uy * uy)};
-    for (int i = 0; i < 5; ++i) {
-        int sx, sy;
-        if (!source_of(G, x, y, i, sx, sy)) continue;
-        double v = gq[i];
-        if (DEV) v -= W5[i] * TR;
-        buf[(9 + i) * G.plane + (long long)sy * G.pitch + sx] = Real(v);
-    }
-}
-
-template <typename Real, bool DEV>
-__global__ __launch_bounds__(TX * TY) void moments_kernel(const Real* __restrict__ src, Geo G, Par<Real> P,
-                                                        double* __restrict__ fields)
-{
-    const int x = blockIdx.x * TX + threadIdx.x;
-    const int y = blockIdx.y * TY + threadIdx.y;
-    if (x >= G.nx || y >= G.ny) return;
-    Real f[9], g[5];
-    pull(src, G, x, y, f, g);
-    if (on_wall(G, x, y)) wall_step<Real, DEV>(src, G, P, x, y, f, g);
-    const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
-    const long long n = (long long)G.nx * G.ny;
-    const long long k = (long long)y * G.nx + x;
-    fields[k] = double(m.rho);
-    fields[n + k] = double(m.ux);
-    fields[2 * n + k] = double(m.uy);
-    fields[3 * n + k] = double(P.TR) + double(m.dT);
-}
-
-template <typename Real, bool DEV>
-__global__ void populations_kernel(const Real* __restrict__ src, Geo G, double TR, double* __restrict__ fo,
-                                   double* __restrict__ go)
-{
-    const int x = blockIdx.x * TX + threadIdx.x;
-    const int y = blockIdx.y * TY + threadIdx.y;
-    if (x >= G.nx || y >= G.ny) return;
-    Real f[9], g[5];
-    pull(src, G, x, y, f, g);
-    const long long n = (long long)G.nx * G.ny;
-    const long long k = (long long)y * G.nx + x;
-    for (int i = 0; i < 9; ++i) {
-        int sx, sy;
-        const bool known = source_of(G, x, y, i, sx, sy);
-        if (fo) fo[i * n + k] = known ? double(f[i]) + (DEV ? W9[i] : 0.0) : __builtin_nan("");
-        if (i < 5 && go) go[i * n + k] = known ? double(g[i]) + (DEV ? W5[i] * TR : 0.0) : __builtin_nan("");
-    }
-}
-
-// Block-wide reductions of DIAG_SLOTS doubles: slots [0, DIAG_SUMS) are summed, the rest maxed.
-__device__ inline double wave_sum(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ inline double wave_max(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-template <int NT>
-__device__ inline void block_reduce(double (&v)[DIAG_SLOTS], double* out)
-{
-    __shared__ double red[NT / 64][DIAG_SLOTS];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int s = 0; s < DIAG_SLOTS; ++s) {
-        const double r = s < DIAG_SUMS ? wave_sum(v[s]) : wave_max(v[s]);
-        if (lane == 0) red[wave][s] = r;
-    }
-    __syncthreads();
-    if (threadIdx.x < DIAG_SLOTS) {
-        const int s = threadIdx.x;
-        double r = red[0][s];
-        for (int w = 1; w < NT / 64; ++w) r = s < DIAG_SUMS ? r + red[w][s] : fmax(r, red[w][s]);
-        out[s] = r;
-    }
-}
-
-constexpr int RED_NT = 256;
-
-// Per-node contributions from the FP64 moment fields (dense [4][ny][nx]).
-__global__ __launch_bounds__(RED_NT) void diag_reduce_kernel(const double* __restrict__ fields,
-                                                            const double* __restrict__ snap, int has_snap,
-                                                            Geo G, double* __restrict__ partials)
-{
-    const long long n = (long long)G.nx * G.ny;
-    const long long k = (long long)blockIdx.x * RED_NT + threadIdx.x;
-    double v[DIAG_SLOTS];
-#pragma unroll
-    for (int s = 0; s < DIAG_SLOTS; ++s) v[s] = 0.0;
-    v[DIAG_SUMS + 1] = v[DIAG_SUMS + 2] = has_snap ? 0.0 : -1.0;
-    if (k < n) {
-        const int x = int(k % G.nx), y = int(k / G.nx);
-        const double rho = fields[k], ux = fields[n + k], uy = fields[2 * n + k], T = fields[3 * n + k];
-        const double wx = (!G.perx && (x == 0 || x == G.nx - 1)) ? 0.5 : 1.0;
-        const double wy = (!G.pery && (y == 0 || y == G.ny - 1)) ? 0.5 : 1.0;
-        const double w = wx * wy;
-        v[0] = rho;
-        v[1] = T;
-        v[2] = rho * ux;
-        v[3] = rho * uy;
-        v[4] = w;
-        v[5] = w * ux * T;
-        v[6] = w * uy * T;
-        // wall heat flux: (3 T_b - 4 T_1 + T_2)/2 along the inward normal, trapezoid weight along the wall
-        const double* Tf = fields + 3 * n;
-        if (!G.perx && x == 0) v[7] = wy * 0.5 * (3.0 * T - 4.0 * Tf[k + 1] + Tf[k + 2]);
-        if (!G.perx && x == G.nx - 1) v[8] = wy * 0.5 * (3.0 * T - 4.0 * Tf[k - 1] + Tf[k - 2]);
-        if (!G.pery && y == 0) v[9] = wx * 0.5 * (3.0 * T - 4.0 * Tf[k + G.nx] + Tf[k + 2 * G.nx]);
-        if (!G.pery && y == G.ny - 1) v[10] = wx * 0.5 * (3.0 * T - 4.0 * Tf[k - G.nx] + Tf[k - 2 * G.nx]);
-        v[DIAG_SUMS + 0] = sqrt(ux * ux + uy * uy);
-        if (has_snap) {
-            v[DIAG_SUMS + 1] = fmax(fabs(ux - snap[k]), fabs(uy - snap[n + k]));
-            v[DIAG_SUMS + 2] = fabs(T - snap[2 * n + k]);
-        }
-        v[DIAG_SUMS + 3] = (__builtin_isfinite(rho) && __builtin_isfinite(ux) && __builtin_isfinite(uy) && __builtin_isfinite(T)) ? 0.0 : 1.0;
-    }
-    block_reduce<RED_NT>(v, partials + (long long)blockIdx.x * DIAG_SLOTS);
-}
-
-__global__ __launch_bounds__(RED_NT) void diag_final_kernel(const double* __restrict__ partials, int nblocks,
-                                                           double* __restrict__ out)
-{
-    double v[DIAG_SLOTS];
-#pragma unroll
-    for (int s = 0; s < DIAG_SLOTS; ++s) v[s] = (s < DIAG_SUMS) ? 0.0 : -1.0;
-    for (int b = threadIdx.x; b < nblocks; b += RED_NT) {
-#pragma unroll
-        for (int s = 0; s < DIAG_SLOTS; ++s)
-            v[s] = s < DIAG_SUMS ? v[s] + partials[(long long)b * DIAG_SLOTS + s]
-                                 : fmax(v[s], partials[(long long)b * DIAG_SLOTS + s]);
-    }
-    block_reduce<RED_NT>(v, out);
-}
-
-// ---------------------------------------------------------------------------------------------
 // Launch helpers.
 
-static dim3 node_grid(const Geo& G) { return dim3((G.nx + TX - 1) / TX, (G.ny + TY - 1) / TY); }
 
 static hipError_t launch_one_step(clb_lattice* h, int shape, const void* src, void* dst)
 {
@@ -321,26 +138,12 @@ int default_shape(const clb_desc& d)
 
 static int launch_moments(clb_lattice* h)
 {
-    const clb_desc& d = h->desc;
-    const Geo G = make_geo(d, h->pitch, h->plane);
-    const dim3 grid = node_grid(G), block(TX, TY);
-    const void* src = h->buf[h->cur];
-    switch (d.precision) {
-    case CLB_FP64:
-        moments_kernel<double, false><<<grid, block, 0, h->stream>>>((const double*)src, G, make_par<double>(d, h->par), h->d_fields);
-        break;
-    case CLB_FP64_DEV:
-        moments_kernel<double, true><<<grid, block, 0, h->stream>>>((const double*)src, G, make_par<double>(d, h->par), h->d_fields);
-        break;
-    default:
-        moments_kernel<float, true><<<grid, block, 0, h->stream>>>((const float*)src, G, make_par<float>(d, h->par), h->d_fields);
-        break;
-    }
-    CLB_HIP(hipGetLastError());
+    const Geo G = make_geo(h->desc, h->pitch, h->plane);
+    CLB_HIP(enqueue_moments(h->desc, h->par, h->buf[h->cur], G, h->d_fields, h->stream));
     return CLB_OK;
 }
 
-static int check_params(double tau_nu, double tau_alpha, double g_beta, double Ma)
+int check_params(double tau_nu, double tau_alpha, double g_beta, double Ma)
 {
     if (!std::isfinite(tau_nu) || !std::isfinite(tau_alpha) || !std::isfinite(g_beta) || !std::isfinite(Ma)) {
         set_error("parameters must be finite");
@@ -507,21 +310,8 @@ extern "C" int clb_init(clb_lattice* h, const double* rho, const double* u, cons
     free(host);
     if (e != hipSuccess) { set_error("upload of initial fields failed: %s", hipGetErrorString(e)); return CLB_EDEVICE; }
     const Geo G = make_geo(d, h->pitch, h->plane);
-    const double TR = is_dev(d.precision) ? d.T0 : 0.0;
-    const dim3 grid = node_grid(G), block(TX, TY);
     h->cur = 0;
-    switch (d.precision) {
-    case CLB_FP64:
-        init_kernel<double, false><<<grid, block, 0, h->stream>>>((double*)h->buf[0], G, h->d_fields, h->par.g_beta, d.T0, h->par.Fvx, h->par.Fvy, TR);
-        break;
-    case CLB_FP64_DEV:
-        init_kernel<double, true><<<grid, block, 0, h->stream>>>((double*)h->buf[0], G, h->d_fields, h->par.g_beta, d.T0, h->par.Fvx, h->par.Fvy, TR);
-        break;
-    default:
-        init_kernel<float, true><<<grid, block, 0, h->stream>>>((float*)h->buf[0], G, h->d_fields, h->par.g_beta, d.T0, h->par.Fvx, h->par.Fvy, TR);
-        break;
-    }
-    CLB_HIP(hipGetLastError());
+    CLB_HIP(enqueue_init(d, h->par, h->buf[0], G, h->d_fields, h->stream));
     h->steps = 0;
     h->has_snap = false;
     return CLB_OK;
@@ -663,15 +453,7 @@ extern "C" int clb_get_populations(clb_lattice* h, double* f, double* g)
     double* dev = nullptr;
     CLB_HIP(hipMalloc((void**)&dev, 14 * n * sizeof(double)));
     const Geo G = make_geo(d, h->pitch, h->plane);
-    const double TR = is_dev(d.precision) ? d.T0 : 0.0;
-    const dim3 grid = node_grid(G), block(TX, TY);
-    const void* src = h->buf[h->cur];
-    switch (d.precision) {
-    case CLB_FP64: populations_kernel<double, false><<<grid, block, 0, h->stream>>>((const double*)src, G, TR, dev, dev + 9 * n); break;
-    case CLB_FP64_DEV: populations_kernel<double, true><<<grid, block, 0, h->stream>>>((const double*)src, G, TR, dev, dev + 9 * n); break;
-    default: populations_kernel<float, true><<<grid, block, 0, h->stream>>>((const float*)src, G, TR, dev, dev + 9 * n); break;
-    }
-    hipError_t e = hipGetLastError();
+    hipError_t e = enqueue_populations(d, h->buf[h->cur], G, dev, h->stream);
     if (e == hipSuccess && f) e = hipMemcpyAsync(f, dev, 9 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess && g) e = hipMemcpyAsync(g, dev + 9 * n, 5 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -686,7 +468,8 @@ extern "C" int clb_diagnostics(clb_lattice* h, int snapshot, clb_diag* out)
     if (!h || !out) { set_error("NULL argument"); return CLB_EINVAL; }
     const clb_desc& d = h->desc;
     const size_t n = size_t(d.nx) * d.ny;
-    const int nblocks = int((n + RED_NT - 1) / RED_NT);
+    const Geo G = make_geo(d, h->pitch, h->plane);
+    const int nblocks = diag_blocks(G);
     if (!h->d_snap) CLB_HIP(hipMalloc((void**)&h->d_snap, 3 * n * sizeof(double)));
     if (!h->d_diag) CLB_HIP(hipMalloc((void**)&h->d_diag, DIAG_SLOTS * sizeof(double)));
     if (h->partials_cap < nblocks) {
@@ -697,11 +480,7 @@ extern "C" int clb_diagnostics(clb_lattice* h, int snapshot, clb_diag* out)
     }
     int rc = launch_moments(h);
     if (rc) return rc;
-    const Geo G = make_geo(d, h->pitch, h->plane);
-    diag_reduce_kernel<<<nblocks, RED_NT, 0, h->stream>>>(h->d_fields, h->d_snap, h->has_snap ? 1 : 0, G, h->d_partials);
-    CLB_HIP(hipGetLastError());
-    diag_final_kernel<<<1, RED_NT, 0, h->stream>>>(h->d_partials, nblocks, h->d_diag);
-    CLB_HIP(hipGetLastError());
+    CLB_HIP(enqueue_diag(h->d_fields, h->d_snap, h->has_snap ? 1 : 0, G, h->d_partials, h->d_diag, h->stream));
     double r[DIAG_SLOTS];
     CLB_HIP(hipMemcpyAsync(r, h->d_diag, sizeof r, hipMemcpyDeviceToHost, h->stream));
     if (snapshot) {
@@ -709,19 +488,7 @@ extern "C" int clb_diagnostics(clb_lattice* h, int snapshot, clb_diag* out)
     }
     CLB_HIP(hipStreamSynchronize(h->stream));
     if (snapshot) h->has_snap = true;
-    out->step = h->steps;
-    out->mass = r[0];
-    out->heat = r[1];
-    out->mom_x = r[2];
-    out->mom_y = r[3];
-    out->sum_w = r[4];
-    out->sum_w_ux_T = r[5];
-    out->sum_w_uy_T = r[6];
-    for (int i = 0; i < 4; ++i) out->wall_flux[i] = r[7 + i];
-    out->u_max = r[DIAG_SUMS + 0];
-    out->du_max = r[DIAG_SUMS + 1];
-    out->dT_max = r[DIAG_SUMS + 2];
-    out->nonfinite = r[DIAG_SUMS + 3] > 0.0 ? 1 : 0;
+    unpack_diag(r, h->steps, out);
     if (out->nonfinite) {
         set_error("non-finite density, velocity or temperature at step %lld", h->steps);
         return CLB_EDIVERGED;

@@ -1,0 +1,888 @@
+// clb_batch.hip -- many lattices of uneven size resident in one HBM pool, advanced together.
+//
+// Memory: one pool (allocated by the library or handed in, e.g. a torch tensor) is carved by a
+// first-fit free list into per-lattice regions: two population buffers (14 planes each, rows on
+// 256-byte boundaries) and an FP64 snapshot of (u_x, u_y, T) for the residual test.  Admission is
+// that allocation succeeding inside the budget.
+//
+// Device tables: one entry per slot (geometry, buffer offsets, current buffer, tile width, and the
+// lattice's parameters in the arithmetic type), and a tile list ordered by slot and, within a
+// lattice, row-major.  Every tile is 256 nodes: 64 x 4, 128 x 2 or 256 x 1, chosen per lattice
+// (the autotuner picks the width per size class).
+//
+// Step schedules, all running the same per-node update (node_update), so a lattice's result does
+// not depend on the schedule or on the other lattices:
+//   grouped     one launch per time step over every tile of every lattice, tiles handed to XCDs in
+//               contiguous bands (as in the single-lattice kernel);
+//   each        one launch per lattice per time step (the schedule a one-lattice-at-a-time caller
+//               would use);
+//   persistent  one cooperative launch for many steps: every workgroup owns a fixed contiguous
+//               range of the tile list and sweeps it once per step; before a tile of lattice L at
+//               step s it waits until all tiles of L have finished step s-1 (a per-lattice counter
+//               with agent-scope release/acquire).  Co-residency makes every wait finite; a spin
+//               limit bounds it anyway and turns an overrun into an error instead of a hang.
+#include "clb_internal.h"
+#include "clb_aux.h"
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+namespace clb {
+
+struct BatchLat {
+    Geo G;
+    long long off[2];   // element offsets of the two population buffers in the pool
+    int cur;            // buffer holding the current post-collision state
+    int tw_log2;        // tile width 1 << tw_log2 (6, 7 or 8); tile rows 256 >> tw_log2
+    int tiles_x, ntiles;
+};
+
+template <typename Real>
+struct BatchEntry {
+    BatchLat L;
+    Par<Real> P;
+};
+
+struct TileRef { int lat, tile; };
+
+constexpr int BNT = 256;
+
+template <typename Real, bool DEV, bool NT>
+__device__ __forceinline__ void batch_tile(Real* __restrict__ pool, const BatchEntry<Real>& E, int tile, int parity)
+{
+    const int tyi = tile / E.L.tiles_x, txi = tile - tyi * E.L.tiles_x;
+    const int x = (txi << E.L.tw_log2) + int(threadIdx.x & ((1u << E.L.tw_log2) - 1));
+    const int y = tyi * (BNT >> E.L.tw_log2) + int(threadIdx.x >> E.L.tw_log2);
+    if (x >= E.L.G.nx || y >= E.L.G.ny) return;
+    // select the buffers without indexing off[] by a runtime value (which would put the entry
+    // in private memory)
+    const bool c = (E.L.cur ^ parity) != 0;
+    const long long o_src = c ? E.L.off[1] : E.L.off[0];
+    const long long o_dst = c ? E.L.off[0] : E.L.off[1];
+    node_update<Real, DEV, NT>(pool + o_src, pool + o_dst, E.L.G, E.P, x, y);
+}
+
+template <typename Real, bool DEV, bool NT>
+__global__ __launch_bounds__(BNT) void batch_step_kernel(Real* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
+                                                       const TileRef* __restrict__ tiles, int tile_base, int ntiles,
+                                                       int parity)
+{
+    const int q = int(gridDim.x >> 3);
+    const int t = int(blockIdx.x & 7) * q + int(blockIdx.x >> 3);
+    if (t >= ntiles) return;
+    const TileRef r = tiles[tile_base + t];
+    const BatchEntry<Real> E = lats[r.lat];
+    batch_tile<Real, DEV, NT>(pool, E, r.tile, parity);
+}
+
+// Flip the current-buffer index of every listed slot (after an odd number of steps).
+template <typename Real>
+__global__ void batch_flip_kernel(BatchEntry<Real>* lats, const int* slots, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) lats[slots[i]].L.cur ^= 1;
+}
+
+__global__ void batch_zero_kernel(unsigned* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// sync[0 .. capacity): per-slot tiles finished (cumulative over this launch's steps);
+// sync[capacity]: failure flag.
+template <typename Real, bool DEV, bool NT>
+__global__ __launch_bounds__(BNT) void batch_persistent_kernel(Real* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
+                                                             const TileRef* __restrict__ tiles, int ntiles, int nsteps,
+                                                             unsigned* sync, int capacity, unsigned spin_limit)
+{
+    const int q = int(gridDim.x >> 3);
+    const int w = int(blockIdx.x & 7) * q + int(blockIdx.x >> 3);
+    const int G = int(gridDim.x);
+    const int lo = int((long long)ntiles * w / G), hi = int((long long)ntiles * (w + 1) / G);
+    unsigned* fail = sync + capacity;
+    __shared__ int s_stop;
+    for (int s = 0; s < nsteps; ++s) {
+        int waited_lat = -1;
+        for (int t = lo; t < hi; ++t) {
+            const TileRef r = tiles[t];
+            const BatchEntry<Real> E = lats[r.lat];
+            if (s > 0 && r.lat != waited_lat) {
+                if (threadIdx.x == 0) {
+                    const unsigned need = unsigned(s) * unsigned(E.L.ntiles);
+                    unsigned spins = 0;
+                    int stop = 0;
+                    while (__hip_atomic_load(sync + r.lat, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        if (__hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { stop = 1; break; }
+                        if (++spins > spin_limit) {
+                            __hip_atomic_fetch_or(fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            stop = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                    s_stop = stop;
+                }
+                __syncthreads();
+                if (s_stop) return;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                waited_lat = r.lat;
+            }
+            batch_tile<Real, DEV, NT>(pool, E, r.tile, s & 1);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (threadIdx.x == 0) __hip_atomic_fetch_add(sync + r.lat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+}  // namespace clb
+
+using namespace clb;
+
+// ---------------------------------------------------------------------------------------------
+// Host side.
+
+namespace {
+
+struct BatchSlot {
+    bool used = false;
+    clb_desc desc{};
+    Params par;
+    size_t alloc_off = 0, alloc_bytes = 0;   // byte range in the pool
+    long long off[2] = {0, 0};               // element offsets of the population buffers
+    size_t snap_off = 0;                     // byte offset of the FP64 snapshot (3 n doubles)
+    int pitch = 0;
+    long long plane = 0;
+    int cur = 0;
+    long long steps = 0;
+    bool has_snap = false;
+    int tw_log2 = 8;
+};
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+size_t slot_bytes(const clb_desc& d, int* pitch_out, long long* plane_out, size_t* buf_bytes_out)
+{
+    const size_t eb = elem_bytes(d.precision);
+    const int pitch = row_pitch(d.nx, eb);
+    const long long plane = (long long)pitch * d.ny;
+    const size_t buf = align_up(size_t(14) * plane * eb);
+    const size_t snap = align_up(size_t(3) * d.nx * d.ny * sizeof(double));
+    if (pitch_out) *pitch_out = pitch;
+    if (plane_out) *plane_out = plane;
+    if (buf_bytes_out) *buf_bytes_out = buf;
+    return 2 * buf + snap;
+}
+
+int default_tw_log2(int nx) { return nx <= 96 ? 6 : (nx <= 192 ? 7 : 8); }
+
+int size_class(const clb_desc& d)
+{
+    int c = 0;
+    while ((1 << c) < d.nx) ++c;
+    int e = 0;
+    while ((1 << e) < d.ny) ++e;
+    return c * 64 + e;
+}
+
+}  // namespace
+
+struct clb_batch {
+    int capacity = 0;
+    int precision = CLB_FP32_DEV;
+    size_t budget = 0;       // pool bytes available to lattices
+    size_t used_bytes = 0;
+    char* pool = nullptr;
+    bool own_pool = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<BatchSlot> slots;
+    std::map<size_t, size_t> free_list;   // byte offset -> length
+    void* d_lats = nullptr;
+    TileRef* d_tiles = nullptr;
+    size_t tiles_cap = 0;
+    std::vector<TileRef> tiles;
+    std::vector<int> first_tile, ntiles;
+    int* d_active = nullptr;              // slots in use (for the flip kernel)
+    int n_active = 0;
+    bool dirty = true;
+    unsigned* d_sync = nullptr;
+    double* d_fields = nullptr;
+    size_t fields_cap = 0;                // doubles
+    double* d_partials = nullptr;
+    int partials_cap = 0;
+    double* d_diag = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::map<int, int> tw_by_class;       // autotuned tile width (log2) per size class
+    int persistent_grid = 0;
+    bool nontemporal = false;
+};
+
+namespace {
+
+int alloc_range(clb_batch* b, size_t bytes, size_t* off)
+{
+    for (auto it = b->free_list.begin(); it != b->free_list.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t roff = it->first + bytes;
+            b->free_list.erase(it);
+            if (rest) b->free_list[roff] = rest;
+            b->used_bytes += bytes;
+            return CLB_OK;
+        }
+    }
+    return CLB_ENOMEM;
+}
+
+void free_range(clb_batch* b, size_t off, size_t bytes)
+{
+    b->used_bytes -= bytes;
+    auto it = b->free_list.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != b->free_list.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        b->free_list.erase(nx);
+    }
+    if (it != b->free_list.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            b->free_list.erase(it);
+        }
+    }
+}
+
+size_t entry_bytes(int precision) { return precision == CLB_FP32_DEV ? sizeof(BatchEntry<float>) : sizeof(BatchEntry<double>); }
+
+template <typename Real>
+BatchEntry<Real> make_entry(const BatchSlot& s, int tw_log2)
+{
+    BatchEntry<Real> E;
+    E.L.G = make_geo(s.desc, s.pitch, s.plane);
+    E.L.off[0] = s.off[0];
+    E.L.off[1] = s.off[1];
+    E.L.cur = s.cur;
+    E.L.tw_log2 = tw_log2;
+    const int tw = 1 << tw_log2, th = BNT >> tw_log2;
+    E.L.tiles_x = (s.desc.nx + tw - 1) / tw;
+    E.L.ntiles = E.L.tiles_x * ((s.desc.ny + th - 1) / th);
+    E.P = make_par<Real>(s.desc, s.par);
+    return E;
+}
+
+// Rebuild and upload the slot table and the tile list (stream-ordered).
+int upload_tables(clb_batch* b)
+{
+    const int cap = b->capacity;
+    std::vector<char> host(entry_bytes(b->precision) * cap, 0);
+    b->tiles.clear();
+    b->first_tile.assign(cap, 0);
+    b->ntiles.assign(cap, 0);
+    std::vector<int> active;
+    for (int i = 0; i < cap; ++i) {
+        BatchSlot& s = b->slots[i];
+        if (!s.used) continue;
+        active.push_back(i);
+        int nt;
+        if (b->precision == CLB_FP32_DEV) {
+            BatchEntry<float> E = make_entry<float>(s, s.tw_log2);
+            std::memcpy(host.data() + i * sizeof E, &E, sizeof E);
+            nt = E.L.ntiles;
+        } else {
+            BatchEntry<double> E = make_entry<double>(s, s.tw_log2);
+            std::memcpy(host.data() + i * sizeof E, &E, sizeof E);
+            nt = E.L.ntiles;
+        }
+        b->first_tile[i] = int(b->tiles.size());
+        b->ntiles[i] = nt;
+        for (int t = 0; t < nt; ++t) b->tiles.push_back(TileRef{i, t});
+    }
+    CLB_HIP(hipMemcpyAsync(b->d_lats, host.data(), host.size(), hipMemcpyHostToDevice, b->stream));
+    if (b->tiles.size() > b->tiles_cap) {
+        CLB_HIP(hipStreamSynchronize(b->stream));
+        (void)hipFree(b->d_tiles);
+        b->d_tiles = nullptr;
+        const size_t cap_t = std::max<size_t>(b->tiles.size() * 5 / 4, 1024);
+        CLB_HIP(hipMalloc((void**)&b->d_tiles, cap_t * sizeof(TileRef)));
+        b->tiles_cap = cap_t;
+    }
+    if (!b->tiles.empty())
+        CLB_HIP(hipMemcpyAsync(b->d_tiles, b->tiles.data(), b->tiles.size() * sizeof(TileRef), hipMemcpyHostToDevice, b->stream));
+    if (!active.empty())
+        CLB_HIP(hipMemcpyAsync(b->d_active, active.data(), active.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    b->n_active = int(active.size());
+    b->dirty = false;
+    return CLB_OK;
+}
+
+template <typename Real, bool DEV>
+hipError_t grouped_launch(clb_batch* b, int tile_base, int ntiles, int parity)
+{
+    const int q = (ntiles + 7) / 8;
+    if (b->nontemporal)
+        batch_step_kernel<Real, DEV, true><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
+            (Real*)b->pool, (const BatchEntry<Real>*)b->d_lats, b->d_tiles, tile_base, ntiles, parity);
+    else
+        batch_step_kernel<Real, DEV, false><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
+            (Real*)b->pool, (const BatchEntry<Real>*)b->d_lats, b->d_tiles, tile_base, ntiles, parity);
+    return hipGetLastError();
+}
+
+hipError_t grouped_any(clb_batch* b, int tile_base, int ntiles, int parity)
+{
+    if (ntiles <= 0) return hipSuccess;
+    switch (b->precision) {
+    case CLB_FP64: return grouped_launch<double, false>(b, tile_base, ntiles, parity);
+    case CLB_FP64_DEV: return grouped_launch<double, true>(b, tile_base, ntiles, parity);
+    default: return grouped_launch<float, true>(b, tile_base, ntiles, parity);
+    }
+}
+
+hipError_t flip_all(clb_batch* b)
+{
+    if (b->n_active == 0) return hipSuccess;
+    const int nb = (b->n_active + 255) / 256;
+    if (b->precision == CLB_FP32_DEV)
+        batch_flip_kernel<float><<<nb, 256, 0, b->stream>>>((BatchEntry<float>*)b->d_lats, b->d_active, b->n_active);
+    else
+        batch_flip_kernel<double><<<nb, 256, 0, b->stream>>>((BatchEntry<double>*)b->d_lats, b->d_active, b->n_active);
+    return hipGetLastError();
+}
+
+void advance_host(clb_batch* b, long long n)
+{
+    for (auto& s : b->slots)
+        if (s.used) {
+            s.steps += n;
+            if (n & 1) s.cur ^= 1;
+        }
+}
+
+template <typename Real, bool DEV, bool NT>
+int persistent_grid_for(clb_batch* b)
+{
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    CLB_HIP(hipGetDevice(&dev));
+    CLB_HIP(hipGetDeviceProperties(&prop, dev));
+    CLB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_persistent_kernel<Real, DEV, NT>, BNT, 0));
+    const int g = (prop.multiProcessorCount * std::max(per_cu, 1)) / 8 * 8;
+    return std::max(g, 8);
+}
+
+template <typename Real, bool DEV, bool NT>
+int persistent_launch(clb_batch* b, int nsteps)
+{
+    const int grid = persistent_grid_for<Real, DEV, NT>(b);
+    if (grid <= 0) return CLB_EDEVICE;
+    b->persistent_grid = grid;
+    const int nz = b->capacity + 1;
+    batch_zero_kernel<<<(nz + 255) / 256, 256, 0, b->stream>>>(b->d_sync, nz);
+    CLB_HIP(hipGetLastError());
+    Real* pool = (Real*)b->pool;
+    const BatchEntry<Real>* lats = (const BatchEntry<Real>*)b->d_lats;
+    const TileRef* tiles = b->d_tiles;
+    int ntiles = int(b->tiles.size());
+    unsigned* sync = b->d_sync;
+    int capacity = b->capacity;
+    unsigned spin_limit = 1u << 20;   // a wait this long (about a second) means something is wrong
+    void* args[] = {&pool, &lats, &tiles, &ntiles, &nsteps, &sync, &capacity, &spin_limit};
+    CLB_HIP(hipLaunchCooperativeKernel((const void*)batch_persistent_kernel<Real, DEV, NT>, dim3(grid), dim3(BNT), args, 0,
+                                       b->stream));
+    return CLB_OK;
+}
+
+int persistent_any(clb_batch* b, int nsteps)
+{
+    switch (b->precision) {
+    case CLB_FP64: return b->nontemporal ? persistent_launch<double, false, true>(b, nsteps) : persistent_launch<double, false, false>(b, nsteps);
+    case CLB_FP64_DEV: return b->nontemporal ? persistent_launch<double, true, true>(b, nsteps) : persistent_launch<double, true, false>(b, nsteps);
+    default: return b->nontemporal ? persistent_launch<float, true, true>(b, nsteps) : persistent_launch<float, true, false>(b, nsteps);
+    }
+}
+
+int check_slot(clb_batch* b, int slot)
+{
+    if (!b) { set_error("batch is NULL"); return CLB_EINVAL; }
+    if (slot < 0 || slot >= b->capacity || !b->slots[slot].used) { set_error("slot %d is not in use", slot); return CLB_EINVAL; }
+    return CLB_OK;
+}
+
+int ensure_fields(clb_batch* b, size_t doubles)
+{
+    if (b->fields_cap >= doubles) return CLB_OK;
+    CLB_HIP(hipStreamSynchronize(b->stream));
+    (void)hipFree(b->d_fields);
+    b->d_fields = nullptr;
+    CLB_HIP(hipMalloc((void**)&b->d_fields, doubles * sizeof(double)));
+    b->fields_cap = doubles;
+    return CLB_OK;
+}
+
+enum { MODE_GROUPED = 0, MODE_EACH = 1, MODE_PERSISTENT = 2 };
+
+int step_impl(clb_batch* b, int mode, long long n)
+{
+    if (n < 0) { set_error("negative step count"); return CLB_EINVAL; }
+    if (n == 0) return CLB_OK;
+    if (b->dirty) {
+        const int rc = upload_tables(b);
+        if (rc) return rc;
+    }
+    if (b->tiles.empty()) return CLB_OK;
+    if (mode == MODE_PERSISTENT) {
+        // counters count tiles finished over one launch; keep them far below 2^32
+        long long max_tiles = 1;
+        for (int i = 0; i < b->capacity; ++i) max_tiles = std::max<long long>(max_tiles, b->ntiles[i]);
+        const long long chunk = std::max<long long>(1, std::min<long long>(4096, (1LL << 30) / max_tiles));
+        long long done = 0;
+        while (done < n) {
+            const int k = int(std::min(chunk, n - done));
+            const int rc = persistent_any(b, k);
+            if (rc) return rc;
+            if (k & 1) CLB_HIP(flip_all(b));
+            advance_host(b, k);
+            done += k;
+        }
+        return CLB_OK;
+    }
+    for (long long s = 0; s < n; ++s) {
+        const int parity = int(s & 1);
+        if (mode == MODE_GROUPED) {
+            CLB_HIP(grouped_any(b, 0, int(b->tiles.size()), parity));
+        } else {
+            for (int i = 0; i < b->capacity; ++i)
+                if (b->slots[i].used) CLB_HIP(grouped_any(b, b->first_tile[i], b->ntiles[i], parity));
+        }
+    }
+    if (n & 1) CLB_HIP(flip_all(b));
+    advance_host(b, n);
+    return CLB_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// C ABI.
+
+extern "C" int clb_batch_footprint(const clb_desc* desc, size_t* bytes)
+{
+    clear_error();
+    if (!bytes) { set_error("NULL argument"); return CLB_EINVAL; }
+    const int rc = validate_desc(desc);
+    if (rc) return rc;
+    *bytes = slot_bytes(*desc, nullptr, nullptr, nullptr);
+    return CLB_OK;
+}
+
+extern "C" void clb_batch_destroy(clb_batch* b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->own_pool) (void)hipFree(b->pool);
+    (void)hipFree(b->d_lats);
+    (void)hipFree(b->d_tiles);
+    (void)hipFree(b->d_active);
+    (void)hipFree(b->d_sync);
+    (void)hipFree(b->d_fields);
+    (void)hipFree(b->d_partials);
+    (void)hipFree(b->d_diag);
+    if (b->ev[0]) (void)hipEventDestroy(b->ev[0]);
+    if (b->ev[1]) (void)hipEventDestroy(b->ev[1]);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+static int batch_create_impl(int capacity, int precision, size_t budget, void* pool, size_t pool_bytes, void* hip_stream,
+                             clb_batch* b)
+{
+    if (capacity <= 0 || capacity > (1 << 20)) { set_error("capacity must be in [1, 2^20]"); return CLB_EINVAL; }
+    if (precision != CLB_FP64 && precision != CLB_FP32_DEV && precision != CLB_FP64_DEV) {
+        set_error("unknown precision %d", precision);
+        return CLB_EINVAL;
+    }
+    b->capacity = capacity;
+    b->precision = precision;
+    b->slots.resize(capacity);
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        CLB_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        b->own_stream = true;
+    }
+    if (pool) {
+        if (pool_bytes < kAlign || (reinterpret_cast<uintptr_t>(pool) % kAlign) != 0) {
+            set_error("external pool must be 256-byte aligned and at least 256 bytes");
+            return CLB_EINVAL;
+        }
+        b->pool = (char*)pool;
+        b->budget = pool_bytes / kAlign * kAlign;
+    } else {
+        if (budget < kAlign) { set_error("budget must be at least 256 bytes"); return CLB_EINVAL; }
+        b->budget = budget / kAlign * kAlign;
+        if (hipMalloc((void**)&b->pool, b->budget) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("pool allocation of %zu bytes failed", b->budget);
+            return CLB_ENOMEM;
+        }
+        b->own_pool = true;
+    }
+    b->free_list[0] = b->budget;
+    CLB_HIP(hipMalloc(&b->d_lats, entry_bytes(precision) * capacity));
+    CLB_HIP(hipMemsetAsync(b->d_lats, 0, entry_bytes(precision) * capacity, b->stream));
+    CLB_HIP(hipMalloc((void**)&b->d_active, sizeof(int) * capacity));
+    CLB_HIP(hipMalloc((void**)&b->d_sync, sizeof(unsigned) * (capacity + 1)));
+    CLB_HIP(hipMemsetAsync(b->d_sync, 0, sizeof(unsigned) * (capacity + 1), b->stream));
+    CLB_HIP(hipMalloc((void**)&b->d_diag, DIAG_SLOTS * sizeof(double)));
+    CLB_HIP(hipEventCreate(&b->ev[0]));
+    CLB_HIP(hipEventCreate(&b->ev[1]));
+    b->nontemporal = precision != CLB_FP32_DEV;
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_create(int capacity, int precision, size_t hbm_budget_bytes, void* pool, size_t pool_bytes,
+                                void* hip_stream, clb_batch** out)
+{
+    clear_error();
+    if (!out) { set_error("out is NULL"); return CLB_EINVAL; }
+    *out = nullptr;
+    clb_batch* b = new (std::nothrow) clb_batch;
+    if (!b) { set_error("host allocation failed"); return CLB_ENOMEM; }
+    const int rc = batch_create_impl(capacity, precision, hbm_budget_bytes, pool, pool_bytes, hip_stream, b);
+    if (rc) {
+        clb_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, double tau_alpha, double g_beta,
+                             double Ma, int* slot)
+{
+    clear_error();
+    if (!b || !slot) { set_error("NULL argument"); return CLB_EINVAL; }
+    int rc = validate_desc(desc);
+    if (rc) return rc;
+    if (desc->precision != b->precision) { set_error("lattice precision differs from the batch's"); return CLB_EINVAL; }
+    rc = check_params(tau_nu, tau_alpha, g_beta, Ma);
+    if (rc) return rc;
+    int free_slot = -1;
+    for (int i = 0; i < b->capacity; ++i)
+        if (!b->slots[i].used) { free_slot = i; break; }
+    if (free_slot < 0) { set_error("batch is full (%d slots)", b->capacity); return CLB_ENOMEM; }
+    BatchSlot s;
+    size_t buf_bytes = 0;
+    const size_t bytes = slot_bytes(*desc, &s.pitch, &s.plane, &buf_bytes);
+    size_t off = 0;
+    if (alloc_range(b, bytes, &off) != CLB_OK) {
+        set_error("lattice needs %zu bytes; %zu of %zu bytes in use", bytes, b->used_bytes, b->budget);
+        return CLB_ENOMEM;
+    }
+    const size_t n = size_t(desc->nx) * desc->ny;
+    rc = ensure_fields(b, 4 * n);
+    if (rc) { free_range(b, off, bytes); return rc; }
+    const size_t eb = elem_bytes(desc->precision);
+    s.used = true;
+    s.desc = *desc;
+    s.par.tau_nu = tau_nu;
+    s.par.tau_alpha = tau_alpha;
+    s.par.g_beta = g_beta;
+    s.par.Ma = Ma;
+    s.alloc_off = off;
+    s.alloc_bytes = bytes;
+    s.off[0] = (long long)(off / eb);
+    s.off[1] = (long long)((off + buf_bytes) / eb);
+    s.snap_off = off + 2 * buf_bytes;
+    auto it = b->tw_by_class.find(size_class(*desc));
+    s.tw_log2 = it != b->tw_by_class.end() ? it->second : default_tw_log2(desc->nx);
+    b->slots[free_slot] = s;
+    b->dirty = true;
+    *slot = free_slot;
+    rc = clb_batch_init(b, free_slot, nullptr, nullptr, nullptr);
+    if (rc) {
+        b->slots[free_slot].used = false;
+        free_range(b, off, bytes);
+        return rc;
+    }
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_set_relaxation(clb_batch* b, int slot, double s_b, double s3, double s4, double lambda2)
+{
+    clear_error();
+    int rc = check_slot(b, slot);
+    if (rc) return rc;
+    const double v[4] = {s_b, s3, s4, lambda2};
+    for (double r : v)
+        if (!std::isfinite(r) || r <= 0.0 || r >= 2.0) { set_error("relaxation rates must lie in (0, 2)"); return CLB_EINVAL; }
+    Params& p = b->slots[slot].par;
+    p.s_b = s_b;
+    p.s3 = s3;
+    p.s4 = s4;
+    p.lam2 = lambda2;
+    b->dirty = true;
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_set_body_force(clb_batch* b, int slot, double Fvx, double Fvy)
+{
+    clear_error();
+    int rc = check_slot(b, slot);
+    if (rc) return rc;
+    if (!std::isfinite(Fvx) || !std::isfinite(Fvy)) { set_error("body force must be finite"); return CLB_EINVAL; }
+    b->slots[slot].par.Fvx = Fvx;
+    b->slots[slot].par.Fvy = Fvy;
+    b->dirty = true;
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_init(clb_batch* b, int slot, const double* rho, const double* u, const double* T)
+{
+    clear_error();
+    int rc = check_slot(b, slot);
+    if (rc) return rc;
+    BatchSlot& s = b->slots[slot];
+    const clb_desc& d = s.desc;
+    const size_t n = size_t(d.nx) * d.ny;
+    std::vector<double> host(4 * n);
+    for (size_t k = 0; k < n; ++k) {
+        host[k] = rho ? rho[k] : 1.0;
+        host[n + k] = u ? u[k] : 0.0;
+        host[2 * n + k] = u ? u[n + k] : 0.0;
+        host[3 * n + k] = T ? T[k] : d.T0;
+    }
+    for (size_t k = 0; k < 4 * n; ++k)
+        if (!std::isfinite(host[k]) || (k < n && host[k] <= 0.0)) {
+            set_error("initial fields must be finite with rho > 0");
+            return CLB_EINVAL;
+        }
+    rc = ensure_fields(b, 4 * n);
+    if (rc) return rc;
+    const size_t eb = elem_bytes(d.precision);
+    const size_t buf_bytes = size_t(s.off[1] - s.off[0]) * eb;
+    CLB_HIP(hipMemsetAsync(b->pool + s.off[0] * eb, 0, 2 * buf_bytes, b->stream));
+    CLB_HIP(hipMemcpyAsync(b->d_fields, host.data(), 4 * n * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    const Geo G = make_geo(d, s.pitch, s.plane);
+    CLB_HIP(enqueue_init(d, s.par, b->pool + s.off[0] * eb, G, b->d_fields, b->stream));
+    CLB_HIP(hipStreamSynchronize(b->stream));
+    s.cur = 0;
+    s.steps = 0;
+    s.has_snap = false;
+    b->dirty = true;
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_remove(clb_batch* b, int slot)
+{
+    clear_error();
+    int rc = check_slot(b, slot);
+    if (rc) return rc;
+    BatchSlot& s = b->slots[slot];
+    free_range(b, s.alloc_off, s.alloc_bytes);
+    s = BatchSlot();
+    b->dirty = true;
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_step(clb_batch* b, long long n)
+{
+    clear_error();
+    if (!b) { set_error("batch is NULL"); return CLB_EINVAL; }
+    return step_impl(b, MODE_GROUPED, n);
+}
+
+extern "C" int clb_batch_step_each(clb_batch* b, long long n)
+{
+    clear_error();
+    if (!b) { set_error("batch is NULL"); return CLB_EINVAL; }
+    return step_impl(b, MODE_EACH, n);
+}
+
+extern "C" int clb_batch_step_persistent(clb_batch* b, long long n)
+{
+    clear_error();
+    if (!b) { set_error("batch is NULL"); return CLB_EINVAL; }
+    return step_impl(b, MODE_PERSISTENT, n);
+}
+
+extern "C" int clb_batch_check(clb_batch* b)
+{
+    clear_error();
+    if (!b) { set_error("batch is NULL"); return CLB_EINVAL; }
+    unsigned flag = 0;
+    CLB_HIP(hipMemcpyAsync(&flag, b->d_sync + b->capacity, sizeof flag, hipMemcpyDeviceToHost, b->stream));
+    CLB_HIP(hipStreamSynchronize(b->stream));
+    if (flag) { set_error("a persistent launch gave up waiting for a lattice step (spin limit)"); return CLB_EDEVICE; }
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_time_steps(clb_batch* b, int mode, long long n, double* ms)
+{
+    clear_error();
+    if (!b || !ms) { set_error("NULL argument"); return CLB_EINVAL; }
+    if (mode < MODE_GROUPED || mode > MODE_PERSISTENT || n <= 0) { set_error("bad mode or step count"); return CLB_EINVAL; }
+    if (b->dirty) {
+        const int rc = upload_tables(b);
+        if (rc) return rc;
+    }
+    CLB_HIP(hipEventRecord(b->ev[0], b->stream));
+    const int rc = step_impl(b, mode, n);
+    if (rc) return rc;
+    CLB_HIP(hipEventRecord(b->ev[1], b->stream));
+    CLB_HIP(hipEventSynchronize(b->ev[1]));
+    float t = 0.0f;
+    CLB_HIP(hipEventElapsedTime(&t, b->ev[0], b->ev[1]));
+    *ms = t;
+    return mode == MODE_PERSISTENT ? clb_batch_check(b) : CLB_OK;
+}
+
+extern "C" int clb_batch_synchronize(clb_batch* b)
+{
+    clear_error();
+    if (!b) { set_error("batch is NULL"); return CLB_EINVAL; }
+    CLB_HIP(hipStreamSynchronize(b->stream));
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_info(clb_batch* b, int* count, size_t* used_bytes, size_t* budget_bytes, long long* sites)
+{
+    clear_error();
+    if (!b) { set_error("batch is NULL"); return CLB_EINVAL; }
+    int c = 0;
+    long long ns = 0;
+    for (auto& s : b->slots)
+        if (s.used) {
+            ++c;
+            ns += (long long)s.desc.nx * s.desc.ny;
+        }
+    if (count) *count = c;
+    if (used_bytes) *used_bytes = b->used_bytes;
+    if (budget_bytes) *budget_bytes = b->budget;
+    if (sites) *sites = ns;
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_moments(clb_batch* b, int slot, double* rho, double* u, double* T)
+{
+    clear_error();
+    int rc = check_slot(b, slot);
+    if (rc) return rc;
+    BatchSlot& s = b->slots[slot];
+    const clb_desc& d = s.desc;
+    const size_t n = size_t(d.nx) * d.ny;
+    rc = ensure_fields(b, 4 * n);
+    if (rc) return rc;
+    const size_t eb = elem_bytes(d.precision);
+    const Geo G = make_geo(d, s.pitch, s.plane);
+    CLB_HIP(enqueue_moments(d, s.par, b->pool + s.off[s.cur] * eb, G, b->d_fields, b->stream));
+    if (rho) CLB_HIP(hipMemcpyAsync(rho, b->d_fields, n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    if (u) CLB_HIP(hipMemcpyAsync(u, b->d_fields + n, 2 * n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    if (T) CLB_HIP(hipMemcpyAsync(T, b->d_fields + 3 * n, n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    CLB_HIP(hipStreamSynchronize(b->stream));
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_diagnostics(clb_batch* b, int slot, int snapshot, clb_diag* out)
+{
+    clear_error();
+    int rc = check_slot(b, slot);
+    if (rc) return rc;
+    if (!out) { set_error("NULL argument"); return CLB_EINVAL; }
+    BatchSlot& s = b->slots[slot];
+    const clb_desc& d = s.desc;
+    const size_t n = size_t(d.nx) * d.ny;
+    rc = ensure_fields(b, 4 * n);
+    if (rc) return rc;
+    const Geo G = make_geo(d, s.pitch, s.plane);
+    const int nb = diag_blocks(G);
+    if (b->partials_cap < nb) {
+        CLB_HIP(hipStreamSynchronize(b->stream));
+        (void)hipFree(b->d_partials);
+        b->d_partials = nullptr;
+        CLB_HIP(hipMalloc((void**)&b->d_partials, size_t(nb) * DIAG_SLOTS * sizeof(double)));
+        b->partials_cap = nb;
+    }
+    const size_t eb = elem_bytes(d.precision);
+    double* snap = (double*)(b->pool + s.snap_off);
+    CLB_HIP(enqueue_moments(d, s.par, b->pool + s.off[s.cur] * eb, G, b->d_fields, b->stream));
+    CLB_HIP(enqueue_diag(b->d_fields, snap, s.has_snap ? 1 : 0, G, b->d_partials, b->d_diag, b->stream));
+    double r[DIAG_SLOTS];
+    CLB_HIP(hipMemcpyAsync(r, b->d_diag, sizeof r, hipMemcpyDeviceToHost, b->stream));
+    if (snapshot) CLB_HIP(hipMemcpyAsync(snap, b->d_fields + n, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, b->stream));
+    CLB_HIP(hipStreamSynchronize(b->stream));
+    if (snapshot) s.has_snap = true;
+    unpack_diag(r, s.steps, out);
+    if (out->nonfinite) {
+        set_error("slot %d: non-finite density, velocity or temperature at step %lld", slot, s.steps);
+        return CLB_EDIVERGED;
+    }
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_set_tile_width(clb_batch* b, int slot, int tile_width)
+{
+    clear_error();
+    int rc = check_slot(b, slot);
+    if (rc) return rc;
+    const int lg = tile_width == 64 ? 6 : tile_width == 128 ? 7 : tile_width == 256 ? 8 : -1;
+    if (lg < 0) { set_error("tile width must be 64, 128 or 256"); return CLB_EINVAL; }
+    b->slots[slot].tw_log2 = lg;
+    b->dirty = true;
+    return CLB_OK;
+}
+
+// For every size class present, time the grouped step over that class's lattices with each tile
+// width (state unchanged: reads the current buffers, writes the spare ones) and keep the fastest.
+extern "C" int clb_batch_autotune(clb_batch* b, int launches)
+{
+    clear_error();
+    if (!b || launches <= 0) { set_error("bad arguments"); return CLB_EINVAL; }
+    std::map<int, std::vector<int>> classes;
+    for (int i = 0; i < b->capacity; ++i)
+        if (b->slots[i].used) classes[size_class(b->slots[i].desc)].push_back(i);
+    for (auto& kv : classes) {
+        int best = -1;
+        double best_t = 0.0;
+        for (int lg = 6; lg <= 8; ++lg) {
+            std::vector<bool> keep(b->capacity, false);
+            for (int i : kv.second) keep[i] = true;
+            // restrict the tables to this class with width lg
+            std::vector<int> saved_tw(b->capacity);
+            std::vector<char> saved_used(b->capacity);
+            for (int i = 0; i < b->capacity; ++i) {
+                saved_tw[i] = b->slots[i].tw_log2;
+                saved_used[i] = b->slots[i].used;
+                if (b->slots[i].used && !keep[i]) b->slots[i].used = false;
+                if (keep[i]) b->slots[i].tw_log2 = lg;
+            }
+            int rc = upload_tables(b);
+            for (int i = 0; i < b->capacity; ++i) {
+                b->slots[i].used = saved_used[i] != 0;
+                b->slots[i].tw_log2 = saved_tw[i];
+            }
+            if (rc) { b->dirty = true; return rc; }
+            const int nt = int(b->tiles.size());
+            for (int w = 0; w < 2; ++w) CLB_HIP(grouped_any(b, 0, nt, 0));
+            CLB_HIP(hipEventRecord(b->ev[0], b->stream));
+            for (int r = 0; r < launches; ++r) CLB_HIP(grouped_any(b, 0, nt, 0));
+            CLB_HIP(hipEventRecord(b->ev[1], b->stream));
+            CLB_HIP(hipEventSynchronize(b->ev[1]));
+            float ms = 0.0f;
+            CLB_HIP(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+            if (best < 0 || ms < best_t) { best = lg; best_t = ms; }
+        }
+        b->tw_by_class[kv.first] = best;
+        for (int i : kv.second) b->slots[i].tw_log2 = best;
+    }
+    b->dirty = true;
+    return upload_tables(b);
+}

@@ -46,6 +46,9 @@ struct Params {
 
 Geo make_geo(const clb_desc& d, int pitch, long long plane);
 
+// CLB_OK, or CLB_EINVAL with a message, for relaxation times / buoyancy / Mach number.
+int check_params(double tau_nu, double tau_alpha, double g_beta, double Ma);
+
 template <typename Real>
 Par<Real> make_par(const clb_desc& d, const Params& p)
 {

@@ -69,3 +69,21 @@ def test_null_arguments():
     clb._lib.clb_destroy(None)   # NULL-safe
     assert clb._lib.clb_step(None, 1) == clb.CLB_EINVAL
     assert clb._lib.clb_moments(None, None, None, None) == clb.CLB_EINVAL
+
+
+def test_batch_footprint_and_host_side_rejections():
+    """Pool bytes per lattice: two 14-plane population buffers with 256-byte rows plus an FP64
+    (u_x, u_y, T) snapshot; bad batch arguments are rejected before any device call."""
+    from paper_1710_10569_amd import clb
+    fp = clb.footprint(100, 60, "fp32")
+    pitch = 128                                  # 100 floats rounded up to 64-float rows
+    buf = -(-14 * pitch * 60 * 4 // 256) * 256
+    snap = -(-3 * 100 * 60 * 8 // 256) * 256
+    assert fp == 2 * buf + snap
+    assert clb.footprint(100, 60, "fp64") > fp
+    h = ctypes.c_void_p()
+    assert clb._lib.clb_batch_create(0, clb.CLB_FP32_DEV, 1 << 20, None, 0, None, ctypes.byref(h)) == clb.CLB_EINVAL
+    assert clb._lib.clb_batch_create(4, 9, 1 << 20, None, 0, None, ctypes.byref(h)) == clb.CLB_EINVAL
+    assert clb._lib.clb_batch_create(4, clb.CLB_FP32_DEV, 1 << 20, None, 0, None, None) == clb.CLB_EINVAL
+    clb._lib.clb_batch_destroy(None)
+    assert clb._lib.clb_batch_step(None, 1) == clb.CLB_EINVAL

@@ -1,0 +1,160 @@
+"""GPU tests of the batched path: many lattices of uneven size in one pool, advanced by the grouped
+(one launch per step), per-lattice (one launch per lattice per step) and persistent (one
+cooperative launch) schedules.  Each lattice's result must be bitwise the one it gets alone
+through the single-lattice API, whatever the schedule and whatever else is resident."""
+import numpy as np
+import pytest
+
+from paper_1710_10569_amd import workloads as W
+from tests.helpers import field_errors, oracle_from_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _clb():
+    from paper_1710_10569_amd import clb
+    return clb
+
+
+def mixed_workloads():
+    return [
+        W.cavity(64, Ra=1e4),
+        W.random_walled(100, 37, seed=1, wall_u=0.02, g_beta=2e-3),
+        W.random_walled(45, 130, seed=2, kinds=("periodic", "periodic", "dirichlet", "adiabatic")),
+        W.random_periodic(70, 33, seed=3, T0=0.2),
+        W.cavity(96, Ra=1e5, seed=9),
+        W.rayleigh_benard(300, 41, Ra=1e4, seed=5),
+    ]
+
+
+def alone(w, precision, steps):
+    clb = _clb()
+    g = clb.lattice_from_workload(w, precision)
+    g.step(steps)
+    m = g.moments()
+    g.close()
+    return m
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["grouped", "each", "persistent"])
+def test_batch_equals_alone(gpu, precision, mode):
+    clb = _clb()
+    ws = mixed_workloads()
+    b = clb.Batch(16, precision, budget_bytes=256 << 20)
+    slots = [b.add_workload(w) for w in ws]
+    print(f"[batch] {precision} {mode} slots={slots}", flush=True)
+    b.step(37, mode)
+    b.step(20, mode)
+    if mode == "persistent":
+        b.check()
+    for w, s in zip(ws, slots):
+        got = b.moments(s)
+        ref = alone(w, precision, 57)
+        for a, r in zip(got, ref):
+            assert np.array_equal(a, r), (w["name"], mode)
+        assert b.diagnostics(s)["step"] == 57
+    b.close()
+
+
+def test_batch_fp64_matches_oracle(gpu):
+    clb = _clb()
+    ws = mixed_workloads()[:3]
+    b = clb.Batch(4, "fp64", budget_bytes=64 << 20)
+    slots = [b.add_workload(w) for w in ws]
+    b.step(120, "persistent")
+    b.check()
+    for w, s in zip(ws, slots):
+        o = oracle_from_workload(w)
+        o.step(120)
+        e = field_errors(b.moments(s), o.moments(), w["T0"], w["u_scale"])
+        assert max(e.values()) < 1e-12, (w["name"], e)
+
+
+def test_admission_by_footprint_and_slot_reuse(gpu):
+    """The pool holds exactly two 128 x 128 FP32 lattices: a third is refused (CLB_ENOMEM); after a
+    removal it fits.  The lattice that stayed resident is unaffected by the others coming and
+    going: bitwise equal to its run alone."""
+    clb = _clb()
+    fp = clb.footprint(128, 128, "fp32")
+    b = clb.Batch(8, "fp32", budget_bytes=2 * fp)
+    w1, w2, w3 = W.cavity(128, Ra=1e5, seed=1), W.cavity(128, Ra=3e4, seed=2), W.cavity(128, Ra=1e3, seed=3)
+    s1, s2 = b.add_workload(w1), b.add_workload(w2)
+    assert s1 is not None and s2 is not None
+    assert b.add_workload(w3) is None
+    assert b.info()["used_bytes"] == 2 * fp
+    b.step(50)
+    b.remove(s2)
+    s3 = b.add_workload(w3)
+    assert s3 is not None
+    b.step(50)
+    got = b.moments(s1)
+    ref = alone(w1, "fp32", 100)
+    for a, r in zip(got, ref):
+        assert np.array_equal(a, r)
+    assert b.diagnostics(s3)["step"] == 50
+    b.close()
+
+
+def test_external_torch_pool(gpu):
+    import torch
+    clb = _clb()
+    w = W.random_walled(80, 60, seed=7, wall_u=0.01)
+    pool = torch.empty(clb.footprint(80, 60, "fp32") * 3, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    b = clb.Batch(4, "fp32", pool=pool, stream=stream.cuda_stream)
+    s = b.add_workload(w)
+    b.step(33)
+    got = b.moments(s)
+    ref = alone(w, "fp32", 33)
+    for a, r in zip(got, ref):
+        assert np.array_equal(a, r)
+    b.close()
+
+
+def test_batch_autotune_keeps_state(gpu):
+    clb = _clb()
+    ws = mixed_workloads()
+    b1 = clb.Batch(8, "fp32", budget_bytes=128 << 20)
+    b2 = clb.Batch(8, "fp32", budget_bytes=128 << 20)
+    s1 = [b1.add_workload(w) for w in ws]
+    s2 = [b2.add_workload(w) for w in ws]
+    b1.step(11)
+    b2.step(11)
+    b1.autotune(3)
+    b1.step(11)
+    b2.step(11)
+    for a, c in zip(s1, s2):
+        for x, y in zip(b1.moments(a), b2.moments(c)):
+            assert np.array_equal(x, y)
+
+
+def test_persistent_long_run_matches_grouped(gpu):
+    """More steps than one persistent launch covers (chunks of 4096 steps), odd total."""
+    clb = _clb()
+    ws = [W.cavity(64, Ra=10 ** (3 + i / 3), seed=i) for i in range(6)]
+    bp = clb.Batch(8, "fp32", budget_bytes=64 << 20)
+    bg = clb.Batch(8, "fp32", budget_bytes=64 << 20)
+    sp = [bp.add_workload(w) for w in ws]
+    sg = [bg.add_workload(w) for w in ws]
+    bp.step(4101, "persistent")
+    bp.check()
+    bg.step(4101, "grouped")
+    for a, c in zip(sp, sg):
+        for x, y in zip(bp.moments(a), bg.moments(c)):
+            assert np.array_equal(x, y)
+
+
+def test_batch_residual_snapshot(gpu):
+    clb = _clb()
+    b = clb.Batch(4, "fp32", budget_bytes=32 << 20)
+    s = b.add_workload(W.cavity(64, Ra=1e5))
+    b.step(100)
+    _, ux0, uy0, T0 = b.moments(s)
+    d0 = b.diagnostics(s, snapshot=True)
+    assert d0["du_max"] == -1.0
+    b.step(100)
+    _, ux1, uy1, T1 = b.moments(s)
+    d = b.diagnostics(s)
+    assert d["du_max"] == pytest.approx(max(np.abs(ux1 - ux0).max(), np.abs(uy1 - uy0).max()), rel=1e-14)
+    assert d["dT_max"] == pytest.approx(np.abs(T1 - T0).max(), rel=1e-14)
