@@ -128,6 +128,53 @@ def cpu_baseline(W, budget_s=15.0):
             "sample": f"{n} steps of the 2048x1024 Rayleigh-Benard lattice ({sites * n:.3g} site updates), FP64"}
 
 
+def run_batch(clb, W, steps, stream, log_each=True):
+    """The 512 batched cavities (sides from {64, 96, ..., 512}, Ra log-uniform in [1e3, 1e6], seed 7),
+    FP32, in one pool: autotuned tile widths, then the grouped (one launch per step), persistent (one
+    cooperative launch) and one-launch-per-cavity schedules timed over the same number of steps."""
+    import torch
+    specs = W.batch_cavity_specs()
+    total = sum(L * L for L, _, _ in specs)
+    budget = sum(clb.footprint(L, L, "fp32") for L, _, _ in specs) + (64 << 20)
+    b = clb.Batch(len(specs), "fp32", budget_bytes=budget, stream=stream)
+    t0 = time.perf_counter()
+    for L, Ra, seed in specs:
+        if b.add_workload(W.cavity(L, Ra=Ra, seed=seed)) is None:
+            raise RuntimeError("batch pool too small")
+    log(f"[bench] batch: {len(specs)} cavities, {total:.4g} nodes, pool {budget / 1e9:.2f} GB, "
+        f"set up in {time.perf_counter() - t0:.1f} s")
+    b.step(20)
+    b.autotune(3)
+    torch.cuda.synchronize()
+    out = {"cavities": len(specs), "sites": total, "steps": steps, "pool_GB": budget / 1e9}
+    for mode in ("grouped", "persistent", "each"):
+        n = steps if mode != "each" else max(10, steps // 10)
+        b.step(2, mode)
+        ms = b.time_steps(n, mode)
+        mlups = total * n / (ms * 1e-3) / 1e6
+        out[mode] = {"MLUPS": mlups, "ms_per_step": ms / n, "steps_timed": n,
+                     "achieved_GBps": 112 * total * n / (ms * 1e-3) / 1e9}
+        log(f"[bench] batch {mode}: {ms / n:.3f} ms/step, {mlups:.0f} MLUPS")
+    b.close()
+    return out
+
+
+def run_serving(clb, W, stream, n=40, lam=4.0, L_range=(32, 256), tol=1e-8, step_cap=400_000):
+    """A Poisson stream of cavity requests served with continuous batching (serving.py)."""
+    from paper_1710_10569_amd import serving as S
+    specs = W.serving_requests(n=n, lam=lam, L_range=L_range)
+    reqs = S.requests_from(specs)
+    srv = S.CavityServer(budget_bytes=8 << 30, capacity=256, chunk=1000, tol=tol, step_cap=step_cap,
+                         schedule="persistent", stream=stream)
+    out = srv.run(reqs)
+    summ = S.summarize(out, srv.wall, srv.site_updates)
+    srv.close()
+    summ.update({"lambda_per_s": lam, "L_range": list(L_range), "Ra_range": [1e3, 1e6], "tol": tol,
+                 "step_cap": step_cap, "chunk": 1000})
+    log(f"[bench] serving: {summ}")
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +184,9 @@ def main():
     ap.add_argument("--no-control", action="store_true", help="skip the 8192x4096 control lattice")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
     ap.add_argument("--no-copy", action="store_true", help="skip the plain-copy bandwidth reference")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-cavity batch")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference kernel for "
                          "scaling hardware byte counters) and exit")
@@ -214,6 +264,12 @@ def main():
         latc.close()
         result["control_8192x4096"] = {"value": rc["mlups"], "unit": "MLUPS", "achieved_GBps": rc["gbps"],
                                        "frac": rc["gbps"] / HBM_PEAK_GBPS, "footprint_GB": 2 * 14 * 4 * 8192 * 4096 / 1e9}
+        torch.cuda.empty_cache()
+    if not args.no_batch:
+        result["batched_512_cavities"] = run_batch(clb, W, args.batch_steps, stream.cuda_stream)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        result["served"] = run_serving(clb, W, stream.cuda_stream)
         torch.cuda.empty_cache()
     if not args.no_copy:
         cb = copy_bandwidth(torch)

@@ -235,6 +235,14 @@ int clb_batch_init(clb_batch* b, int slot, const double* rho, const double* u, c
 int clb_batch_moments(clb_batch* b, int slot, double* rho, double* u, double* T);
 int clb_batch_diagnostics(clb_batch* b, int slot, int snapshot, clb_diag* out);
 
+/* Residual of every resident lattice in one pass: for each slot, the max-norm change of
+ * (u_x, u_y) and of T since the slot's last snapshot, then the snapshot is replaced by the current
+ * fields.  A slot's snapshot starts as its initial fields (clb_batch_add / clb_batch_init), so
+ * calling this every k steps measures the change per k steps.  Arrays have `capacity` entries
+ * indexed by slot; unused slots get -1 and 0.  nonfinite[i] = 1 if lattice i holds a NaN or
+ * infinity in rho, u or T.  Any output may be NULL.  Synchronises. */
+int clb_batch_residuals(clb_batch* b, double* du, double* dT, int* nonfinite);
+
 /* Release a slot and its pool region (stream-ordered after the work already enqueued). */
 int clb_batch_remove(clb_batch* b, int slot);
 

@@ -299,6 +299,7 @@ _sig("clb_batch_autotune", ctypes.c_int, [_B, ctypes.c_int])
 _sig("clb_batch_info", ctypes.c_int, [_B, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t),
                                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_longlong)])
 _sig("clb_batch_synchronize", ctypes.c_int, [_B])
+_sig("clb_batch_residuals", ctypes.c_int, [_B, _dp, _dp, ctypes.POINTER(ctypes.c_int)])
 _sig("clb_batch_destroy", None, [_B])
 
 MODES = {"grouped": 0, "each": 1, "persistent": 2}
@@ -331,6 +332,7 @@ class Batch:
                                        None if stream is None else _vp(int(stream)), ctypes.byref(h))
         _check(rc)
         self._h = h
+        self._capacity = int(capacity)
         self.shapes = {}
 
     def close(self):
@@ -431,6 +433,15 @@ class Batch:
         _check(_lib.clb_batch_moments(self._h, int(slot), _ptr(rho), _ptr(u), _ptr(T)))
         s = (ny, nx)
         return rho.reshape(s), u[:n].reshape(s), u[n:].reshape(s), T.reshape(s)
+
+    def residuals(self):
+        """{slot: (du, dT, nonfinite)} for every resident lattice: the max-norm change of u and of T
+        since the previous call (or since initialisation); snapshots are then updated."""
+        cap = self._capacity
+        du, dT = np.empty(cap), np.empty(cap)
+        nf = (ctypes.c_int * cap)()
+        _check(_lib.clb_batch_residuals(self._h, _ptr(du), _ptr(dT), nf))
+        return {s: (float(du[s]), float(dT[s]), bool(nf[s])) for s in self.shapes}
 
     def diagnostics(self, slot, snapshot=False, raise_on_diverged=True):
         d = clb_diag()

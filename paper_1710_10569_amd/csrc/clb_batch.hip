@@ -36,6 +36,7 @@ namespace clb {
 struct BatchLat {
     Geo G;
     long long off[2];   // element offsets of the two population buffers in the pool
+    long long snap;     // byte offset of the FP64 (u_x, u_y, T) snapshot in the pool
     int cur;            // buffer holding the current post-collision state
     int tw_log2;        // tile width 1 << tw_log2 (6, 7 or 8); tile rows 256 >> tw_log2
     int tiles_x, ntiles;
@@ -140,6 +141,65 @@ __global__ __launch_bounds__(BNT) void batch_persistent_kernel(Real* __restrict_
     }
 }
 
+// Residual of every resident lattice in one launch: at each node the moments of the current step
+// (pull, wall step, macroscopic, as in clb_moments) are compared with the lattice's FP64 snapshot,
+// which is then overwritten; per lattice the maxima of |u_x - u_x'|, |u_y - u_y'| (together),
+// |T - T'| and a non-finite flag are combined with atomic max on their IEEE bit patterns (all
+// values are non-negative, so the integer order is the numeric order and the result does not
+// depend on the order of the updates).
+template <typename Real, bool DEV>
+__global__ __launch_bounds__(BNT) void batch_residual_kernel(Real* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
+                                                           const TileRef* __restrict__ tiles, int ntiles,
+                                                           unsigned long long* __restrict__ res)
+{
+    const int q = int(gridDim.x >> 3);
+    const int t = int(blockIdx.x & 7) * q + int(blockIdx.x >> 3);
+    if (t >= ntiles) return;   // uniform over the workgroup
+    const TileRef r = tiles[t];
+    const BatchEntry<Real> E = lats[r.lat];
+    const int tyi = r.tile / E.L.tiles_x, txi = r.tile - tyi * E.L.tiles_x;
+    const int x = (txi << E.L.tw_log2) + int(threadIdx.x & ((1u << E.L.tw_log2) - 1));
+    const int y = tyi * (BNT >> E.L.tw_log2) + int(threadIdx.x >> E.L.tw_log2);
+    double du = 0.0, dT = 0.0, bad = 0.0;
+    if (x < E.L.G.nx && y < E.L.G.ny) {
+        const Real* src = pool + (E.L.cur ? E.L.off[1] : E.L.off[0]);
+        Real f[9], g[5];
+        pull(src, E.L.G, x, y, f, g);
+        if (on_wall(E.L.G, x, y)) wall_step<Real, DEV>(src, E.L.G, E.P, x, y, f, g);
+        const Macro<Real, DEV> m = macro<Real, DEV>(f, g, E.P);
+        const double ux = double(m.ux), uy = double(m.uy), T = double(E.P.TR) + double(m.dT);
+        double* snap = reinterpret_cast<double*>(reinterpret_cast<char*>(pool) + E.L.snap);
+        const long long n = (long long)E.L.G.nx * E.L.G.ny, k = (long long)y * E.L.G.nx + x;
+        du = fmax(fabs(ux - snap[k]), fabs(uy - snap[n + k]));
+        dT = fabs(T - snap[2 * n + k]);
+        bad = (__builtin_isfinite(double(m.rho)) && __builtin_isfinite(ux) && __builtin_isfinite(uy) &&
+               __builtin_isfinite(T)) ? 0.0 : 1.0;
+        snap[k] = ux;
+        snap[n + k] = uy;
+        snap[2 * n + k] = T;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        du = fmax(du, __shfl_xor(du, o, 64));
+        dT = fmax(dT, __shfl_xor(dT, o, 64));
+        bad = fmax(bad, __shfl_xor(bad, o, 64));
+    }
+    __shared__ double red[BNT / 64][3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { red[wave][0] = du; red[wave][1] = dT; red[wave][2] = bad; }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double v = red[0][threadIdx.x];
+        for (int w = 1; w < BNT / 64; ++w) v = fmax(v, red[w][threadIdx.x]);
+        atomicMax(res + 3 * r.lat + threadIdx.x, (unsigned long long)__double_as_longlong(v));
+    }
+}
+
+__global__ void batch_zero64_kernel(unsigned long long* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 }  // namespace clb
 
 using namespace clb;
@@ -218,6 +278,7 @@ struct clb_batch {
     double* d_partials = nullptr;
     int partials_cap = 0;
     double* d_diag = nullptr;
+    unsigned long long* d_res = nullptr;  // 3 per slot: residual of u, of T, non-finite flag
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::map<int, int> tw_by_class;       // autotuned tile width (log2) per size class
     int persistent_grid = 0;
@@ -269,6 +330,7 @@ BatchEntry<Real> make_entry(const BatchSlot& s, int tw_log2)
     E.L.G = make_geo(s.desc, s.pitch, s.plane);
     E.L.off[0] = s.off[0];
     E.L.off[1] = s.off[1];
+    E.L.snap = (long long)s.snap_off;
     E.L.cur = s.cur;
     E.L.tw_log2 = tw_log2;
     const int tw = 1 << tw_log2, th = BNT >> tw_log2;
@@ -495,6 +557,7 @@ extern "C" void clb_batch_destroy(clb_batch* b)
     (void)hipFree(b->d_fields);
     (void)hipFree(b->d_partials);
     (void)hipFree(b->d_diag);
+    (void)hipFree(b->d_res);
     if (b->ev[0]) (void)hipEventDestroy(b->ev[0]);
     if (b->ev[1]) (void)hipEventDestroy(b->ev[1]);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -542,6 +605,7 @@ static int batch_create_impl(int capacity, int precision, size_t budget, void* p
     CLB_HIP(hipMalloc((void**)&b->d_sync, sizeof(unsigned) * (capacity + 1)));
     CLB_HIP(hipMemsetAsync(b->d_sync, 0, sizeof(unsigned) * (capacity + 1), b->stream));
     CLB_HIP(hipMalloc((void**)&b->d_diag, DIAG_SLOTS * sizeof(double)));
+    CLB_HIP(hipMalloc((void**)&b->d_res, sizeof(unsigned long long) * 3 * capacity));
     CLB_HIP(hipEventCreate(&b->ev[0]));
     CLB_HIP(hipEventCreate(&b->ev[1]));
     b->nontemporal = precision != CLB_FP32_DEV;
@@ -673,10 +737,14 @@ extern "C" int clb_batch_init(clb_batch* b, int slot, const double* rho, const d
     CLB_HIP(hipMemcpyAsync(b->d_fields, host.data(), 4 * n * sizeof(double), hipMemcpyHostToDevice, b->stream));
     const Geo G = make_geo(d, s.pitch, s.plane);
     CLB_HIP(enqueue_init(d, s.par, b->pool + s.off[0] * eb, G, b->d_fields, b->stream));
+    // the snapshot starts as the initial (u_x, u_y, T), so the first residual measures the first chunk
+    CLB_HIP(enqueue_moments(d, s.par, b->pool + s.off[0] * eb, G, b->d_fields, b->stream));
+    CLB_HIP(hipMemcpyAsync(b->pool + s.snap_off, b->d_fields + n, 3 * n * sizeof(double), hipMemcpyDeviceToDevice,
+                           b->stream));
     CLB_HIP(hipStreamSynchronize(b->stream));
     s.cur = 0;
     s.steps = 0;
-    s.has_snap = false;
+    s.has_snap = true;
     b->dirty = true;
     return CLB_OK;
 }
@@ -885,4 +953,46 @@ extern "C" int clb_batch_autotune(clb_batch* b, int launches)
     }
     b->dirty = true;
     return upload_tables(b);
+}
+
+template <typename Real, bool DEV>
+static hipError_t residual_launch(clb_batch* b)
+{
+    const int nt = int(b->tiles.size());
+    const int q = (nt + 7) / 8;
+    batch_residual_kernel<Real, DEV><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
+        (Real*)b->pool, (const BatchEntry<Real>*)b->d_lats, b->d_tiles, nt, b->d_res);
+    return hipGetLastError();
+}
+
+extern "C" int clb_batch_residuals(clb_batch* b, double* du, double* dT, int* nonfinite)
+{
+    clear_error();
+    if (!b) { set_error("batch is NULL"); return CLB_EINVAL; }
+    if (b->dirty) {
+        const int rc = upload_tables(b);
+        if (rc) return rc;
+    }
+    const int n3 = 3 * b->capacity;
+    batch_zero64_kernel<<<(n3 + 255) / 256, 256, 0, b->stream>>>(b->d_res, n3);
+    CLB_HIP(hipGetLastError());
+    if (!b->tiles.empty()) {
+        switch (b->precision) {
+        case CLB_FP64: CLB_HIP((residual_launch<double, false>(b))); break;
+        case CLB_FP64_DEV: CLB_HIP((residual_launch<double, true>(b))); break;
+        default: CLB_HIP((residual_launch<float, true>(b))); break;
+        }
+    }
+    std::vector<unsigned long long> host(n3);
+    CLB_HIP(hipMemcpyAsync(host.data(), b->d_res, n3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, b->stream));
+    CLB_HIP(hipStreamSynchronize(b->stream));
+    for (int i = 0; i < b->capacity; ++i) {
+        const bool used = b->slots[i].used;
+        double v[3];
+        std::memcpy(v, &host[3 * i], sizeof v);
+        if (du) du[i] = used ? v[0] : -1.0;
+        if (dT) dT[i] = used ? v[1] : -1.0;
+        if (nonfinite) nonfinite[i] = used && v[2] > 0.0 ? 1 : 0;
+    }
+    return CLB_OK;
 }

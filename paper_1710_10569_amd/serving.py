@@ -1,0 +1,156 @@
+"""Continuous-batching server for steady-state cavity solves on one GPU.
+
+Requests (differentially heated cavities of side L and Rayleigh number Ra) arrive over time.  A
+request is admitted as soon as a batch slot and enough pool memory are free (admission by HBM
+footprint, first come first served); admitted lattices stay resident and are advanced together by
+the batched kernel in chunks of `chunk` steps; after every chunk each resident lattice's FP64
+max-norm change of u and T over that chunk is measured on the device, and a lattice whose change
+is below `tol` (or that hits the step cap, or goes non-finite) is read out and its slot and memory
+are released for the next request.  A request therefore overlaps on the device with whatever else
+is resident, and its result does not depend on the mix: every lattice takes the same per-node
+update and the same chunk-aligned stopping test alone or with others.
+
+All arithmetic runs in libclb's kernels; this module only schedules.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import clb
+from . import workloads as W
+
+
+@dataclass
+class Request:
+    id: int
+    arrival: float          # seconds after the start of the run
+    L: int
+    Ra: float
+    noise_seed: int
+    admitted: float = math.nan
+    finished: float = math.nan
+    steps: int = 0
+    status: str = "pending"   # converged | floor | capped | diverged | rejected
+    du: float = math.nan
+    dT: float = math.nan
+    nu_wall: float = math.nan
+    fields: tuple = field(default=None, repr=False)
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+class CavityServer:
+    """Serve cavity requests through one clb.Batch.
+
+    budget_bytes: HBM pool for resident lattices; capacity: slots; chunk: steps between residual
+    checks; tol: max-norm change of u and of T per chunk that counts as steady; step_cap: give up
+    after this many steps; schedule: 'grouped' or 'persistent'; keep_fields: return (rho, ux, uy, T)."""
+
+    def __init__(self, budget_bytes=16 << 30, capacity=1024, precision="fp32", chunk=1000, tol=1e-8,
+                 step_cap=5_000_000, schedule="persistent", Pr=0.71, Ma=0.1, keep_fields=False,
+                 floor_patience=20, stream=None):
+        self.batch = clb.Batch(capacity, precision, budget_bytes=budget_bytes, stream=stream)
+        self.precision, self.chunk, self.tol, self.step_cap = precision, int(chunk), float(tol), int(step_cap)
+        self.schedule, self.Pr, self.Ma, self.keep_fields = schedule, Pr, Ma, keep_fields
+        self.floor_patience = int(floor_patience)
+        self.site_updates = 0
+
+    def close(self):
+        self.batch.close()
+
+    def _workload(self, r):
+        return W.cavity(r.L, Ra=r.Ra, Pr=self.Pr, Ma=self.Ma, seed=r.noise_seed)
+
+    def run(self, requests, clock=time.perf_counter, idle_sleep=1e-3, log=None):
+        """Serve `requests` (arrival times in seconds from now); returns them completed."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        pending = deque(reqs)
+        waiting = deque()
+        active = {}                # slot -> (request, best residual so far, chunks without progress)
+        t0 = clock()
+        footprint_cache = {}
+        budget = self.batch.info()["budget_bytes"]
+        while pending or waiting or active:
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            while waiting:
+                r = waiting[0]
+                fp = footprint_cache.setdefault(r.L, clb.footprint(r.L, r.L, self.precision))
+                if fp > budget:
+                    r.status, r.finished = "rejected", clock() - t0
+                    waiting.popleft()
+                    continue
+                slot = self.batch.add_workload(self._workload(r))
+                if slot is None:
+                    break           # wait until memory or a slot frees up
+                waiting.popleft()
+                r.admitted = clock() - t0
+                active[slot] = [r, math.inf, 0]
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, min(idle_sleep, pending[0].arrival - (clock() - t0))))
+                continue
+            self.batch.step(self.chunk, self.schedule)
+            if self.schedule == "persistent":
+                self.batch.check()
+            self.site_updates += self.chunk * sum(a[0].L * a[0].L for a in active.values())
+            done = []
+            resid = self.batch.residuals()      # one pass over every resident lattice
+            for slot, st in active.items():
+                r = st[0]
+                r.steps += self.chunk
+                r.du, r.dT, nonfinite = resid[slot]
+                res = max(r.du, r.dT)
+                if nonfinite:
+                    r.status = "diverged"
+                elif res < self.tol:
+                    r.status = "converged"
+                else:
+                    if res < 0.5 * st[1]:
+                        st[1], st[2] = res, 0
+                    else:
+                        st[2] += 1
+                    if st[2] >= self.floor_patience and res < 1e-6:
+                        r.status = "floor"      # stopped decreasing at the arithmetic's resolution
+                    elif r.steps >= self.step_cap:
+                        r.status = "capped"
+                if r.status != "pending":
+                    if r.status != "diverged":
+                        d = self.batch.diagnostics(slot)
+                        r.nu_wall = d["wall_flux"][0]       # hot wall, dT = 1: Nu_w
+                        if self.keep_fields:
+                            r.fields = self.batch.moments(slot)
+                    r.finished = clock() - t0
+                    done.append(slot)
+            for slot in done:
+                r = active.pop(slot)[0]
+                self.batch.remove(slot)
+                if log:
+                    log(f"[serve] t={r.finished:.3f}s id={r.id} L={r.L} Ra={r.Ra:.3g} {r.status} "
+                        f"steps={r.steps} latency={r.latency:.3f}s resident={len(active)}")
+        self.wall = clock() - t0
+        return reqs
+
+
+def summarize(reqs, wall, site_updates):
+    """p50/p99 latency of finished requests, solves/s, aggregate MLUPS, counts by status."""
+    fin = [r for r in reqs if r.status in ("converged", "floor", "capped")]
+    lat = np.array([r.latency for r in fin]) if fin else np.array([math.nan])
+    counts = {}
+    for r in reqs:
+        counts[r.status] = counts.get(r.status, 0) + 1
+    return {"requests": len(reqs), "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "solves_per_s": len(fin) / wall if wall > 0 else 0.0,
+            "aggregate_MLUPS": site_updates / wall / 1e6 if wall > 0 else 0.0, "wall_s": wall, "status": counts}
+
+
+def requests_from(specs):
+    return [Request(id=s["id"], arrival=s["arrival"], L=s["L"], Ra=s["Ra"], noise_seed=s["noise_seed"]) for s in specs]

@@ -146,15 +146,49 @@ def test_persistent_long_run_matches_grouped(gpu):
 
 
 def test_batch_residual_snapshot(gpu):
+    """Per-slot diagnostics and the one-pass residual of all slots measure the same change of u and
+    T between snapshots; the first snapshot is the initial state."""
     clb = _clb()
     b = clb.Batch(4, "fp32", budget_bytes=32 << 20)
-    s = b.add_workload(W.cavity(64, Ra=1e5))
+    w = W.cavity(64, Ra=1e5)
+    s = b.add_workload(w)
+    s2 = b.add_workload(W.cavity(80, Ra=1e4, seed=4))
     b.step(100)
     _, ux0, uy0, T0 = b.moments(s)
-    d0 = b.diagnostics(s, snapshot=True)
-    assert d0["du_max"] == -1.0
+    res = b.residuals()
+    assert res[s][0] == pytest.approx(max(np.abs(ux0).max(), np.abs(uy0).max()), rel=1e-14)
+    assert res[s][1] == pytest.approx(np.abs(T0 - w["fields"]["T"]).max(), rel=1e-12)
+    assert not res[s][2] and set(res) == {s, s2}
     b.step(100)
     _, ux1, uy1, T1 = b.moments(s)
+    r2 = b.residuals()
+    assert r2[s][0] == pytest.approx(max(np.abs(ux1 - ux0).max(), np.abs(uy1 - uy0).max()), rel=1e-14)
+    assert r2[s][1] == pytest.approx(np.abs(T1 - T0).max(), rel=1e-14)
+    b.diagnostics(s, snapshot=True)
+    b.step(100)
+    _, ux2, uy2, T2 = b.moments(s)
     d = b.diagnostics(s)
-    assert d["du_max"] == pytest.approx(max(np.abs(ux1 - ux0).max(), np.abs(uy1 - uy0).max()), rel=1e-14)
-    assert d["dT_max"] == pytest.approx(np.abs(T1 - T0).max(), rel=1e-14)
+    assert d["du_max"] == pytest.approx(max(np.abs(ux2 - ux1).max(), np.abs(uy2 - uy1).max()), rel=1e-14)
+    assert d["dT_max"] == pytest.approx(np.abs(T2 - T1).max(), rel=1e-14)
+
+
+def test_served_result_same_alone_and_in_mix(gpu):
+    """Continuous batching: a request served alone and the same request served while others
+    arrive, run and leave gives bitwise the same fields, stopping step and Nusselt number."""
+    from paper_1710_10569_amd import serving as S
+    mk = lambda: [S.Request(0, 0.0, 48, 2e4, 11)]
+    alone_srv = S.CavityServer(budget_bytes=64 << 20, capacity=16, chunk=500, tol=1e-6, step_cap=40000,
+                               schedule="grouped", keep_fields=True)
+    (a,) = alone_srv.run(mk())
+    alone_srv.close()
+    mix = mk() + [S.Request(1, 0.0, 64, 1e5, 12), S.Request(2, 0.0, 40, 3e3, 13), S.Request(3, 0.05, 56, 5e4, 14),
+                  S.Request(4, 0.1, 36, 1e3, 15)]
+    mix_srv = S.CavityServer(budget_bytes=64 << 20, capacity=16, chunk=500, tol=1e-6, step_cap=40000,
+                             schedule="persistent", keep_fields=True)
+    out = mix_srv.run(mix)
+    mix_srv.close()
+    m = next(r for r in out if r.id == 0)
+    assert a.status == m.status and a.steps == m.steps and a.nu_wall == m.nu_wall
+    for x, y in zip(a.fields, m.fields):
+        assert np.array_equal(x, y)
+    assert all(r.status in ("converged", "floor", "capped") for r in out)
