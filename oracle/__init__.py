@@ -27,14 +27,18 @@ EDGE_ORDER = ("west", "east", "south", "north")
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
-def _load():
+def _load(path=None):
+    """The oracle library (built on first use).  `path` loads another build of the same source
+    -- the mutation tests use it for deliberately broken copies -- and makes it current."""
     global _lib
-    if _lib is not None:
+    if _lib is not None and path is None:
         return _lib
-    if not os.path.exists(_LIBPATH):
-        from . import build as _build
-        _build.build()
-    lib = ctypes.CDLL(_LIBPATH)
+    if path is None:
+        if not os.path.exists(_LIBPATH):
+            from . import build as _build
+            _build.build()
+        path = _LIBPATH
+    lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.orc_create.restype = vp
     lib.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp, _dp,
@@ -68,6 +72,20 @@ def _load():
     lib.orc_zou_he.argtypes = [_dp, ctypes.c_int, ctypes.c_int] + [ctypes.c_double] * 4
     _lib = lib
     return lib
+
+
+def use_library(path):
+    """Make the oracle library at `path` current (None: the default build); returns the previous one."""
+    global _lib
+    prev = _lib
+    _lib = None
+    _load(path)
+    return prev
+
+
+def restore_library(prev):
+    global _lib
+    _lib = prev
 
 
 def _ptr(a):

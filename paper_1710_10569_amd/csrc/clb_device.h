@@ -402,4 +402,50 @@ __device__ __forceinline__ void node_update(const Real* __restrict__ src, Real* 
     }
 }
 
+// Two nodes of one column, (x, y0) and (x, y1): both pulls are issued before either update is
+// computed, so a thread has 28 loads in flight instead of 14.
+template <typename Real, bool DEV, bool NT>
+__device__ __forceinline__ void node_update2(const Real* __restrict__ src, Real* __restrict__ dst, const Geo& G,
+                                             const Par<Real>& P, int x, int y0, int y1)
+{
+    Real fa[9], ga[5], fb[9], gb[5];
+    pull(src, G, x, y0, fa, ga);
+    pull(src, G, x, y1, fb, gb);
+    if (on_wall(G, x, y0)) wall_step<Real, DEV>(src, G, P, x, y0, fa, ga);
+    if (on_wall(G, x, y1)) wall_step<Real, DEV>(src, G, P, x, y1, fb, gb);
+    const long long PL = G.plane;
+    {
+        const Macro<Real, DEV> m = macro<Real, DEV>(fa, ga, P);
+        collide_f<Real, DEV>(fa, m, P);
+        collide_g<Real, DEV>(ga, m, P);
+        const int o = y0 * G.pitch + x;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            if (NT) __builtin_nontemporal_store(fa[i], dst + i * PL + o);
+            else dst[i * PL + o] = fa[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            if (NT) __builtin_nontemporal_store(ga[i], dst + (9 + i) * PL + o);
+            else dst[(9 + i) * PL + o] = ga[i];
+        }
+    }
+    {
+        const Macro<Real, DEV> m = macro<Real, DEV>(fb, gb, P);
+        collide_f<Real, DEV>(fb, m, P);
+        collide_g<Real, DEV>(gb, m, P);
+        const int o = y1 * G.pitch + x;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            if (NT) __builtin_nontemporal_store(fb[i], dst + i * PL + o);
+            else dst[i * PL + o] = fb[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            if (NT) __builtin_nontemporal_store(gb[i], dst + (9 + i) * PL + o);
+            else dst[(9 + i) * PL + o] = gb[i];
+        }
+    }
+}
+
 }  // namespace clb

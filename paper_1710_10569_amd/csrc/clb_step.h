@@ -14,28 +14,34 @@
 
 namespace clb {
 
-struct TileShape { int tx, ty, spt, nt; };
+// tx x ty threads, spt nodes per thread (ty rows apart), nt: non-temporal stores, wpe: minimum
+// waves per SIMD the register allocation must allow (0: compiler's choice); spt = 2 variants pull
+// both nodes' 28 values before computing either, to double the loads in flight per thread.
+struct TileShape { int tx, ty, spt, nt, wpe; };
 
 // The compiled shapes (the autotuner chooses among them).
-constexpr int kNumShapes = 8;
+constexpr int kNumShapes = 11;
 __host__ __device__ constexpr TileShape tile_shape(int i)
 {
-    return i == 0 ? TileShape{64, 4, 1, 0}
-         : i == 1 ? TileShape{128, 2, 1, 0}
-         : i == 2 ? TileShape{256, 1, 1, 0}
-         : i == 3 ? TileShape{256, 1, 2, 0}
-         : i == 4 ? TileShape{128, 4, 1, 0}
-         : i == 5 ? TileShape{256, 2, 1, 0}
-         : i == 6 ? TileShape{256, 1, 1, 1}
-                  : TileShape{64, 4, 2, 0};
+    return i == 0 ? TileShape{64, 4, 1, 0, 0}
+         : i == 1 ? TileShape{128, 2, 1, 0, 0}
+         : i == 2 ? TileShape{256, 1, 1, 0, 0}
+         : i == 3 ? TileShape{256, 1, 2, 0, 0}
+         : i == 4 ? TileShape{128, 4, 1, 0, 0}
+         : i == 5 ? TileShape{256, 2, 1, 0, 0}
+         : i == 6 ? TileShape{256, 1, 1, 1, 0}
+         : i == 7 ? TileShape{64, 4, 2, 0, 0}
+         : i == 8 ? TileShape{256, 1, 1, 0, 8}
+         : i == 9 ? TileShape{256, 1, 1, 1, 8}
+                  : TileShape{128, 2, 1, 1, 8};
 }
 
 inline int tiles_x_of(const Geo& G, const TileShape& s) { return (G.nx + s.tx - 1) / s.tx; }
 inline int tiles_y_of(const Geo& G, const TileShape& s) { return (G.ny + s.ty * s.spt - 1) / (s.ty * s.spt); }
 
-template <typename Real, bool DEV, int TXW, int TY, int SPT, bool NT>
-__global__ __launch_bounds__(TXW * TY) void step_tile_kernel(const Real* __restrict__ src, Real* __restrict__ dst,
-                                                            Geo G, Par<Real> P, int tiles_x, int ntiles)
+template <typename Real, bool DEV, int TXW, int TY, int SPT, bool NT, int WPE>
+__global__ __launch_bounds__(TXW * TY, WPE) void step_tile_kernel(const Real* __restrict__ src, Real* __restrict__ dst,
+                                                                 Geo G, Par<Real> P, int tiles_x, int ntiles)
 {
     const int q = int(gridDim.x >> 3);
     const int t = int(blockIdx.x & 7) * q + int(blockIdx.x >> 3);
@@ -44,10 +50,12 @@ __global__ __launch_bounds__(TXW * TY) void step_tile_kernel(const Real* __restr
     const int x = txi * TXW + int(threadIdx.x % TXW);
     const int y0 = tyi * (TY * SPT) + int(threadIdx.x / TXW);
     if (x >= G.nx) return;
-#pragma unroll
-    for (int s = 0; s < SPT; ++s) {
-        const int y = y0 + s * TY;
-        if (y < G.ny) node_update<Real, DEV, NT>(src, dst, G, P, x, y);
+    if (SPT == 1) {
+        if (y0 < G.ny) node_update<Real, DEV, NT>(src, dst, G, P, x, y0);
+    } else {
+        const int y1 = y0 + TY;
+        if (y1 < G.ny) node_update2<Real, DEV, NT>(src, dst, G, P, x, y0, y1);
+        else if (y0 < G.ny) node_update<Real, DEV, NT>(src, dst, G, P, x, y0);
     }
 }
 
@@ -58,7 +66,7 @@ hipError_t launch_step_shape(const void* src, void* dst, const Geo& G, const Par
     constexpr TileShape sh = tile_shape(S);
     const int tx = tiles_x_of(G, sh), ntiles = tx * tiles_y_of(G, sh);
     const int q = (ntiles + 7) / 8;
-    step_tile_kernel<Real, DEV, sh.tx, sh.ty, sh.spt, sh.nt != 0><<<dim3(8 * q), dim3(sh.tx * sh.ty), 0, st>>>(
+    step_tile_kernel<Real, DEV, sh.tx, sh.ty, sh.spt, sh.nt != 0, (sh.wpe > 0 ? sh.wpe : 1)><<<dim3(8 * q), dim3(sh.tx * sh.ty), 0, st>>>(
         (const Real*)src, (Real*)dst, G, P, tx, ntiles);
     return hipGetLastError();
 }
@@ -74,7 +82,10 @@ hipError_t launch_step_any(int shape, const void* src, void* dst, const Geo& G, 
     case 4: return launch_step_shape<Real, DEV, 4>(src, dst, G, P, st);
     case 5: return launch_step_shape<Real, DEV, 5>(src, dst, G, P, st);
     case 6: return launch_step_shape<Real, DEV, 6>(src, dst, G, P, st);
-    default: return launch_step_shape<Real, DEV, 7>(src, dst, G, P, st);
+    case 7: return launch_step_shape<Real, DEV, 7>(src, dst, G, P, st);
+    case 8: return launch_step_shape<Real, DEV, 8>(src, dst, G, P, st);
+    case 9: return launch_step_shape<Real, DEV, 9>(src, dst, G, P, st);
+    default: return launch_step_shape<Real, DEV, 10>(src, dst, G, P, st);
     }
 }
 

@@ -1,0 +1,149 @@
+"""The pins bind: each plausible mistake planted in a temporary copy of the oracle source (a sign,
+a dropped term, a wrong constant, a swapped index) makes at least one pin fail.  The copies are
+built on the CPU in a temporary directory; the oracle itself is untouched."""
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import Edge
+from paper_1710_10569_amd import workloads as W
+from tests.helpers import oracle_from_workload
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "clb_oracle.c")
+
+# (name, original text, mutated text, pin that must fail)
+MUTANTS = [
+    ("printed_k02_sign", "uy2, 0, -2 * uy, 0, 1, 0, 0, 0, 0,", "uy2, 0, 2 * uy, 0, 1, 0, 0, 0, 0,", "moments"),
+    ("dropped_third_order_forcing", "CS2 * Fy, CS2 * Fx, 0};", "0.0 * Fy, 0.0 * Fx, 0};", "forcing"),
+    ("wrong_cT2", "#define CT2 (1.0 / 4.0)", "#define CT2 (1.0 / 3.0)", "decay"),
+    ("swapped_bulk_shear", "S[5 * 9 + 5] = L->s_nu;", "S[5 * 9 + 5] = L->s_b;", "shear"),
+    ("u_without_half_force", "*ux = (jx + 0.5 * (*Fx)) / r;", "*ux = jx / r;", "poiseuille"),
+    ("zou_he_force_sign", "+ 0.5 * (rho * ut - 0.5 * Ft) + 0.5 * (rho * un - 0.5 * Fn - Dn);",
+     "+ 0.5 * (rho * ut + 0.5 * Ft) + 0.5 * (rho * un - 0.5 * Fn - Dn);", "poiseuille"),
+    ("adiabatic_first_order", "Tb = (4.0 * Tf - Tff) / 3.0;", "Tb = Tf;", "walls"),
+    ("streaming_reversed", "int tx = x + EX[i], ty = y + EY[i];", "int tx = x - EX[i], ty = y - EY[i];", "walls"),
+]
+
+
+def build_mutant(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    lib = tmp_path / f"lib_{name}.so"
+    subprocess.run(["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", str(lib), str(path), "-lm"],
+                   check=True)
+    return str(lib)
+
+
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
+
+
+def pin_moments():
+    rng = np.random.default_rng(1)
+    f = 0.05 + rng.random(9) * 0.2
+    ux, uy = 0.1, 0.2
+    K = np.array([[(EX[i] - ux) ** m * (EY[i] - uy) ** n for i in range(9)]
+                  for (m, n) in [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (1, 1), (2, 1), (1, 2), (2, 2)]])
+    return np.allclose(O.matrix_N(ux, uy) @ O.matrix_M() @ f, K @ f, atol=1e-14)
+
+
+def pin_forcing():
+    """Collision vs Eq. 8 through the definitions (central-moment matrix + linear solve)."""
+    L = O.OracleLattice(3, 3)
+    L.set_params(0.7, 0.8, 0.0)
+    L.set_relaxation(1.3, 0.6, 1.2, 1.0)
+    rng = np.random.default_rng(2)
+    f = 0.05 + rng.random(9) * 0.2
+    Fx, Fy = 3e-3, -2e-3
+    rho = f.sum()
+    ux, uy = ((f * EX).sum() + Fx / 2) / rho, ((f * EY).sum() + Fy / 2) / rho
+    K = np.array([[(EX[i] - ux) ** m * (EY[i] - uy) ** n for i in range(9)]
+                  for (m, n) in [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (1, 1), (2, 1), (1, 2), (2, 2)]])
+    S = np.zeros((9, 9))
+    S[3, 3] = S[4, 4] = (1.3 + 1 / 0.7) / 2
+    S[3, 4] = S[4, 3] = (1.3 - 1 / 0.7) / 2
+    S[5, 5], S[6, 6], S[7, 7], S[8, 8] = 1 / 0.7, 0.6, 0.6, 1.2
+    C = np.array([0, Fx, Fy, 0, 0, 0, Fy / 3, Fx / 3, 0])
+    geq = np.array([rho, 0, 0, rho / 3, rho / 3, 0, 0, 0, rho / 9])
+    ref = np.linalg.solve(K, (np.eye(9) - S) @ (K @ f) + S @ geq + (np.eye(9) - S / 2) @ C)
+    return np.allclose(L.collide9(f, Fx, Fy), ref, atol=1e-14)
+
+
+def pin_decay():
+    """Taylor-Green velocity and temperature decay rates (nu = (tau - 1/2)/3, alpha = (tau - 1/2)/4)."""
+    w = W.taylor_green(32)
+    lat = oracle_from_workload(w)
+    ur, tr = w["fields"]["ux"], w["fields"]["T"] - 1
+    amp = lambda a, r: (a * r).sum() / (r * r).sum()
+    lat.step(50)
+    _, ux0, _, T0 = lat.moments()
+    lat.step(300)
+    _, ux1, _, T1 = lat.moments()
+    k = w["k"]
+    ru = math.log(amp(ux0, ur) / amp(ux1, ur)) / 300
+    rT = math.log(amp(T0 - 1, tr) / amp(T1 - 1, tr)) / 300
+    return abs(ru / (2 * 0.1 * k * k) - 1) < 3e-3 and abs(rT / (2 * 0.05 * k * k) - 1) < 3e-3
+
+
+def pin_poiseuille():
+    w = W.poiseuille(nx=4, ny=17, tau_nu=0.8, Fx=1e-6)
+    lat = oracle_from_workload(w)
+    lat.step(20000)
+    _, ux, _, _ = lat.moments()
+    y = np.arange(17)
+    ua = 1e-6 * y * (16 - y) / (2 * 0.1)
+    return np.abs(ux[:, 0] - ua).max() / ua.max() < 1e-6
+
+
+def pin_walls():
+    w = W.random_walled(12, 10, seed=5, wall_u=0.02)
+    lat = oracle_from_workload(w)
+    try:
+        lat.step(7)
+        _, ux, uy, T = lat.moments()
+    except RuntimeError:
+        return False          # an unknown population survived the wall step
+    ok = np.abs(T[0, 1:-1] - (4 * T[1, 1:-1] - T[2, 1:-1]) / 3).max() < 1e-14
+    return ok and np.abs(ux[1:-1, 0] - w["edges"]["west"][1]).max() < 1e-14
+
+
+def pin_shear():
+    """A shear wave u_x = U sin(k y) decays as exp(-nu k^2 t): k~11 relaxes at s_nu."""
+    n = 32
+    k = 2 * math.pi / n
+    lat = O.OracleLattice(3, n)
+    lat.set_params(0.8, 0.8, 0.0)
+    y = np.arange(n)[:, None]
+    u0 = np.broadcast_to(1e-3 * np.sin(k * y), (n, 3))
+    lat.init(ux=u0)
+    lat.step(50)
+    _, a, _, _ = lat.moments()
+    lat.step(300)
+    _, b, _, _ = lat.moments()
+    r = math.log((a * u0).sum() / (b * u0).sum()) / 300
+    return abs(r / (0.1 * k * k) - 1) < 3e-3
+
+
+PINS = {"shear": pin_shear, "moments": pin_moments, "forcing": pin_forcing, "decay": pin_decay, "poiseuille": pin_poiseuille,
+        "walls": pin_walls}
+
+
+def test_pins_hold_on_the_real_oracle():
+    for name, pin in PINS.items():
+        assert pin(), name
+
+
+@pytest.mark.parametrize("name,old,new,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(tmp_path, name, old, new, pin):
+    lib = build_mutant(tmp_path, name, old, new)
+    prev = O.use_library(lib)
+    try:
+        assert not PINS[pin](), f"mutant {name} passed pin {pin}"
+    finally:
+        O.restore_library(prev)

@@ -94,6 +94,27 @@ def test_taylor_green_decay_rates():
     assert abs(eT128) < abs(eT64) / 2.5
 
 
+def test_shear_wave_decay():
+    """u_x = U sin(k y): pure shear, decays as exp(-nu k^2 t) -- the k~11 rate s_nu (the
+    Taylor-Green orientation above has no shear strain and does not see it)."""
+    n = 64
+    k = 2 * math.pi / n
+    lat = O.OracleLattice(3, n)
+    lat.set_params(0.8, 0.8, 0.0)
+    y = np.arange(n)[:, None]
+    u0 = np.broadcast_to(1e-3 * np.sin(k * y), (n, 3))
+    lat.init(ux=u0)
+    ts, amp = [], []
+    for s in range(0, 2001, 200):
+        if s:
+            lat.step(200)
+        _, ux, _, _ = lat.moments()
+        ts.append(s)
+        amp.append((ux * u0).sum() / (u0 * u0).sum())
+    rate = -np.polyfit(ts[1:], np.log(amp[1:]), 1)[0]
+    assert rate / (O.nu_of_tau(0.8) * k * k) - 1 == pytest.approx(0, abs=1e-3)
+
+
 @pytest.mark.parametrize("s_b", [1.0, 1.5])
 def test_sound_attenuation_sets_bulk_viscosity(s_b):
     """A standing sound wave rho = 1 + eps cos(kx) oscillates at c_s k and decays at
