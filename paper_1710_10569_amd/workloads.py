@@ -171,3 +171,21 @@ def serving_requests(n=200, lam=1.0, seed=5, L_range=(32, 1024), Ra_range=(1e3, 
     Ras = np.exp(rng.uniform(math.log(Ra_range[0]), math.log(Ra_range[1]), n))
     return [{"id": i, "arrival": float(a), "L": int(L), "Ra": float(Ra), "noise_seed": 5000 + i}
             for i, (a, L, Ra) in enumerate(zip(arrivals, Ls, Ras))]
+
+
+def normal_plate(L=30, Re=10.0, Pr=0.71, nu=0.1, nx=5, T_L=0.0, T_H=1.0):
+    """Normal-plate channel: periodic in x (nx nodes), walls on nodes y = 0 and y = L.  Fluid is
+    injected through the bottom plate with v0 and withdrawn through the top plate, which also slides
+    with u0; u0 = v0 = Re nu / L.  Bottom plate at T_L, top plate at T_H, no buoyancy.  The D2Q5
+    second-order rate follows the zero-numerical-slip relation lambda2 = 12 (lambda1 - 2)/(lambda1 - 12)
+    with lambda1 = 1/tau_alpha.  Starts from rest at T = T_L."""
+    v0 = Re * nu / L
+    alpha = nu / Pr
+    tau_nu, tau_alpha = 3.0 * nu + 0.5, 4.0 * alpha + 0.5
+    lam1 = 1.0 / tau_alpha
+    return {"name": f"normal_plate_L{L}_Re{Re:g}_Pr{Pr:g}", "nx": nx, "ny": L + 1, "T0": T_L,
+            "edges": _edges(south=("dirichlet", 0.0, v0, T_L), north=("dirichlet", v0, v0, T_H)),
+            "taus": {"tau_nu": tau_nu, "tau_alpha": tau_alpha, "g_beta": 0.0},
+            "lambda2": 12.0 * (lam1 - 2.0) / (lam1 - 12.0),
+            "u_scale": v0, "Re": Re, "Pr": Pr, "L": L, "u0": v0, "T_L": T_L, "T_H": T_H,
+            "fields": {"rho": None, "ux": None, "uy": np.full((L + 1, nx), v0), "T": None}}

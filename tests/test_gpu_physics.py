@@ -1,0 +1,94 @@
+"""Physics on the GPU path (through the C ABI): the paper's validation problems run as GPU
+workloads -- the normal-plate problem's second-order convergence (Sec. 3.2, Fig. 2b) and the
+Rayleigh-Benard Nusselt table (Sec. 3.3, Table 1) as one batch of small lattices."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1710_10569_amd import workloads as W
+from tests.helpers import field_errors, oracle_from_workload
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _clb():
+    from paper_1710_10569_amd import clb
+    return clb
+
+
+def rel_l2(x, ref):
+    return float(np.sqrt(((x - ref) ** 2).sum() / (ref ** 2).sum()))
+
+
+def test_normal_plate_parity_fp64(gpu):
+    clb = _clb()
+    w = W.normal_plate(L=30)
+    g = clb.lattice_from_workload(w, "fp64")
+    g.set_relaxation(1.0, 1.0, 1.0, w["lambda2"])
+    o = oracle_from_workload(w)
+    o.set_relaxation(1.0, 1.0, 1.0, w["lambda2"])
+    g.step(3000)
+    o.step(3000)
+    e = field_errors(g.moments(), o.moments(), w["T0"], w["u_scale"])
+    assert max(e.values()) < 1e-12, e
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_normal_plate_second_order_on_gpu(gpu, precision):
+    clb = _clb()
+    Ls, Eu, ET = [30, 60, 90], [], []
+    Re = 10.0
+    for L in Ls:
+        w = W.normal_plate(L=L, Re=Re)
+        g = clb.lattice_from_workload(w, precision)
+        g.set_relaxation(1.0, 1.0, 1.0, w["lambda2"])
+        g.diagnostics(snapshot=True)
+        tol = 1e-13 if precision == "fp64" else 1e-9
+        for _ in range(200):
+            g.step(2000)
+            d = g.diagnostics(snapshot=True)
+            if max(d["du_max"], d["dT_max"]) < tol:
+                break
+        _, ux, _, T = g.moments()
+        y = np.arange(L + 1) / L
+        Eu.append(rel_l2(ux[:, 0], w["u0"] * np.expm1(Re * y) / math.expm1(Re)))
+        ET.append(rel_l2(T[:, 0], np.expm1(Re * w["Pr"] * y) / math.expm1(Re * w["Pr"])))
+        g.close()
+    su = -np.polyfit(np.log(Ls), np.log(Eu), 1)[0]
+    sT = -np.polyfit(np.log(Ls), np.log(ET), 1)[0]
+    print(f"[physics] normal plate {precision}: E_u {Eu} slope {su:.3f}; E_T {ET} slope {sT:.3f}", flush=True)
+    assert abs(su - 2.0) < 0.15 and abs(sT - 2.0) < 0.25
+
+
+def test_table1_nusselt_batch_fp32(gpu):
+    """All eight Table 1 cells (60 x 30, Pr = 0.71, Ma = 0.3, temperatures centred on 0) in one
+    FP32 batch, persistent schedule, run to a steady state.  Ra <= 20000 within 0.5% of the
+    analytic Nu (the paper's own errors reach 0.41%); all within 1.5%."""
+    clb = _clb()
+    gold = json.load(open(os.path.join(GOLD, "table1_nusselt.json")))
+    rows = gold["rows"]
+    b = clb.Batch(len(rows), "fp32", budget_bytes=64 << 20)
+    slots, alphas = [], []
+    for r in rows:
+        w = W.rb_cell(r["Ra"], T_hot=0.05, T_cold=-0.05)
+        slots.append(b.add_workload(w))
+        p = w["physics"]
+        alphas.append((clb.params_from_physics(p["Ra"], p["Pr"], p["Ma"], p["H"], p["dT"])[1] - 0.5) / 4)
+    for _ in range(80):
+        b.step(1000, "persistent")
+        b.check()
+        res = b.residuals()
+        if max(max(v[0], v[1]) for v in res.values()) < 1e-9:
+            break
+    out = []
+    for r, s, a in zip(rows, slots, alphas):
+        d = b.diagnostics(s)
+        nu = 1 + d["sum_w_uy_T"] / d["sum_w"] * 30 / (a * 0.1)
+        out.append((r["Ra"], nu, nu / r["Nu_analytic"] - 1))
+    print("[physics] Table 1 on GPU:", [(ra, round(nu, 4), f"{e:+.2%}") for ra, nu, e in out], flush=True)
+    for ra, nu, e in out:
+        assert abs(e) < (5e-3 if ra <= 20000 else 1.5e-2), (ra, nu, e)

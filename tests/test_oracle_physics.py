@@ -270,3 +270,34 @@ def test_table1_nusselt_centred_temperatures():
                 break
             prev = nu
         assert nu == pytest.approx(rows[Ra]["Nu_analytic"], rel=5e-3)
+
+
+def _normal_plate_errors(L, Re=10.0):
+    w = W.normal_plate(L=L, Re=Re)
+    lat = make(w)
+    lat.set_relaxation(1.0, 1.0, 1.0, w["lambda2"])
+    prev = None
+    for _ in range(400):
+        lat.step(2000)
+        _, ux, _, T = lat.moments()
+        if prev is not None and max(np.abs(ux - prev[0]).max(), np.abs(T - prev[1]).max()) < 1e-13:
+            break
+        prev = (ux.copy(), T.copy())
+    y = np.arange(L + 1) / L
+    ua = w["u0"] * np.expm1(Re * y) / math.expm1(Re)
+    Ta = np.expm1(Re * w["Pr"] * y) / math.expm1(Re * w["Pr"])
+    return O.rel_l2(ux[:, 0], ua), O.rel_l2(T[:, 0], Ta)
+
+
+def test_normal_plate_second_order():
+    """Sec. 3.2: channel with a sliding, permeable top plate and an injecting bottom plate
+    (Re = 10, Pr = 0.71, lambda2 from the zero-numerical-slip relation).  Steady u and T follow
+    the exponential profiles; the relative L2 errors E_u, E_T fall with slope about 2 in the
+    lattice spacing (Fig. 2b)."""
+    Ls = [30, 60, 90]
+    errs = [_normal_plate_errors(L) for L in Ls]
+    su = -np.polyfit(np.log(Ls), np.log([e[0] for e in errs]), 1)[0]
+    sT = -np.polyfit(np.log(Ls), np.log([e[1] for e in errs]), 1)[0]
+    assert abs(su - 2.0) < 0.15, su
+    assert abs(sT - 2.0) < 0.25, sT
+    assert errs[0][0] < 2e-3 and errs[0][1] < 1e-2
