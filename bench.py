@@ -130,8 +130,8 @@ def cpu_baseline(W, budget_s=15.0):
 
 def run_batch(clb, W, steps, stream, log_each=True):
     """The 512 batched cavities (sides from {64, 96, ..., 512}, Ra log-uniform in [1e3, 1e6], seed 7),
-    FP32, in one pool: autotuned tile widths, then the grouped (one launch per step), persistent (one
-    cooperative launch) and one-launch-per-cavity schedules timed over the same number of steps."""
+    FP32, in one pool: autotuned tile widths, then the grouped schedule (one launch per step over all
+    cavities) and the one-launch-per-cavity schedule, timed with HIP events on the batch's stream."""
     import torch
     specs = W.batch_cavity_specs()
     total = sum(L * L for L, _, _ in specs)
@@ -147,7 +147,7 @@ def run_batch(clb, W, steps, stream, log_each=True):
     b.autotune(3)
     torch.cuda.synchronize()
     out = {"cavities": len(specs), "sites": total, "steps": steps, "pool_GB": budget / 1e9}
-    for mode in ("grouped", "persistent", "each"):
+    for mode in ("grouped", "each"):
         n = steps if mode != "each" else max(10, steps // 10)
         b.step(2, mode)
         ms = b.time_steps(n, mode)
@@ -159,18 +159,19 @@ def run_batch(clb, W, steps, stream, log_each=True):
     return out
 
 
-def run_serving(clb, W, stream, n=40, lam=4.0, L_range=(32, 256), tol=1e-8, step_cap=400_000):
+def run_serving(clb, W, stream, n=32, lam=8.0, L_range=(32, 128), tol=1e-8, step_cap=200_000, patience=10):
     """A Poisson stream of cavity requests served with continuous batching (serving.py)."""
     from paper_1710_10569_amd import serving as S
     specs = W.serving_requests(n=n, lam=lam, L_range=L_range)
     reqs = S.requests_from(specs)
     srv = S.CavityServer(budget_bytes=8 << 30, capacity=256, chunk=1000, tol=tol, step_cap=step_cap,
-                         schedule="persistent", stream=stream)
+                         schedule="grouped", floor_patience=patience, stream=stream)
     out = srv.run(reqs)
     summ = S.summarize(out, srv.wall, srv.site_updates)
     srv.close()
     summ.update({"lambda_per_s": lam, "L_range": list(L_range), "Ra_range": [1e3, 1e6], "tol": tol,
-                 "step_cap": step_cap, "chunk": 1000})
+                 "step_cap": step_cap, "chunk": 1000, "precision": "fp32",
+                 "floor_rule": f"residual not halved in {patience} chunks and below 1e-6"})
     log(f"[bench] serving: {summ}")
     return summ
 

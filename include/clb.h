@@ -183,13 +183,15 @@ int clb_set_tile_shape(clb_lattice* h, int shape);
 int clb_get_tile_shape(clb_lattice* h, int* shape);
 
 /* Time every shape for `launches_per_shape` launches on this lattice, select the fastest for the
- * handle and record it for its size class.  The timed launches read the current state and write
- * only the spare buffer, so the lattice state and step count are unchanged.  best_shape and
- * best_us (average launch time of the winner, microseconds) may be NULL.  Synchronises. */
+ * handle and record it for its size class.  The timed steps ping-pong between two temporary device
+ * buffers that start as a copy of the current state (the access pattern of real stepping); the
+ * lattice state and step count are unchanged.  If the temporary pair cannot be allocated, each
+ * launch instead reads the current state and writes the spare buffer.  best_shape and best_us
+ * (average launch time of the winner, microseconds) may be NULL.  Synchronises. */
 int clb_autotune(clb_lattice* h, int launches_per_shape, int* best_shape, double* best_us);
 
-/* Average launch time in microseconds of `launches` step launches with shape `shape`, state
- * unchanged as in clb_autotune.  Synchronises. */
+/* Average launch time in microseconds of `launches` step launches with shape `shape`, measured
+ * as in clb_autotune; state unchanged.  Synchronises. */
 int clb_time_shape(clb_lattice* h, int shape, int launches, double* us);
 
 /* Wait for the handle's stream. */
@@ -252,12 +254,13 @@ int clb_batch_step(clb_batch* b, long long n);
 /* The same n steps with one launch per lattice per step (the one-lattice-at-a-time schedule). */
 int clb_batch_step_each(clb_batch* b, long long n);
 
-/* The same n steps in one cooperative persistent launch (per chunk of at most 4096 steps): each
- * workgroup sweeps a fixed range of tiles every step, waiting per lattice for the previous step.
- * A bounded wait turns an overrun into CLB_EDEVICE from clb_batch_check instead of a hang. */
+/* The same n steps with small lattices (at most 128*128 nodes) workgroup-resident: one launch runs
+ * all n steps, each such lattice owned by one 1024-thread workgroup with a workgroup barrier
+ * between steps; larger lattices take the grouped launches concurrently on the batch's stream.
+ * Suited to many small lattices, where per-step launches would dominate. */
 int clb_batch_step_persistent(clb_batch* b, long long n);
 
-/* Synchronise and report whether a persistent launch gave up waiting (CLB_EDEVICE). */
+/* Synchronise the batch's stream and report any pending launch error (CLB_EDEVICE). */
 int clb_batch_check(clb_batch* b);
 
 /* Time n steps of schedule mode (0 grouped, 1 one launch per lattice, 2 persistent) with HIP events

@@ -372,28 +372,74 @@ extern "C" int clb_get_tile_shape(clb_lattice* h, int* shape)
     return CLB_OK;
 }
 
+// Average launch time of `launches` steps with shape `shape`, ping-ponging between two scratch
+// buffers that start as a copy of the current state: the same access pattern and cache behaviour
+// as real stepping, and the lattice itself is not touched.  Falls back to repeated one-direction
+// launches on the lattice's own buffers (reading the state, writing the spare buffer) if the scratch
+// pair cannot be allocated.
+static int time_shape_impl(clb_lattice* h, int shape, int launches, void* const scratch[2], double* us)
+{
+    void* src = scratch[0] ? scratch[0] : h->buf[h->cur];
+    void* dst = scratch[0] ? scratch[1] : h->buf[h->cur ^ 1];
+    for (int w = 0; w < 2; ++w) {
+        CLB_HIP(launch_one_step(h, shape, src, dst));
+        if (scratch[0]) std::swap(src, dst);
+    }
+    CLB_HIP(hipEventRecord(h->ev[0], h->stream));
+    for (int r = 0; r < launches; ++r) {
+        CLB_HIP(launch_one_step(h, shape, src, dst));
+        if (scratch[0]) std::swap(src, dst);
+    }
+    CLB_HIP(hipEventRecord(h->ev[1], h->stream));
+    CLB_HIP(hipEventSynchronize(h->ev[1]));
+    float ms = 0.0f;
+    CLB_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+    *us = 1e3 * ms / launches;
+    return CLB_OK;
+}
+
+static void scratch_pair(clb_lattice* h, void* scratch[2])
+{
+    scratch[0] = scratch[1] = nullptr;
+    if (hipMalloc(&scratch[0], h->buf_bytes) != hipSuccess || hipMalloc(&scratch[1], h->buf_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(scratch[0]);
+        (void)hipFree(scratch[1]);
+        scratch[0] = scratch[1] = nullptr;
+        return;
+    }
+    if (hipMemcpyAsync(scratch[0], h->buf[h->cur], h->buf_bytes, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(scratch[0]);
+        (void)hipFree(scratch[1]);
+        scratch[0] = scratch[1] = nullptr;
+    }
+}
+
+static void free_scratch(clb_lattice* h, void* scratch[2])
+{
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(scratch[0]);
+    (void)hipFree(scratch[1]);
+}
+
 extern "C" int clb_autotune(clb_lattice* h, int launches_per_shape, int* best_shape, double* best_us)
 {
     clear_error();
     if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
     if (launches_per_shape <= 0) { set_error("launches_per_shape must be positive"); return CLB_EINVAL; }
-    // Every timed launch reads the current state and writes the other buffer, which holds no
-    // state; the lattice is left exactly as it was.
-    const void* src = h->buf[h->cur];
-    void* dst = h->buf[h->cur ^ 1];
+    void* scratch[2];
+    scratch_pair(h, scratch);
     int best = -1;
     double best_t = 0.0;
     for (int s = 0; s < kNumShapes; ++s) {
-        for (int w = 0; w < 2; ++w) CLB_HIP(launch_one_step(h, s, src, dst));
-        CLB_HIP(hipEventRecord(h->ev[0], h->stream));
-        for (int r = 0; r < launches_per_shape; ++r) CLB_HIP(launch_one_step(h, s, src, dst));
-        CLB_HIP(hipEventRecord(h->ev[1], h->stream));
-        CLB_HIP(hipEventSynchronize(h->ev[1]));
-        float ms = 0.0f;
-        CLB_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
-        const double us = 1e3 * ms / launches_per_shape;
+        double us = 0.0;
+        const int rc = time_shape_impl(h, s, launches_per_shape, scratch, &us);
+        if (rc) { free_scratch(h, scratch); return rc; }
         if (best < 0 || us < best_t) { best = s; best_t = us; }
     }
+    free_scratch(h, scratch);
     h->shape = best;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -409,17 +455,11 @@ extern "C" int clb_time_shape(clb_lattice* h, int shape, int launches, double* u
     clear_error();
     if (!h || !us) { set_error("NULL argument"); return CLB_EINVAL; }
     if (shape < 0 || shape >= kNumShapes || launches <= 0) { set_error("bad shape or launch count"); return CLB_EINVAL; }
-    const void* src = h->buf[h->cur];
-    void* dst = h->buf[h->cur ^ 1];
-    for (int w = 0; w < 2; ++w) CLB_HIP(launch_one_step(h, shape, src, dst));
-    CLB_HIP(hipEventRecord(h->ev[0], h->stream));
-    for (int r = 0; r < launches; ++r) CLB_HIP(launch_one_step(h, shape, src, dst));
-    CLB_HIP(hipEventRecord(h->ev[1], h->stream));
-    CLB_HIP(hipEventSynchronize(h->ev[1]));
-    float ms = 0.0f;
-    CLB_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
-    *us = 1e3 * ms / launches;
-    return CLB_OK;
+    void* scratch[2];
+    scratch_pair(h, scratch);
+    const int rc = time_shape_impl(h, shape, launches, scratch, us);
+    free_scratch(h, scratch);
+    return rc;
 }
 
 extern "C" int clb_synchronize(clb_lattice* h)

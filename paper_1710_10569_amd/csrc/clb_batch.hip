@@ -16,11 +16,12 @@
 //               contiguous bands (as in the single-lattice kernel);
 //   each        one launch per lattice per time step (the schedule a one-lattice-at-a-time caller
 //               would use);
-//   persistent  one cooperative launch for many steps: every workgroup owns a fixed contiguous
-//               range of the tile list and sweeps it once per step; before a tile of lattice L at
-//               step s it waits until all tiles of L have finished step s-1 (a per-lattice counter
-//               with agent-scope release/acquire).  Co-residency makes every wait finite; a spin
-//               limit bounds it anyway and turns an overrun into an error instead of a hang.
+//   persistent  every lattice of at most kResidentMaxNodes nodes is owned by one workgroup of
+//               1024 threads that runs all the steps of the call inside one launch, with a
+//               workgroup barrier between steps (all its waves share one CU and its L1, so no
+//               cross-workgroup synchronisation or agent-scope cache maintenance is needed, and a
+//               small lattice's two buffers stay in that XCD's L2); larger lattices take the grouped
+//               launches, on the batch's stream, while the resident kernel runs on a second stream.
 #include "clb_internal.h"
 #include "clb_aux.h"
 
@@ -94,50 +95,28 @@ __global__ void batch_zero_kernel(unsigned* p, int n)
     if (i < n) p[i] = 0u;
 }
 
-// sync[0 .. capacity): per-slot tiles finished (cumulative over this launch's steps);
-// sync[capacity]: failure flag.
-template <typename Real, bool DEV, bool NT>
-__global__ __launch_bounds__(BNT) void batch_persistent_kernel(Real* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
-                                                             const TileRef* __restrict__ tiles, int ntiles, int nsteps,
-                                                             unsigned* sync, int capacity, unsigned spin_limit)
+// Workgroup-resident steps: workgroup i owns lattice slots[i] and advances it nsteps steps.
+constexpr int RNT = 1024;
+constexpr long long kResidentMaxNodes = 128 * 128;
+
+template <typename Real, bool DEV>
+__global__ __launch_bounds__(RNT) void batch_resident_kernel(Real* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
+                                                           const int* __restrict__ slots, int nslots, int nsteps)
 {
-    const int q = int(gridDim.x >> 3);
-    const int w = int(blockIdx.x & 7) * q + int(blockIdx.x >> 3);
-    const int G = int(gridDim.x);
-    const int lo = int((long long)ntiles * w / G), hi = int((long long)ntiles * (w + 1) / G);
-    unsigned* fail = sync + capacity;
-    __shared__ int s_stop;
+    if (int(blockIdx.x) >= nslots) return;
+    const BatchEntry<Real> E = lats[slots[blockIdx.x]];
+    const int nx = E.L.G.nx, n = E.L.G.nx * E.L.G.ny;
     for (int s = 0; s < nsteps; ++s) {
-        int waited_lat = -1;
-        for (int t = lo; t < hi; ++t) {
-            const TileRef r = tiles[t];
-            const BatchEntry<Real> E = lats[r.lat];
-            if (s > 0 && r.lat != waited_lat) {
-                if (threadIdx.x == 0) {
-                    const unsigned need = unsigned(s) * unsigned(E.L.ntiles);
-                    unsigned spins = 0;
-                    int stop = 0;
-                    while (__hip_atomic_load(sync + r.lat, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                        if (__hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { stop = 1; break; }
-                        if (++spins > spin_limit) {
-                            __hip_atomic_fetch_or(fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            stop = 1;
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(2);
-                    }
-                    s_stop = stop;
-                }
-                __syncthreads();
-                if (s_stop) return;
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                waited_lat = r.lat;
-            }
-            batch_tile<Real, DEV, NT>(pool, E, r.tile, s & 1);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
-            if (threadIdx.x == 0) __hip_atomic_fetch_add(sync + r.lat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool c = (E.L.cur ^ (s & 1)) != 0;
+        const Real* src = pool + (c ? E.L.off[1] : E.L.off[0]);
+        Real* dst = pool + (c ? E.L.off[0] : E.L.off[1]);
+        for (int k = int(threadIdx.x); k < n; k += RNT) {
+            const int y = k / nx, x = k - y * nx;
+            node_update<Real, DEV, false>(src, dst, E.L.G, E.P, x, y);
         }
+        // every store of step s is visible to every load of step s + 1: all waves of the workgroup
+        // are on one CU and share its L1
+        __syncthreads();
     }
 }
 
@@ -272,7 +251,13 @@ struct clb_batch {
     int* d_active = nullptr;              // slots in use (for the flip kernel)
     int n_active = 0;
     bool dirty = true;
-    unsigned* d_sync = nullptr;
+    hipStream_t side = nullptr;           // second stream for the workgroup-resident kernel
+    hipEvent_t fork = nullptr, join = nullptr;
+    int* d_small = nullptr;               // slots run by the resident kernel
+    std::vector<int> small_slots;
+    std::vector<TileRef> tiles_big;       // tiles of the other lattices (grouped launches)
+    TileRef* d_tiles_big = nullptr;
+    size_t tiles_big_cap = 0;
     double* d_fields = nullptr;
     size_t fields_cap = 0;                // doubles
     double* d_partials = nullptr;
@@ -281,7 +266,6 @@ struct clb_batch {
     unsigned long long* d_res = nullptr;  // 3 per slot: residual of u, of T, non-finite flag
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::map<int, int> tw_by_class;       // autotuned tile width (log2) per size class
-    int persistent_grid = 0;
     bool nontemporal = false;
 };
 
@@ -381,30 +365,76 @@ int upload_tables(clb_batch* b)
     if (!active.empty())
         CLB_HIP(hipMemcpyAsync(b->d_active, active.data(), active.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
     b->n_active = int(active.size());
+    // split for the persistent schedule: small lattices are workgroup-resident, the rest grouped
+    b->small_slots.clear();
+    b->tiles_big.clear();
+    for (int i : active) {
+        const BatchSlot& s = b->slots[i];
+        if ((long long)s.desc.nx * s.desc.ny <= kResidentMaxNodes) {
+            b->small_slots.push_back(i);
+        } else {
+            for (int t = 0; t < b->ntiles[i]; ++t) b->tiles_big.push_back(TileRef{i, t});
+        }
+    }
+    if (!b->small_slots.empty())
+        CLB_HIP(hipMemcpyAsync(b->d_small, b->small_slots.data(), b->small_slots.size() * sizeof(int),
+                               hipMemcpyHostToDevice, b->stream));
+    if (b->tiles_big.size() > b->tiles_big_cap) {
+        CLB_HIP(hipStreamSynchronize(b->stream));
+        CLB_HIP(hipStreamSynchronize(b->side));
+        (void)hipFree(b->d_tiles_big);
+        b->d_tiles_big = nullptr;
+        const size_t cap_t = std::max<size_t>(b->tiles_big.size() * 5 / 4, 1024);
+        CLB_HIP(hipMalloc((void**)&b->d_tiles_big, cap_t * sizeof(TileRef)));
+        b->tiles_big_cap = cap_t;
+    }
+    if (!b->tiles_big.empty())
+        CLB_HIP(hipMemcpyAsync(b->d_tiles_big, b->tiles_big.data(), b->tiles_big.size() * sizeof(TileRef),
+                               hipMemcpyHostToDevice, b->stream));
     b->dirty = false;
     return CLB_OK;
 }
 
 template <typename Real, bool DEV>
-hipError_t grouped_launch(clb_batch* b, int tile_base, int ntiles, int parity)
+hipError_t grouped_launch(clb_batch* b, const TileRef* tiles, int tile_base, int ntiles, int parity)
 {
     const int q = (ntiles + 7) / 8;
     if (b->nontemporal)
         batch_step_kernel<Real, DEV, true><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
-            (Real*)b->pool, (const BatchEntry<Real>*)b->d_lats, b->d_tiles, tile_base, ntiles, parity);
+            (Real*)b->pool, (const BatchEntry<Real>*)b->d_lats, tiles, tile_base, ntiles, parity);
     else
         batch_step_kernel<Real, DEV, false><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
-            (Real*)b->pool, (const BatchEntry<Real>*)b->d_lats, b->d_tiles, tile_base, ntiles, parity);
+            (Real*)b->pool, (const BatchEntry<Real>*)b->d_lats, tiles, tile_base, ntiles, parity);
     return hipGetLastError();
 }
 
-hipError_t grouped_any(clb_batch* b, int tile_base, int ntiles, int parity)
+hipError_t grouped_any(clb_batch* b, int tile_base, int ntiles, int parity, const TileRef* tiles = nullptr)
 {
     if (ntiles <= 0) return hipSuccess;
+    if (!tiles) tiles = b->d_tiles;
     switch (b->precision) {
-    case CLB_FP64: return grouped_launch<double, false>(b, tile_base, ntiles, parity);
-    case CLB_FP64_DEV: return grouped_launch<double, true>(b, tile_base, ntiles, parity);
-    default: return grouped_launch<float, true>(b, tile_base, ntiles, parity);
+    case CLB_FP64: return grouped_launch<double, false>(b, tiles, tile_base, ntiles, parity);
+    case CLB_FP64_DEV: return grouped_launch<double, true>(b, tiles, tile_base, ntiles, parity);
+    default: return grouped_launch<float, true>(b, tiles, tile_base, ntiles, parity);
+    }
+}
+
+template <typename Real, bool DEV>
+hipError_t resident_launch(clb_batch* b, int nsteps, hipStream_t st)
+{
+    const int ns = int(b->small_slots.size());
+    batch_resident_kernel<Real, DEV><<<dim3(ns), dim3(RNT), 0, st>>>((Real*)b->pool, (const BatchEntry<Real>*)b->d_lats,
+                                                                     b->d_small, ns, nsteps);
+    return hipGetLastError();
+}
+
+hipError_t resident_any(clb_batch* b, int nsteps, hipStream_t st)
+{
+    if (b->small_slots.empty() || nsteps <= 0) return hipSuccess;
+    switch (b->precision) {
+    case CLB_FP64: return resident_launch<double, false>(b, nsteps, st);
+    case CLB_FP64_DEV: return resident_launch<double, true>(b, nsteps, st);
+    default: return resident_launch<float, true>(b, nsteps, st);
     }
 }
 
@@ -426,49 +456,6 @@ void advance_host(clb_batch* b, long long n)
             s.steps += n;
             if (n & 1) s.cur ^= 1;
         }
-}
-
-template <typename Real, bool DEV, bool NT>
-int persistent_grid_for(clb_batch* b)
-{
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    CLB_HIP(hipGetDevice(&dev));
-    CLB_HIP(hipGetDeviceProperties(&prop, dev));
-    CLB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_persistent_kernel<Real, DEV, NT>, BNT, 0));
-    const int g = (prop.multiProcessorCount * std::max(per_cu, 1)) / 8 * 8;
-    return std::max(g, 8);
-}
-
-template <typename Real, bool DEV, bool NT>
-int persistent_launch(clb_batch* b, int nsteps)
-{
-    const int grid = persistent_grid_for<Real, DEV, NT>(b);
-    if (grid <= 0) return CLB_EDEVICE;
-    b->persistent_grid = grid;
-    const int nz = b->capacity + 1;
-    batch_zero_kernel<<<(nz + 255) / 256, 256, 0, b->stream>>>(b->d_sync, nz);
-    CLB_HIP(hipGetLastError());
-    Real* pool = (Real*)b->pool;
-    const BatchEntry<Real>* lats = (const BatchEntry<Real>*)b->d_lats;
-    const TileRef* tiles = b->d_tiles;
-    int ntiles = int(b->tiles.size());
-    unsigned* sync = b->d_sync;
-    int capacity = b->capacity;
-    unsigned spin_limit = 1u << 20;   // a wait this long (about a second) means something is wrong
-    void* args[] = {&pool, &lats, &tiles, &ntiles, &nsteps, &sync, &capacity, &spin_limit};
-    CLB_HIP(hipLaunchCooperativeKernel((const void*)batch_persistent_kernel<Real, DEV, NT>, dim3(grid), dim3(BNT), args, 0,
-                                       b->stream));
-    return CLB_OK;
-}
-
-int persistent_any(clb_batch* b, int nsteps)
-{
-    switch (b->precision) {
-    case CLB_FP64: return b->nontemporal ? persistent_launch<double, false, true>(b, nsteps) : persistent_launch<double, false, false>(b, nsteps);
-    case CLB_FP64_DEV: return b->nontemporal ? persistent_launch<double, true, true>(b, nsteps) : persistent_launch<double, true, false>(b, nsteps);
-    default: return b->nontemporal ? persistent_launch<float, true, true>(b, nsteps) : persistent_launch<float, true, false>(b, nsteps);
-    }
 }
 
 int check_slot(clb_batch* b, int slot)
@@ -501,15 +488,21 @@ int step_impl(clb_batch* b, int mode, long long n)
     }
     if (b->tiles.empty()) return CLB_OK;
     if (mode == MODE_PERSISTENT) {
-        // counters count tiles finished over one launch; keep them far below 2^32
-        long long max_tiles = 1;
-        for (int i = 0; i < b->capacity; ++i) max_tiles = std::max<long long>(max_tiles, b->ntiles[i]);
-        const long long chunk = std::max<long long>(1, std::min<long long>(4096, (1LL << 30) / max_tiles));
+        // small lattices: one resident launch per chunk on the side stream; big ones: grouped
+        // launches on the main stream, concurrently
+        const long long chunk = 1 << 20;
         long long done = 0;
         while (done < n) {
             const int k = int(std::min(chunk, n - done));
-            const int rc = persistent_any(b, k);
-            if (rc) return rc;
+            if (!b->small_slots.empty()) {
+                CLB_HIP(hipEventRecord(b->fork, b->stream));
+                CLB_HIP(hipStreamWaitEvent(b->side, b->fork, 0));
+                CLB_HIP(resident_any(b, k, b->side));
+                CLB_HIP(hipEventRecord(b->join, b->side));
+            }
+            for (int s = 0; s < k; ++s)
+                CLB_HIP(grouped_any(b, 0, int(b->tiles_big.size()), s & 1, b->d_tiles_big));
+            if (!b->small_slots.empty()) CLB_HIP(hipStreamWaitEvent(b->stream, b->join, 0));
             if (k & 1) CLB_HIP(flip_all(b));
             advance_host(b, k);
             done += k;
@@ -553,7 +546,12 @@ extern "C" void clb_batch_destroy(clb_batch* b)
     (void)hipFree(b->d_lats);
     (void)hipFree(b->d_tiles);
     (void)hipFree(b->d_active);
-    (void)hipFree(b->d_sync);
+    (void)hipFree(b->d_small);
+    (void)hipFree(b->d_tiles_big);
+    if (b->side) (void)hipStreamSynchronize(b->side);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
+    if (b->side) (void)hipStreamDestroy(b->side);
     (void)hipFree(b->d_fields);
     (void)hipFree(b->d_partials);
     (void)hipFree(b->d_diag);
@@ -602,8 +600,10 @@ static int batch_create_impl(int capacity, int precision, size_t budget, void* p
     CLB_HIP(hipMalloc(&b->d_lats, entry_bytes(precision) * capacity));
     CLB_HIP(hipMemsetAsync(b->d_lats, 0, entry_bytes(precision) * capacity, b->stream));
     CLB_HIP(hipMalloc((void**)&b->d_active, sizeof(int) * capacity));
-    CLB_HIP(hipMalloc((void**)&b->d_sync, sizeof(unsigned) * (capacity + 1)));
-    CLB_HIP(hipMemsetAsync(b->d_sync, 0, sizeof(unsigned) * (capacity + 1), b->stream));
+    CLB_HIP(hipMalloc((void**)&b->d_small, sizeof(int) * capacity));
+    CLB_HIP(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+    CLB_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    CLB_HIP(hipEventCreateWithFlags(&b->join, hipEventDisableTiming));
     CLB_HIP(hipMalloc((void**)&b->d_diag, DIAG_SLOTS * sizeof(double)));
     CLB_HIP(hipMalloc((void**)&b->d_res, sizeof(unsigned long long) * 3 * capacity));
     CLB_HIP(hipEventCreate(&b->ev[0]));
@@ -786,10 +786,8 @@ extern "C" int clb_batch_check(clb_batch* b)
 {
     clear_error();
     if (!b) { set_error("batch is NULL"); return CLB_EINVAL; }
-    unsigned flag = 0;
-    CLB_HIP(hipMemcpyAsync(&flag, b->d_sync + b->capacity, sizeof flag, hipMemcpyDeviceToHost, b->stream));
     CLB_HIP(hipStreamSynchronize(b->stream));
-    if (flag) { set_error("a persistent launch gave up waiting for a lattice step (spin limit)"); return CLB_EDEVICE; }
+    CLB_HIP(hipGetLastError());
     return CLB_OK;
 }
 
@@ -810,7 +808,7 @@ extern "C" int clb_batch_time_steps(clb_batch* b, int mode, long long n, double*
     float t = 0.0f;
     CLB_HIP(hipEventElapsedTime(&t, b->ev[0], b->ev[1]));
     *ms = t;
-    return mode == MODE_PERSISTENT ? clb_batch_check(b) : CLB_OK;
+    return CLB_OK;
 }
 
 extern "C" int clb_batch_synchronize(clb_batch* b)

@@ -130,7 +130,7 @@ def test_batch_autotune_keeps_state(gpu):
 
 
 def test_persistent_long_run_matches_grouped(gpu):
-    """More steps than one persistent launch covers (chunks of 4096 steps), odd total."""
+    """A long workgroup-resident run (odd step count) equals the grouped schedule bitwise."""
     clb = _clb()
     ws = [W.cavity(64, Ra=10 ** (3 + i / 3), seed=i) for i in range(6)]
     bp = clb.Batch(8, "fp32", budget_bytes=64 << 20)
@@ -193,3 +193,21 @@ def test_served_result_same_alone_and_in_mix(gpu):
     for x, y in zip(a.fields, m.fields):
         assert np.array_equal(x, y)
     assert all(r.status in ("converged", "floor", "capped") for r in out)
+
+
+def test_persistent_with_small_and_large_lattices(gpu):
+    """The persistent schedule splits a mix: lattices up to 128 x 128 nodes run workgroup-resident on
+    a second stream while larger ones take grouped launches; both kinds match their runs alone."""
+    clb = _clb()
+    ws = [W.cavity(64, Ra=1e4, seed=1), W.random_walled(200, 100, seed=2, wall_u=0.01),
+          W.rayleigh_benard(320, 65, Ra=1e4, seed=3), W.random_periodic(128, 128, seed=4),
+          W.cavity(130, Ra=1e5, seed=5)]
+    b = clb.Batch(8, "fp32", budget_bytes=128 << 20)
+    slots = [b.add_workload(w) for w in ws]
+    b.step(101, "persistent")
+    b.step(40, "grouped")
+    b.step(7, "persistent")
+    b.check()
+    for w, s in zip(ws, slots):
+        for a, r in zip(b.moments(s), alone(w, "fp32", 148)):
+            assert np.array_equal(a, r), w["name"]
