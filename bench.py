@@ -38,11 +38,12 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the sources that define the single-lattice step kernel and of the build flags."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1710_10569_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode())
+    for rel in ("paper_1710_10569_amd/csrc/clb_device.h", "paper_1710_10569_amd/csrc/clb_step.h",
+                "paper_1710_10569_amd/build.py"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(rel.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -60,13 +61,17 @@ def measured_traffic(sites):
     return t.get("bytes_per_launch")
 
 
-def run_precision(clb, W, precision, steps, warmup, stream, workload):
+def run_precision(clb, W, precision, steps, warmup, stream, workload, autotune=False, shape=None):
     lat = clb.lattice_from_workload(workload, precision, stream=stream)
     if warmup:
         lat.step(warmup)
-    # the autotuner times every compiled tile shape on this lattice (state unchanged) and keeps
-    # the fastest; part of warm-up, outside the timed region
-    shape, tuned_us = lat.autotune(20 if workload["nx"] * workload["ny"] <= 1 << 22 else 5)
+    if shape is not None:
+        lat.tile_shape = shape
+    elif autotune:
+        # times every compiled tile shape on scratch copies of the state, keeps the fastest; part
+        # of warm-up, outside the timed region
+        lat.autotune(20 if workload["nx"] * workload["ny"] <= 1 << 22 else 5)
+    shape = lat.tile_shape
     lat.synchronize()
     import torch
     torch.cuda.synchronize()
@@ -188,6 +193,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-cavity batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the single-lattice tile shape instead of the library default")
+    ap.add_argument("--tile-shape", type=int, default=None, help="force a single-lattice tile shape")
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference kernel for "
                          "scaling hardware byte counters) and exit")
@@ -217,7 +225,8 @@ def main():
     w = W.rayleigh_benard()
     sites = w["nx"] * w["ny"]
 
-    lat32, r32 = run_precision(clb, W, "fp32", args.steps, args.warmup, stream.cuda_stream, w)
+    lat32, r32 = run_precision(clb, W, "fp32", args.steps, args.warmup, stream.cuda_stream, w,
+                               args.autotune, args.tile_shape)
     result = {
         "metric": METRIC,
         "value": r32["mlups"],
@@ -243,7 +252,7 @@ def main():
                           "algorithmic_bytes_per_launch": BYTES_PER_SITE["fp32"] * sites,
                           "avg_launch_us": r32["ms_per_step"] * 1e3}
     if not args.no_fp64:
-        lat64, r64 = run_precision(clb, W, "fp64", args.steps, args.warmup, stream.cuda_stream, w)
+        lat64, r64 = run_precision(clb, W, "fp64", args.steps, args.warmup, stream.cuda_stream, w, args.autotune)
         _, ux32, uy32, T32 = lat32.moments()
         _, ux64, uy64, T64 = lat64.moments()
         import numpy as np
@@ -251,6 +260,7 @@ def main():
         eu = max(np.abs(ux32 - ux64).max(), np.abs(uy32 - uy64).max()) / umax
         eT = np.abs(T32 - T64).max() / np.abs(T64 - w["T0"]).max()
         result["fp64"] = {"value": r64["mlups"], "unit": "MLUPS", "ms_per_step": r64["ms_per_step"],
+                          "tile_shape": r64["tile_shape"],
                           "achieved_GBps": r64["gbps"], "frac": r64["gbps"] / HBM_PEAK_GBPS,
                           "bytes_per_site": BYTES_PER_SITE["fp64"]}
         result["fp32_vs_fp64_field_error"] = {"u": float(eu), "T": float(eT),
@@ -261,7 +271,8 @@ def main():
     lat32.close()
     if not args.no_control:
         wc = W.rayleigh_benard(nx=8192, ny=4096)
-        latc, rc = run_precision(clb, W, "fp32", max(20, args.steps // 40), 10, stream.cuda_stream, wc)
+        latc, rc = run_precision(clb, W, "fp32", max(20, args.steps // 40), 10, stream.cuda_stream, wc,
+                                 args.autotune, args.tile_shape)
         latc.close()
         result["control_8192x4096"] = {"value": rc["mlups"], "unit": "MLUPS", "achieved_GBps": rc["gbps"],
                                        "frac": rc["gbps"] / HBM_PEAK_GBPS, "footprint_GB": 2 * 14 * 4 * 8192 * 4096 / 1e9}

@@ -178,7 +178,7 @@ int clb_tile_shape_info(int shape, int* tx, int* ty, int* spt, int* nontemporal)
 
 /* Select / read the shape used by clb_step.  A new handle starts with the shape the autotuner
  * last chose in this process for the same precision and size class (ceil(log2 nx),
- * ceil(log2 ny)), else shape 2. */
+ * ceil(log2 ny)), else shape 8 (FP32) or 6 (FP64). */
 int clb_set_tile_shape(clb_lattice* h, int shape);
 int clb_get_tile_shape(clb_lattice* h, int* shape);
 
