@@ -211,3 +211,22 @@ def test_persistent_with_small_and_large_lattices(gpu):
     for w, s in zip(ws, slots):
         for a, r in zip(b.moments(s), alone(w, "fp32", 148)):
             assert np.array_equal(a, r), w["name"]
+
+
+def test_served_fp32_matches_fp64_oracle(gpu):
+    """North-star accuracy of the served form: FP32 deviation storage, served through the batch,
+    against the FP64 oracle run for the same number of steps -- max-norm error of u (relative to the
+    convective scale Ma c_s) and of T (relative to max |T - T0|) within 1e-5."""
+    from paper_1710_10569_amd import serving as S
+    reqs = [S.Request(0, 0.0, 32, 5e3, 21), S.Request(1, 0.0, 40, 2e4, 22)]
+    srv = S.CavityServer(budget_bytes=64 << 20, capacity=8, chunk=1000, tol=1e-8, step_cap=15000,
+                         schedule="grouped", keep_fields=True)
+    out = srv.run(reqs)
+    srv.close()
+    for r in out:
+        w = W.cavity(r.L, Ra=r.Ra, seed=r.noise_seed)
+        o = oracle_from_workload(w)
+        o.step(r.steps)
+        e = field_errors(r.fields, o.moments(), w["T0"], w["u_scale"])
+        print(f"[batch] served L={r.L} Ra={r.Ra:g} steps={r.steps} {r.status}: {e}", flush=True)
+        assert e["u"] < 1e-5 and e["T"] < 1e-5, e
