@@ -47,7 +47,13 @@ enum {
     CLB_FP64 = 0,        /* f_i, g_i stored and collided in FP64 */
     CLB_FP32_DEV = 1,    /* stored and collided in FP32 as deviations f_i - w_i and g_i - w^T_i T0
                             from the rest equilibrium (w: D2Q9 weights; w^T = (1/2, 1/8 x 4)) */
-    CLB_FP64_DEV = 2     /* the deviation algebra of CLB_FP32_DEV carried out in FP64 */
+    CLB_FP64_DEV = 2,    /* the deviation algebra of CLB_FP32_DEV carried out in FP64 */
+    CLB_FP32_SR = 3      /* stored as FP32 deviations (as CLB_FP32_DEV, same bytes), collided in FP64,
+                            and rounded to FP32 on store stochastically (up or down with probability
+                            given by the dropped fraction, from a counter-based hash of node, step
+                            and population): unbiased storage rounding, so a long steady-state solve
+                            does not drift from the FP64 solution.  Deterministic: the same inputs
+                            and step count give bitwise the same state, alone or in a batch. */
 };
 
 /* Kind of an edge of the domain.  West/east must both be periodic or both walls; same for
@@ -66,7 +72,7 @@ typedef struct {
 
 typedef struct {
     int nx, ny;        /* nodes; >= 3 each, >= 4 along the normal of an adiabatic wall pair */
-    int precision;     /* CLB_FP64, CLB_FP32_DEV or CLB_FP64_DEV */
+    int precision;     /* CLB_FP64, CLB_FP32_DEV, CLB_FP64_DEV or CLB_FP32_SR */
     clb_edge west, east, south, north;
     double T0;         /* reference temperature of the Boussinesq force (Eq. 3) */
     int prescribed_u;  /* reserved, must be 0 */

@@ -28,9 +28,10 @@ _lib = ctypes.CDLL(LIBPATH)
 
 # enums of clb.h
 CLB_OK, CLB_EINVAL, CLB_ENOMEM, CLB_EDEVICE, CLB_ESTATE, CLB_EDIVERGED = 0, -1, -2, -3, -4, -5
-CLB_FP64, CLB_FP32_DEV, CLB_FP64_DEV = 0, 1, 2
+CLB_FP64, CLB_FP32_DEV, CLB_FP64_DEV, CLB_FP32_SR = 0, 1, 2, 3
 CLB_PERIODIC, CLB_WALL_DIRICHLET, CLB_WALL_ADIABATIC = 0, 1, 2
-PRECISIONS = {"fp64": CLB_FP64, "fp32": CLB_FP32_DEV, "fp32_dev": CLB_FP32_DEV, "fp64_dev": CLB_FP64_DEV}
+PRECISIONS = {"fp64": CLB_FP64, "fp32": CLB_FP32_DEV, "fp32_dev": CLB_FP32_DEV, "fp64_dev": CLB_FP64_DEV,
+              "fp32_sr": CLB_FP32_SR}
 KINDS = {"periodic": CLB_PERIODIC, "dirichlet": CLB_WALL_DIRICHLET, "adiabatic": CLB_WALL_ADIABATIC}
 
 

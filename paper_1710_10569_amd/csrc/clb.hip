@@ -39,7 +39,8 @@ void clear_error() { g_err[0] = 0; }
 int validate_desc(const clb_desc* d)
 {
     if (!d) { set_error("desc is NULL"); return CLB_EINVAL; }
-    if (d->precision != CLB_FP64 && d->precision != CLB_FP32_DEV && d->precision != CLB_FP64_DEV) {
+    if (d->precision != CLB_FP64 && d->precision != CLB_FP32_DEV && d->precision != CLB_FP64_DEV &&
+        d->precision != CLB_FP32_SR) {
         set_error("unknown precision %d", d->precision);
         return CLB_EINVAL;
     }
@@ -98,21 +99,23 @@ Geo make_geo(const clb_desc& d, int pitch, long long plane)
 // Launch helpers.
 
 
-static hipError_t launch_one_step(clb_lattice* h, int shape, const void* src, void* dst)
+static hipError_t launch_one_step(clb_lattice* h, int shape, const void* src, void* dst, long long step)
 {
     const clb_desc& d = h->desc;
     const Geo G = make_geo(d, h->pitch, h->plane);
+    const uint32_t key = step_key(uint32_t(step));
     switch (d.precision) {
-    case CLB_FP64: return launch_step_any<double, false>(shape, src, dst, G, make_par<double>(d, h->par), h->stream);
-    case CLB_FP64_DEV: return launch_step_any<double, true>(shape, src, dst, G, make_par<double>(d, h->par), h->stream);
-    default: return launch_step_any<float, true>(shape, src, dst, G, make_par<float>(d, h->par), h->stream);
+    case CLB_FP64: return launch_step_any<double, double, false>(shape, src, dst, G, make_par<double>(d, h->par), key, h->stream);
+    case CLB_FP64_DEV: return launch_step_any<double, double, true>(shape, src, dst, G, make_par<double>(d, h->par), key, h->stream);
+    case CLB_FP32_SR: return launch_step_any<float, double, true>(shape, src, dst, G, make_par<double>(d, h->par), key, h->stream);
+    default: return launch_step_any<float, float, true>(shape, src, dst, G, make_par<float>(d, h->par), key, h->stream);
     }
 }
 
 static int launch_step(clb_lattice* h, long long n)
 {
     for (long long s = 0; s < n; ++s) {
-        CLB_HIP(launch_one_step(h, h->shape, h->buf[h->cur], h->buf[h->cur ^ 1]));
+        CLB_HIP(launch_one_step(h, h->shape, h->buf[h->cur], h->buf[h->cur ^ 1], h->steps));
         h->cur ^= 1;
         h->steps += 1;
     }
@@ -130,14 +133,14 @@ static std::tuple<int, int, int> tune_key(const clb_desc& d)
 }
 
 // Without an autotuner result for the size class: 256 x 1 tiles, occupancy-8 register budget in
-// FP32 and non-temporal stores in FP64 (the fastest in sweeps on MI355X at 2048 x 1024 and
-// 8192 x 4096 in real ping-pong stepping).
+// FP32 and non-temporal stores in FP64; 128 x 4 tiles for FP32 storage with FP64 arithmetic (the
+// fastest in sweeps on MI355X at 2048 x 1024 and 8192 x 4096 in real ping-pong stepping).
 int default_shape(const clb_desc& d)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(tune_key(d));
     if (it != g_tune_cache.end()) return it->second;
-    return d.precision == CLB_FP32_DEV ? 8 : 6;
+    return d.precision == CLB_FP32_DEV ? 8 : d.precision == CLB_FP32_SR ? 4 : 6;
 }
 
 static int launch_moments(clb_lattice* h)
@@ -386,12 +389,12 @@ static int time_shape_impl(clb_lattice* h, int shape, int launches, void* const 
     void* src = scratch[0] ? scratch[0] : h->buf[h->cur];
     void* dst = scratch[0] ? scratch[1] : h->buf[h->cur ^ 1];
     for (int w = 0; w < 2; ++w) {
-        CLB_HIP(launch_one_step(h, shape, src, dst));
+        CLB_HIP(launch_one_step(h, shape, src, dst, w));
         if (scratch[0]) std::swap(src, dst);
     }
     CLB_HIP(hipEventRecord(h->ev[0], h->stream));
     for (int r = 0; r < launches; ++r) {
-        CLB_HIP(launch_one_step(h, shape, src, dst));
+        CLB_HIP(launch_one_step(h, shape, src, dst, 2 + r));
         if (scratch[0]) std::swap(src, dst);
     }
     CLB_HIP(hipEventRecord(h->ev[1], h->stream));

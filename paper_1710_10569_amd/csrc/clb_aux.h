@@ -31,8 +31,8 @@ __device__ __forceinline__ bool source_of(const Geo& G, int x, int y, int i, int
 // g_i^eq = T (c_T^2 +- u + u^2)/2 on the axes, T (1 - 2 c_T^2 - |u|^2) at rest, c_T^2 = 1/4.
 __device__ inline double psi(int e, double v) { return e == 0 ? 2.0 / 3.0 - v * v : 0.5 * (1.0 / 3.0 + e * v + v * v); }
 
-template <typename Real, bool DEV>
-__global__ void init_kernel(Real* __restrict__ buf, Geo G, const double* __restrict__ fields,
+template <typename S, bool DEV>
+__global__ void init_kernel(S* __restrict__ buf, Geo G, const double* __restrict__ fields,
                             double g_beta, double T0, double Fvx, double Fvy, double TR)
 {
     const int x = blockIdx.x * TX + threadIdx.x;
@@ -49,7 +49,7 @@ __global__ void init_kernel(Real* __restrict__ buf, Geo G, const double* __restr
         if (!source_of(G, x, y, i, sx, sy)) continue;
         double v = rho * psi(EXd[i], vx) * psi(EYd[i], vy);
         if (DEV) v -= W9[i];
-        buf[i * G.plane + (long long)sy * G.pitch + sx] = Real(v);
+        buf[i * G.plane + (long long)sy * G.pitch + sx] = S(v);
     }
     const double gq[5] = {T * (0.5 - ux * ux - uy * uy), 0.5 * T * (0.25 + ux + ux * ux),
                           0.5 * T * (0.25 + uy + uy * uy), 0.5 * T * (0.25 - ux + ux * ux),
@@ -59,12 +59,12 @@ __global__ void init_kernel(Real* __restrict__ buf, Geo G, const double* __restr
         if (!source_of(G, x, y, i, sx, sy)) continue;
         double v = gq[i];
         if (DEV) v -= W5[i] * TR;
-        buf[(9 + i) * G.plane + (long long)sy * G.pitch + sx] = Real(v);
+        buf[(9 + i) * G.plane + (long long)sy * G.pitch + sx] = S(v);
     }
 }
 
-template <typename Real, bool DEV>
-__global__ __launch_bounds__(TX * TY) void moments_kernel(const Real* __restrict__ src, Geo G, Par<Real> P,
+template <typename S, typename Real, bool DEV>
+__global__ __launch_bounds__(TX * TY) void moments_kernel(const S* __restrict__ src, Geo G, Par<Real> P,
                                                         double* __restrict__ fields)
 {
     const int x = blockIdx.x * TX + threadIdx.x;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(TX * TY) void moments_kernel(const Real* __restrict
     if (x >= G.nx || y >= G.ny) return;
     Real f[9], g[5];
     pull(src, G, x, y, f, g);
-    if (on_wall(G, x, y)) wall_step<Real, DEV>(src, G, P, x, y, f, g);
+    if (on_wall(G, x, y)) wall_step<S, Real, DEV>(src, G, P, x, y, f, g);
     const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
     const long long n = (long long)G.nx * G.ny;
     const long long k = (long long)y * G.nx + x;
@@ -82,14 +82,14 @@ __global__ __launch_bounds__(TX * TY) void moments_kernel(const Real* __restrict
     fields[3 * n + k] = double(P.TR) + double(m.dT);
 }
 
-template <typename Real, bool DEV>
-__global__ void populations_kernel(const Real* __restrict__ src, Geo G, double TR, double* __restrict__ fo,
+template <typename S, bool DEV>
+__global__ void populations_kernel(const S* __restrict__ src, Geo G, double TR, double* __restrict__ fo,
                                    double* __restrict__ go)
 {
     const int x = blockIdx.x * TX + threadIdx.x;
     const int y = blockIdx.y * TY + threadIdx.y;
     if (x >= G.nx || y >= G.ny) return;
-    Real f[9], g[5];
+    double f[9], g[5];
     pull(src, G, x, y, f, g);
     const long long n = (long long)G.nx * G.ny;
     const long long k = (long long)y * G.nx + x;
@@ -204,6 +204,7 @@ inline hipError_t enqueue_init(const clb_desc& d, const Params& p, void* buf, co
     switch (d.precision) {
     case CLB_FP64: init_kernel<double, false><<<grid, block, 0, st>>>((double*)buf, G, d_fields, p.g_beta, d.T0, p.Fvx, p.Fvy, TR); break;
     case CLB_FP64_DEV: init_kernel<double, true><<<grid, block, 0, st>>>((double*)buf, G, d_fields, p.g_beta, d.T0, p.Fvx, p.Fvy, TR); break;
+    case CLB_FP32_SR:
     default: init_kernel<float, true><<<grid, block, 0, st>>>((float*)buf, G, d_fields, p.g_beta, d.T0, p.Fvx, p.Fvy, TR); break;
     }
     return hipGetLastError();
@@ -214,9 +215,10 @@ inline hipError_t enqueue_moments(const clb_desc& d, const Params& p, const void
 {
     const dim3 grid = node_grid(G), block(TX, TY);
     switch (d.precision) {
-    case CLB_FP64: moments_kernel<double, false><<<grid, block, 0, st>>>((const double*)buf, G, make_par<double>(d, p), d_fields); break;
-    case CLB_FP64_DEV: moments_kernel<double, true><<<grid, block, 0, st>>>((const double*)buf, G, make_par<double>(d, p), d_fields); break;
-    default: moments_kernel<float, true><<<grid, block, 0, st>>>((const float*)buf, G, make_par<float>(d, p), d_fields); break;
+    case CLB_FP64: moments_kernel<double, double, false><<<grid, block, 0, st>>>((const double*)buf, G, make_par<double>(d, p), d_fields); break;
+    case CLB_FP64_DEV: moments_kernel<double, double, true><<<grid, block, 0, st>>>((const double*)buf, G, make_par<double>(d, p), d_fields); break;
+    case CLB_FP32_SR: moments_kernel<float, double, true><<<grid, block, 0, st>>>((const float*)buf, G, make_par<double>(d, p), d_fields); break;
+    default: moments_kernel<float, float, true><<<grid, block, 0, st>>>((const float*)buf, G, make_par<float>(d, p), d_fields); break;
     }
     return hipGetLastError();
 }
@@ -229,6 +231,7 @@ inline hipError_t enqueue_populations(const clb_desc& d, const void* buf, const 
     switch (d.precision) {
     case CLB_FP64: populations_kernel<double, false><<<grid, block, 0, st>>>((const double*)buf, G, TR, d_out, d_out + 9 * n); break;
     case CLB_FP64_DEV: populations_kernel<double, true><<<grid, block, 0, st>>>((const double*)buf, G, TR, d_out, d_out + 9 * n); break;
+    case CLB_FP32_SR:
     default: populations_kernel<float, true><<<grid, block, 0, st>>>((const float*)buf, G, TR, d_out, d_out + 9 * n); break;
     }
     return hipGetLastError();

@@ -39,6 +39,7 @@ struct BatchLat {
     long long off[2];   // element offsets of the two population buffers in the pool
     long long snap;     // byte offset of the FP64 (u_x, u_y, T) snapshot in the pool
     int cur;            // buffer holding the current post-collision state
+    uint32_t step;      // steps taken before the current call (low 32 bits): the rounding key base
     int tw_log2;        // tile width 1 << tw_log2 (6, 7 or 8); tile rows 256 >> tw_log2
     int tiles_x, ntiles;
 };
@@ -53,8 +54,8 @@ struct TileRef { int lat, tile; };
 
 constexpr int BNT = 256;
 
-template <typename Real, bool DEV, bool NT>
-__device__ __forceinline__ void batch_tile(Real* __restrict__ pool, const BatchEntry<Real>& E, int tile, int parity)
+template <typename S, typename Real, bool DEV, bool NT>
+__device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntry<Real>& E, int tile, int s)
 {
     const int tyi = tile / E.L.tiles_x, txi = tile - tyi * E.L.tiles_x;
     const int x = (txi << E.L.tw_log2) + int(threadIdx.x & ((1u << E.L.tw_log2) - 1));
@@ -62,31 +63,35 @@ __device__ __forceinline__ void batch_tile(Real* __restrict__ pool, const BatchE
     if (x >= E.L.G.nx || y >= E.L.G.ny) return;
     // select the buffers without indexing off[] by a runtime value (which would put the entry
     // in private memory)
-    const bool c = (E.L.cur ^ parity) != 0;
+    const bool c = (E.L.cur ^ (s & 1)) != 0;
     const long long o_src = c ? E.L.off[1] : E.L.off[0];
     const long long o_dst = c ? E.L.off[0] : E.L.off[1];
-    node_update<Real, DEV, NT>(pool + o_src, pool + o_dst, E.L.G, E.P, x, y);
+    node_update<S, Real, DEV, NT>(pool + o_src, pool + o_dst, E.L.G, E.P, x, y, step_key(E.L.step + uint32_t(s)));
 }
 
-template <typename Real, bool DEV, bool NT>
-__global__ __launch_bounds__(BNT) void batch_step_kernel(Real* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
+template <typename S, typename Real, bool DEV, bool NT>
+__global__ __launch_bounds__(BNT) void batch_step_kernel(S* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
                                                        const TileRef* __restrict__ tiles, int tile_base, int ntiles,
-                                                       int parity)
+                                                       int s)
 {
     const int q = int(gridDim.x >> 3);
     const int t = int(blockIdx.x & 7) * q + int(blockIdx.x >> 3);
     if (t >= ntiles) return;
     const TileRef r = tiles[tile_base + t];
     const BatchEntry<Real> E = lats[r.lat];
-    batch_tile<Real, DEV, NT>(pool, E, r.tile, parity);
+    batch_tile<S, Real, DEV, NT>(pool, E, r.tile, s);
 }
 
-// Flip the current-buffer index of every listed slot (after an odd number of steps).
+// After a call of nsteps steps: flip the current-buffer index of every listed slot if nsteps is
+// odd, and advance its step count.
 template <typename Real>
-__global__ void batch_flip_kernel(BatchEntry<Real>* lats, const int* slots, int n)
+__global__ void batch_advance_kernel(BatchEntry<Real>* lats, const int* slots, int n, int nsteps)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) lats[slots[i]].L.cur ^= 1;
+    if (i < n) {
+        lats[slots[i]].L.cur ^= nsteps & 1;
+        lats[slots[i]].L.step += uint32_t(nsteps);
+    }
 }
 
 __global__ void batch_zero_kernel(unsigned* p, int n)
@@ -99,8 +104,8 @@ __global__ void batch_zero_kernel(unsigned* p, int n)
 constexpr int RNT = 1024;
 constexpr long long kResidentMaxNodes = 128 * 128;
 
-template <typename Real, bool DEV>
-__global__ __launch_bounds__(RNT) void batch_resident_kernel(Real* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
+template <typename S, typename Real, bool DEV>
+__global__ __launch_bounds__(RNT) void batch_resident_kernel(S* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
                                                            const int* __restrict__ slots, int nslots, int nsteps)
 {
     if (int(blockIdx.x) >= nslots) return;
@@ -108,11 +113,11 @@ __global__ __launch_bounds__(RNT) void batch_resident_kernel(Real* __restrict__ 
     const int nx = E.L.G.nx, n = E.L.G.nx * E.L.G.ny;
     for (int s = 0; s < nsteps; ++s) {
         const bool c = (E.L.cur ^ (s & 1)) != 0;
-        const Real* src = pool + (c ? E.L.off[1] : E.L.off[0]);
-        Real* dst = pool + (c ? E.L.off[0] : E.L.off[1]);
+        const S* src = pool + (c ? E.L.off[1] : E.L.off[0]);
+        S* dst = pool + (c ? E.L.off[0] : E.L.off[1]);
         for (int k = int(threadIdx.x); k < n; k += RNT) {
             const int y = k / nx, x = k - y * nx;
-            node_update<Real, DEV, false>(src, dst, E.L.G, E.P, x, y);
+            node_update<S, Real, DEV, false>(src, dst, E.L.G, E.P, x, y, step_key(E.L.step + uint32_t(s)));
         }
         // every store of step s is visible to every load of step s + 1: all waves of the workgroup
         // are on one CU and share its L1
@@ -126,8 +131,8 @@ __global__ __launch_bounds__(RNT) void batch_resident_kernel(Real* __restrict__ 
 // |T - T'| and a non-finite flag are combined with atomic max on their IEEE bit patterns (all
 // values are non-negative, so the integer order is the numeric order and the result does not
 // depend on the order of the updates).
-template <typename Real, bool DEV>
-__global__ __launch_bounds__(BNT) void batch_residual_kernel(Real* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
+template <typename S, typename Real, bool DEV>
+__global__ __launch_bounds__(BNT) void batch_residual_kernel(S* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
                                                            const TileRef* __restrict__ tiles, int ntiles,
                                                            unsigned long long* __restrict__ res)
 {
@@ -141,10 +146,10 @@ __global__ __launch_bounds__(BNT) void batch_residual_kernel(Real* __restrict__ 
     const int y = tyi * (BNT >> E.L.tw_log2) + int(threadIdx.x >> E.L.tw_log2);
     double du = 0.0, dT = 0.0, bad = 0.0;
     if (x < E.L.G.nx && y < E.L.G.ny) {
-        const Real* src = pool + (E.L.cur ? E.L.off[1] : E.L.off[0]);
+        const S* src = pool + (E.L.cur ? E.L.off[1] : E.L.off[0]);
         Real f[9], g[5];
         pull(src, E.L.G, x, y, f, g);
-        if (on_wall(E.L.G, x, y)) wall_step<Real, DEV>(src, E.L.G, E.P, x, y, f, g);
+        if (on_wall(E.L.G, x, y)) wall_step<S, Real, DEV>(src, E.L.G, E.P, x, y, f, g);
         const Macro<Real, DEV> m = macro<Real, DEV>(f, g, E.P);
         const double ux = double(m.ux), uy = double(m.uy), T = double(E.P.TR) + double(m.dT);
         double* snap = reinterpret_cast<double*>(reinterpret_cast<char*>(pool) + E.L.snap);
@@ -248,7 +253,7 @@ struct clb_batch {
     size_t tiles_cap = 0;
     std::vector<TileRef> tiles;
     std::vector<int> first_tile, ntiles;
-    int* d_active = nullptr;              // slots in use (for the flip kernel)
+    int* d_active = nullptr;              // slots in use (for the advance kernel)
     int n_active = 0;
     bool dirty = true;
     hipStream_t side = nullptr;           // second stream for the workgroup-resident kernel
@@ -316,6 +321,7 @@ BatchEntry<Real> make_entry(const BatchSlot& s, int tw_log2)
     E.L.off[1] = s.off[1];
     E.L.snap = (long long)s.snap_off;
     E.L.cur = s.cur;
+    E.L.step = uint32_t(s.steps);
     E.L.tw_log2 = tw_log2;
     const int tw = 1 << tw_log2, th = BNT >> tw_log2;
     E.L.tiles_x = (s.desc.nx + tw - 1) / tw;
@@ -395,35 +401,36 @@ int upload_tables(clb_batch* b)
     return CLB_OK;
 }
 
-template <typename Real, bool DEV>
-hipError_t grouped_launch(clb_batch* b, const TileRef* tiles, int tile_base, int ntiles, int parity)
+template <typename S, typename Real, bool DEV>
+hipError_t grouped_launch(clb_batch* b, const TileRef* tiles, int tile_base, int ntiles, int s)
 {
     const int q = (ntiles + 7) / 8;
     if (b->nontemporal)
-        batch_step_kernel<Real, DEV, true><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
-            (Real*)b->pool, (const BatchEntry<Real>*)b->d_lats, tiles, tile_base, ntiles, parity);
+        batch_step_kernel<S, Real, DEV, true><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
+            (S*)b->pool, (const BatchEntry<Real>*)b->d_lats, tiles, tile_base, ntiles, s);
     else
-        batch_step_kernel<Real, DEV, false><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
-            (Real*)b->pool, (const BatchEntry<Real>*)b->d_lats, tiles, tile_base, ntiles, parity);
+        batch_step_kernel<S, Real, DEV, false><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
+            (S*)b->pool, (const BatchEntry<Real>*)b->d_lats, tiles, tile_base, ntiles, s);
     return hipGetLastError();
 }
 
-hipError_t grouped_any(clb_batch* b, int tile_base, int ntiles, int parity, const TileRef* tiles = nullptr)
+hipError_t grouped_any(clb_batch* b, int tile_base, int ntiles, int s, const TileRef* tiles = nullptr)
 {
     if (ntiles <= 0) return hipSuccess;
     if (!tiles) tiles = b->d_tiles;
     switch (b->precision) {
-    case CLB_FP64: return grouped_launch<double, false>(b, tiles, tile_base, ntiles, parity);
-    case CLB_FP64_DEV: return grouped_launch<double, true>(b, tiles, tile_base, ntiles, parity);
-    default: return grouped_launch<float, true>(b, tiles, tile_base, ntiles, parity);
+    case CLB_FP64: return grouped_launch<double, double, false>(b, tiles, tile_base, ntiles, s);
+    case CLB_FP64_DEV: return grouped_launch<double, double, true>(b, tiles, tile_base, ntiles, s);
+    case CLB_FP32_SR: return grouped_launch<float, double, true>(b, tiles, tile_base, ntiles, s);
+    default: return grouped_launch<float, float, true>(b, tiles, tile_base, ntiles, s);
     }
 }
 
-template <typename Real, bool DEV>
+template <typename S, typename Real, bool DEV>
 hipError_t resident_launch(clb_batch* b, int nsteps, hipStream_t st)
 {
     const int ns = int(b->small_slots.size());
-    batch_resident_kernel<Real, DEV><<<dim3(ns), dim3(RNT), 0, st>>>((Real*)b->pool, (const BatchEntry<Real>*)b->d_lats,
+    batch_resident_kernel<S, Real, DEV><<<dim3(ns), dim3(RNT), 0, st>>>((S*)b->pool, (const BatchEntry<Real>*)b->d_lats,
                                                                      b->d_small, ns, nsteps);
     return hipGetLastError();
 }
@@ -432,20 +439,21 @@ hipError_t resident_any(clb_batch* b, int nsteps, hipStream_t st)
 {
     if (b->small_slots.empty() || nsteps <= 0) return hipSuccess;
     switch (b->precision) {
-    case CLB_FP64: return resident_launch<double, false>(b, nsteps, st);
-    case CLB_FP64_DEV: return resident_launch<double, true>(b, nsteps, st);
-    default: return resident_launch<float, true>(b, nsteps, st);
+    case CLB_FP64: return resident_launch<double, double, false>(b, nsteps, st);
+    case CLB_FP64_DEV: return resident_launch<double, double, true>(b, nsteps, st);
+    case CLB_FP32_SR: return resident_launch<float, double, true>(b, nsteps, st);
+    default: return resident_launch<float, float, true>(b, nsteps, st);
     }
 }
 
-hipError_t flip_all(clb_batch* b)
+hipError_t advance_all(clb_batch* b, int nsteps)
 {
     if (b->n_active == 0) return hipSuccess;
     const int nb = (b->n_active + 255) / 256;
     if (b->precision == CLB_FP32_DEV)
-        batch_flip_kernel<float><<<nb, 256, 0, b->stream>>>((BatchEntry<float>*)b->d_lats, b->d_active, b->n_active);
+        batch_advance_kernel<float><<<nb, 256, 0, b->stream>>>((BatchEntry<float>*)b->d_lats, b->d_active, b->n_active, nsteps);
     else
-        batch_flip_kernel<double><<<nb, 256, 0, b->stream>>>((BatchEntry<double>*)b->d_lats, b->d_active, b->n_active);
+        batch_advance_kernel<double><<<nb, 256, 0, b->stream>>>((BatchEntry<double>*)b->d_lats, b->d_active, b->n_active, nsteps);
     return hipGetLastError();
 }
 
@@ -501,25 +509,30 @@ int step_impl(clb_batch* b, int mode, long long n)
                 CLB_HIP(hipEventRecord(b->join, b->side));
             }
             for (int s = 0; s < k; ++s)
-                CLB_HIP(grouped_any(b, 0, int(b->tiles_big.size()), s & 1, b->d_tiles_big));
+                CLB_HIP(grouped_any(b, 0, int(b->tiles_big.size()), s, b->d_tiles_big));
             if (!b->small_slots.empty()) CLB_HIP(hipStreamWaitEvent(b->stream, b->join, 0));
-            if (k & 1) CLB_HIP(flip_all(b));
+            CLB_HIP(advance_all(b, k));
             advance_host(b, k);
             done += k;
         }
         return CLB_OK;
     }
-    for (long long s = 0; s < n; ++s) {
-        const int parity = int(s & 1);
-        if (mode == MODE_GROUPED) {
-            CLB_HIP(grouped_any(b, 0, int(b->tiles.size()), parity));
-        } else {
-            for (int i = 0; i < b->capacity; ++i)
-                if (b->slots[i].used) CLB_HIP(grouped_any(b, b->first_tile[i], b->ntiles[i], parity));
+    // in chunks, so the call-relative step index passed to the kernels stays within int
+    const long long chunk = 1 << 20;
+    for (long long done = 0; done < n;) {
+        const int k = int(std::min(chunk, n - done));
+        for (int s = 0; s < k; ++s) {
+            if (mode == MODE_GROUPED) {
+                CLB_HIP(grouped_any(b, 0, int(b->tiles.size()), s));
+            } else {
+                for (int i = 0; i < b->capacity; ++i)
+                    if (b->slots[i].used) CLB_HIP(grouped_any(b, b->first_tile[i], b->ntiles[i], s));
+            }
         }
+        CLB_HIP(advance_all(b, k));
+        advance_host(b, k);
+        done += k;
     }
-    if (n & 1) CLB_HIP(flip_all(b));
-    advance_host(b, n);
     return CLB_OK;
 }
 
@@ -566,7 +579,7 @@ static int batch_create_impl(int capacity, int precision, size_t budget, void* p
                              clb_batch* b)
 {
     if (capacity <= 0 || capacity > (1 << 20)) { set_error("capacity must be in [1, 2^20]"); return CLB_EINVAL; }
-    if (precision != CLB_FP64 && precision != CLB_FP32_DEV && precision != CLB_FP64_DEV) {
+    if (precision != CLB_FP64 && precision != CLB_FP32_DEV && precision != CLB_FP64_DEV && precision != CLB_FP32_SR) {
         set_error("unknown precision %d", precision);
         return CLB_EINVAL;
     }
@@ -608,7 +621,7 @@ static int batch_create_impl(int capacity, int precision, size_t budget, void* p
     CLB_HIP(hipMalloc((void**)&b->d_res, sizeof(unsigned long long) * 3 * capacity));
     CLB_HIP(hipEventCreate(&b->ev[0]));
     CLB_HIP(hipEventCreate(&b->ev[1]));
-    b->nontemporal = precision != CLB_FP32_DEV;
+    b->nontemporal = precision == CLB_FP64 || precision == CLB_FP64_DEV;
     return CLB_OK;
 }
 
@@ -953,13 +966,13 @@ extern "C" int clb_batch_autotune(clb_batch* b, int launches)
     return upload_tables(b);
 }
 
-template <typename Real, bool DEV>
+template <typename S, typename Real, bool DEV>
 static hipError_t residual_launch(clb_batch* b)
 {
     const int nt = int(b->tiles.size());
     const int q = (nt + 7) / 8;
-    batch_residual_kernel<Real, DEV><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
-        (Real*)b->pool, (const BatchEntry<Real>*)b->d_lats, b->d_tiles, nt, b->d_res);
+    batch_residual_kernel<S, Real, DEV><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
+        (S*)b->pool, (const BatchEntry<Real>*)b->d_lats, b->d_tiles, nt, b->d_res);
     return hipGetLastError();
 }
 
@@ -976,9 +989,10 @@ extern "C" int clb_batch_residuals(clb_batch* b, double* du, double* dT, int* no
     CLB_HIP(hipGetLastError());
     if (!b->tiles.empty()) {
         switch (b->precision) {
-        case CLB_FP64: CLB_HIP((residual_launch<double, false>(b))); break;
-        case CLB_FP64_DEV: CLB_HIP((residual_launch<double, true>(b))); break;
-        default: CLB_HIP((residual_launch<float, true>(b))); break;
+        case CLB_FP64: CLB_HIP((residual_launch<double, double, false>(b))); break;
+        case CLB_FP64_DEV: CLB_HIP((residual_launch<double, double, true>(b))); break;
+        case CLB_FP32_SR: CLB_HIP((residual_launch<float, double, true>(b))); break;
+        default: CLB_HIP((residual_launch<float, float, true>(b))); break;
         }
     }
     std::vector<unsigned long long> host(n3);

@@ -8,6 +8,13 @@
 // `plane` elements long; node (x, y) of a plane is at y*pitch + x.  The buffer read by a step holds
 // post-collision values of the previous step at their source node, so f_i(x, t) = buf_i(x - e_i).
 //
+// The storage type S (what the buffers hold) and the arithmetic type Real may differ: populations
+// are converted on load and rounded once on store.  FP32 storage with FP64 arithmetic rounds
+// stochastically (store_node below): round-to-nearest repeats the same rounding error at every
+// step once the flow is (nearly) steady, and the slow modes of the steady solve integrate that
+// bias into a shift of the fixed point; rounding up or down at random, with probability set by
+// the dropped fraction, makes the store unbiased.
+//
 // Two storage forms share this code through the template flag DEV:
 //   DEV = false: buf holds f_i and g_i.
 //   DEV = true : buf holds f_i - w_i and g_i - w^T_i T0 (w: D2Q9 rest weights, w^T = (1/2, 1/8 x4)).
@@ -63,8 +70,8 @@ __device__ __forceinline__ T sel4(T v0, T v1, T v2, T v3, int i)
 // Pull: the 14 post-streaming populations of node (x, y).  Periodic directions wrap; in a
 // walled direction a source outside the domain is clamped to the edge -- the value read is then
 // meaningless and is replaced by the wall step.
-template <typename Real>
-__device__ __forceinline__ void pull(const Real* __restrict__ src, const Geo& G, int x, int y,
+template <typename S, typename Real>
+__device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, int x, int y,
                                      Real f[9], Real g[5])
 {
     const int xm = x > 0 ? x - 1 : (G.perx ? G.nx - 1 : 0);
@@ -73,35 +80,35 @@ __device__ __forceinline__ void pull(const Real* __restrict__ src, const Geo& G,
     const int yp = y < G.ny - 1 ? y + 1 : (G.pery ? 0 : G.ny - 1);
     const int rc = y * G.pitch, rm = ym * G.pitch, rp = yp * G.pitch;
     const long long P = G.plane;
-    f[0] = src[0 * P + rc + x];
-    f[1] = src[1 * P + rc + xm];
-    f[2] = src[2 * P + rm + x];
-    f[3] = src[3 * P + rc + xp];
-    f[4] = src[4 * P + rp + x];
-    f[5] = src[5 * P + rm + xm];
-    f[6] = src[6 * P + rm + xp];
-    f[7] = src[7 * P + rp + xp];
-    f[8] = src[8 * P + rp + xm];
-    g[0] = src[9 * P + rc + x];
-    g[1] = src[10 * P + rc + xm];
-    g[2] = src[11 * P + rm + x];
-    g[3] = src[12 * P + rc + xp];
-    g[4] = src[13 * P + rp + x];
+    f[0] = Real(src[0 * P + rc + x]);
+    f[1] = Real(src[1 * P + rc + xm]);
+    f[2] = Real(src[2 * P + rm + x]);
+    f[3] = Real(src[3 * P + rc + xp]);
+    f[4] = Real(src[4 * P + rp + x]);
+    f[5] = Real(src[5 * P + rm + xm]);
+    f[6] = Real(src[6 * P + rm + xp]);
+    f[7] = Real(src[7 * P + rp + xp]);
+    f[8] = Real(src[8 * P + rp + xm]);
+    g[0] = Real(src[9 * P + rc + x]);
+    g[1] = Real(src[10 * P + rc + xm]);
+    g[2] = Real(src[11 * P + rm + x]);
+    g[3] = Real(src[12 * P + rc + xp]);
+    g[4] = Real(src[13 * P + rp + x]);
 }
 
-template <typename Real>
-__device__ __forceinline__ void pull_g(const Real* __restrict__ src, const Geo& G, int x, int y, Real g[5])
+template <typename S, typename Real>
+__device__ __forceinline__ void pull_g(const S* __restrict__ src, const Geo& G, int x, int y, Real g[5])
 {
     const int xm = x > 0 ? x - 1 : (G.perx ? G.nx - 1 : 0);
     const int xp = x < G.nx - 1 ? x + 1 : (G.perx ? 0 : G.nx - 1);
     const int ym = y > 0 ? y - 1 : (G.pery ? G.ny - 1 : 0);
     const int yp = y < G.ny - 1 ? y + 1 : (G.pery ? 0 : G.ny - 1);
     const long long P = G.plane;
-    g[0] = src[9 * P + y * G.pitch + x];
-    g[1] = src[10 * P + y * G.pitch + xm];
-    g[2] = src[11 * P + ym * G.pitch + x];
-    g[3] = src[12 * P + y * G.pitch + xp];
-    g[4] = src[13 * P + yp * G.pitch + x];
+    g[0] = Real(src[9 * P + y * G.pitch + x]);
+    g[1] = Real(src[10 * P + y * G.pitch + xm]);
+    g[2] = Real(src[11 * P + ym * G.pitch + x]);
+    g[3] = Real(src[12 * P + y * G.pitch + xp]);
+    g[4] = Real(src[13 * P + yp * G.pitch + x]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -218,8 +225,8 @@ __device__ __forceinline__ void zou_he(Real f[9], int nx, int ny, Real uwx, Real
 //      at the equilibrium velocities u_w - F_b/(2 rho_f) and u_f - F_f/(2 rho_f).
 // Corner data: velocity of the west/east wall; temperature of a Dirichlet wall if one meets
 // there, the west/east wall's otherwise.
-template <typename Real, bool DEV>
-__device__ __forceinline__ void wall_step(const Real* __restrict__ src, const Geo& G, const Par<Real>& P,
+template <typename S, typename Real, bool DEV>
+__device__ __forceinline__ void wall_step(const S* __restrict__ src, const Geo& G, const Par<Real>& P,
                                        int x, int y, Real f[9], Real g[5])
 {
     const bool onW = !G.perx && x == 0, onE = !G.perx && x == G.nx - 1;
@@ -378,73 +385,101 @@ __device__ __forceinline__ void collide_g(Real g[5], const Macro<Real, DEV>& m, 
 // ---------------------------------------------------------------------------------------------
 // The whole node update: pull, wall step (wall nodes only), macroscopic, both collisions, and the
 // store of the 14 post-collision populations at the node itself.  NT selects non-temporal stores.
-template <typename Real, bool DEV, bool NT>
-__device__ __forceinline__ void node_update(const Real* __restrict__ src, Real* __restrict__ dst, const Geo& G,
-                                            const Par<Real>& P, int x, int y)
+// MurmurHash3's 32-bit finalizer (Appleby): a bijective mixer with full avalanche, used as a
+// counter-based generator (distinct counters give distinct, well-mixed words).
+__host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// Key of the random words of one time step of a lattice (step: number of steps taken before it).
+__host__ __device__ __forceinline__ uint32_t step_key(uint32_t step) { return fmix32(step * 0x9e3779b9u + 0x7f4a7c15u); }
+
+// FP64 -> FP32 with stochastic rounding, u a uniform 16-bit word: the 29 mantissa bits FP32 drops
+// are offset by a uniform random amount and cut off, so |v| is rounded up with probability
+// (dropped part) / (FP32 spacing) to within 2^-17, and down otherwise (carries into the exponent
+// are the step to the next binade).  The truncated value has at most 24 significant bits, so the
+// conversion to FP32 is exact in FP32's normal range; NaN stays NaN, +-inf stay inf.
+__device__ __forceinline__ float round_stochastic(double v, uint32_t u)
+{
+    uint64_t b = uint64_t(__double_as_longlong(v));
+    b += (uint64_t(u & 0xffffu) << 13) | (uint64_t(1) << 12);
+    b &= ~((uint64_t(1) << 29) - 1);
+    return float(__longlong_as_double((long long)b));
+}
+
+// Store the 14 post-collision populations of node `node` (= y * nx + x) at offset o.  For FP32
+// storage of FP64 values each pair of populations takes one word fmix32(8 node + pair + key), so
+// the rounding of a node depends only on (node, step), never on the tile shape or the batch.
+template <typename S, typename Real, bool NT>
+__device__ __forceinline__ void store_node(S* __restrict__ dst, long long PL, int o, const Real f[9], const Real g[5],
+                                           uint32_t key, uint32_t node)
+{
+    S v[14];
+    if constexpr (sizeof(S) == 4 && sizeof(Real) == 8) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const uint32_t r = fmix32(node * 8u + uint32_t(k) + key);
+            const Real a = 2 * k < 9 ? f[2 * k] : g[2 * k - 9];
+            const Real c = 2 * k + 1 < 9 ? f[2 * k + 1] : g[2 * k + 1 - 9];
+            v[2 * k] = round_stochastic(a, r);
+            v[2 * k + 1] = round_stochastic(c, r >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = S(f[i]);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) v[9 + i] = S(g[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 14; ++i) {
+        if (NT) __builtin_nontemporal_store(v[i], dst + i * PL + o);
+        else dst[i * PL + o] = v[i];
+    }
+}
+
+// The whole update of node (x, y) of one step; key = step_key(step) (used by FP32 storage of
+// FP64 arithmetic only).
+template <typename S, typename Real, bool DEV, bool NT>
+__device__ __forceinline__ void node_update(const S* __restrict__ src, S* __restrict__ dst, const Geo& G,
+                                            const Par<Real>& P, int x, int y, uint32_t key)
 {
     Real f[9], g[5];
     pull(src, G, x, y, f, g);
-    if (on_wall(G, x, y)) wall_step<Real, DEV>(src, G, P, x, y, f, g);
+    if (on_wall(G, x, y)) wall_step<S, Real, DEV>(src, G, P, x, y, f, g);
     const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
     collide_f<Real, DEV>(f, m, P);
     collide_g<Real, DEV>(g, m, P);
-    const long long PL = G.plane;
-    const int o = y * G.pitch + x;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        if (NT) __builtin_nontemporal_store(f[i], dst + i * PL + o);
-        else dst[i * PL + o] = f[i];
-    }
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        if (NT) __builtin_nontemporal_store(g[i], dst + (9 + i) * PL + o);
-        else dst[(9 + i) * PL + o] = g[i];
-    }
+    store_node<S, Real, NT>(dst, G.plane, y * G.pitch + x, f, g, key, uint32_t(y) * uint32_t(G.nx) + uint32_t(x));
 }
 
 // Two nodes of one column, (x, y0) and (x, y1): both pulls are issued before either update is
 // computed, so a thread has 28 loads in flight instead of 14.
-template <typename Real, bool DEV, bool NT>
-__device__ __forceinline__ void node_update2(const Real* __restrict__ src, Real* __restrict__ dst, const Geo& G,
-                                             const Par<Real>& P, int x, int y0, int y1)
+template <typename S, typename Real, bool DEV, bool NT>
+__device__ __forceinline__ void node_update2(const S* __restrict__ src, S* __restrict__ dst, const Geo& G,
+                                             const Par<Real>& P, int x, int y0, int y1, uint32_t key)
 {
     Real fa[9], ga[5], fb[9], gb[5];
     pull(src, G, x, y0, fa, ga);
     pull(src, G, x, y1, fb, gb);
-    if (on_wall(G, x, y0)) wall_step<Real, DEV>(src, G, P, x, y0, fa, ga);
-    if (on_wall(G, x, y1)) wall_step<Real, DEV>(src, G, P, x, y1, fb, gb);
-    const long long PL = G.plane;
+    if (on_wall(G, x, y0)) wall_step<S, Real, DEV>(src, G, P, x, y0, fa, ga);
+    if (on_wall(G, x, y1)) wall_step<S, Real, DEV>(src, G, P, x, y1, fb, gb);
     {
         const Macro<Real, DEV> m = macro<Real, DEV>(fa, ga, P);
         collide_f<Real, DEV>(fa, m, P);
         collide_g<Real, DEV>(ga, m, P);
-        const int o = y0 * G.pitch + x;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            if (NT) __builtin_nontemporal_store(fa[i], dst + i * PL + o);
-            else dst[i * PL + o] = fa[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            if (NT) __builtin_nontemporal_store(ga[i], dst + (9 + i) * PL + o);
-            else dst[(9 + i) * PL + o] = ga[i];
-        }
+        store_node<S, Real, NT>(dst, G.plane, y0 * G.pitch + x, fa, ga, key, uint32_t(y0) * uint32_t(G.nx) + uint32_t(x));
     }
     {
         const Macro<Real, DEV> m = macro<Real, DEV>(fb, gb, P);
         collide_f<Real, DEV>(fb, m, P);
         collide_g<Real, DEV>(gb, m, P);
-        const int o = y1 * G.pitch + x;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            if (NT) __builtin_nontemporal_store(fb[i], dst + i * PL + o);
-            else dst[i * PL + o] = fb[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            if (NT) __builtin_nontemporal_store(gb[i], dst + (9 + i) * PL + o);
-            else dst[(9 + i) * PL + o] = gb[i];
-        }
+        store_node<S, Real, NT>(dst, G.plane, y1 * G.pitch + x, fb, gb, key, uint32_t(y1) * uint32_t(G.nx) + uint32_t(x));
     }
 }
 

@@ -31,7 +31,7 @@ void clear_error();
 // Row pitch in elements: rows start on 256-byte boundaries.
 inline int row_pitch(int nx, size_t elem) { const int a = int(256 / elem); return (nx + a - 1) / a * a; }
 
-inline size_t elem_bytes(int precision) { return precision == CLB_FP32_DEV ? 4 : 8; }
+inline size_t elem_bytes(int precision) { return (precision == CLB_FP32_DEV || precision == CLB_FP32_SR) ? 4 : 8; }
 inline bool is_dev(int precision) { return precision != CLB_FP64; }
 
 // Validate a lattice description; returns CLB_OK or CLB_EINVAL with a message.

@@ -39,9 +39,10 @@ __host__ __device__ constexpr TileShape tile_shape(int i)
 inline int tiles_x_of(const Geo& G, const TileShape& s) { return (G.nx + s.tx - 1) / s.tx; }
 inline int tiles_y_of(const Geo& G, const TileShape& s) { return (G.ny + s.ty * s.spt - 1) / (s.ty * s.spt); }
 
-template <typename Real, bool DEV, int TXW, int TY, int SPT, bool NT, int WPE>
-__global__ __launch_bounds__(TXW * TY, WPE) void step_tile_kernel(const Real* __restrict__ src, Real* __restrict__ dst,
-                                                                 Geo G, Par<Real> P, int tiles_x, int ntiles)
+template <typename S, typename Real, bool DEV, int TXW, int TY, int SPT, bool NT, int WPE>
+__global__ __launch_bounds__(TXW * TY, WPE) void step_tile_kernel(const S* __restrict__ src, S* __restrict__ dst,
+                                                                 Geo G, Par<Real> P, int tiles_x, int ntiles,
+                                                                 uint32_t key)
 {
     const int q = int(gridDim.x >> 3);
     const int t = int(blockIdx.x & 7) * q + int(blockIdx.x >> 3);
@@ -51,41 +52,42 @@ __global__ __launch_bounds__(TXW * TY, WPE) void step_tile_kernel(const Real* __
     const int y0 = tyi * (TY * SPT) + int(threadIdx.x / TXW);
     if (x >= G.nx) return;
     if (SPT == 1) {
-        if (y0 < G.ny) node_update<Real, DEV, NT>(src, dst, G, P, x, y0);
+        if (y0 < G.ny) node_update<S, Real, DEV, NT>(src, dst, G, P, x, y0, key);
     } else {
         const int y1 = y0 + TY;
-        if (y1 < G.ny) node_update2<Real, DEV, NT>(src, dst, G, P, x, y0, y1);
-        else if (y0 < G.ny) node_update<Real, DEV, NT>(src, dst, G, P, x, y0);
+        if (y1 < G.ny) node_update2<S, Real, DEV, NT>(src, dst, G, P, x, y0, y1, key);
+        else if (y0 < G.ny) node_update<S, Real, DEV, NT>(src, dst, G, P, x, y0, key);
     }
 }
 
-// Enqueue one step from src into dst with shape S.
-template <typename Real, bool DEV, int S>
-hipError_t launch_step_shape(const void* src, void* dst, const Geo& G, const Par<Real>& P, hipStream_t st)
+// Enqueue one step from src into dst with shape SH; key = step_key(number of steps taken before).
+template <typename S, typename Real, bool DEV, int SH>
+hipError_t launch_step_shape(const void* src, void* dst, const Geo& G, const Par<Real>& P, uint32_t key, hipStream_t st)
 {
-    constexpr TileShape sh = tile_shape(S);
+    constexpr TileShape sh = tile_shape(SH);
     const int tx = tiles_x_of(G, sh), ntiles = tx * tiles_y_of(G, sh);
     const int q = (ntiles + 7) / 8;
-    step_tile_kernel<Real, DEV, sh.tx, sh.ty, sh.spt, sh.nt != 0, (sh.wpe > 0 ? sh.wpe : 1)><<<dim3(8 * q), dim3(sh.tx * sh.ty), 0, st>>>(
-        (const Real*)src, (Real*)dst, G, P, tx, ntiles);
+    step_tile_kernel<S, Real, DEV, sh.tx, sh.ty, sh.spt, sh.nt != 0, (sh.wpe > 0 ? sh.wpe : 1)><<<dim3(8 * q), dim3(sh.tx * sh.ty), 0, st>>>(
+        (const S*)src, (S*)dst, G, P, tx, ntiles, key);
     return hipGetLastError();
 }
 
-template <typename Real, bool DEV>
-hipError_t launch_step_any(int shape, const void* src, void* dst, const Geo& G, const Par<Real>& P, hipStream_t st)
+template <typename S, typename Real, bool DEV>
+hipError_t launch_step_any(int shape, const void* src, void* dst, const Geo& G, const Par<Real>& P, uint32_t key,
+                           hipStream_t st)
 {
     switch (shape) {
-    case 0: return launch_step_shape<Real, DEV, 0>(src, dst, G, P, st);
-    case 1: return launch_step_shape<Real, DEV, 1>(src, dst, G, P, st);
-    case 2: return launch_step_shape<Real, DEV, 2>(src, dst, G, P, st);
-    case 3: return launch_step_shape<Real, DEV, 3>(src, dst, G, P, st);
-    case 4: return launch_step_shape<Real, DEV, 4>(src, dst, G, P, st);
-    case 5: return launch_step_shape<Real, DEV, 5>(src, dst, G, P, st);
-    case 6: return launch_step_shape<Real, DEV, 6>(src, dst, G, P, st);
-    case 7: return launch_step_shape<Real, DEV, 7>(src, dst, G, P, st);
-    case 8: return launch_step_shape<Real, DEV, 8>(src, dst, G, P, st);
-    case 9: return launch_step_shape<Real, DEV, 9>(src, dst, G, P, st);
-    default: return launch_step_shape<Real, DEV, 10>(src, dst, G, P, st);
+    case 0: return launch_step_shape<S, Real, DEV, 0>(src, dst, G, P, key, st);
+    case 1: return launch_step_shape<S, Real, DEV, 1>(src, dst, G, P, key, st);
+    case 2: return launch_step_shape<S, Real, DEV, 2>(src, dst, G, P, key, st);
+    case 3: return launch_step_shape<S, Real, DEV, 3>(src, dst, G, P, key, st);
+    case 4: return launch_step_shape<S, Real, DEV, 4>(src, dst, G, P, key, st);
+    case 5: return launch_step_shape<S, Real, DEV, 5>(src, dst, G, P, key, st);
+    case 6: return launch_step_shape<S, Real, DEV, 6>(src, dst, G, P, key, st);
+    case 7: return launch_step_shape<S, Real, DEV, 7>(src, dst, G, P, key, st);
+    case 8: return launch_step_shape<S, Real, DEV, 8>(src, dst, G, P, key, st);
+    case 9: return launch_step_shape<S, Real, DEV, 9>(src, dst, G, P, key, st);
+    default: return launch_step_shape<S, Real, DEV, 10>(src, dst, G, P, key, st);
     }
 }
 

@@ -49,11 +49,13 @@ class Request:
 class CavityServer:
     """Serve cavity requests through one clb.Batch.
 
-    budget_bytes: HBM pool for resident lattices; capacity: slots; chunk: steps between residual
+    budget_bytes: HBM pool for resident lattices; capacity: slots; precision: storage/arithmetic
+    mode (default FP32 storage, FP64 collision, stochastic rounding on store, whose steady states stay
+    within ~1e-7 of the FP64 ones; plain FP32 drifts to ~1e-5); chunk: steps between residual
     checks; tol: max-norm change of u and of T per chunk that counts as steady; step_cap: give up
     after this many steps; schedule: 'grouped' or 'persistent'; keep_fields: return (rho, ux, uy, T)."""
 
-    def __init__(self, budget_bytes=16 << 30, capacity=1024, precision="fp32", chunk=1000, tol=1e-8,
+    def __init__(self, budget_bytes=16 << 30, capacity=1024, precision="fp32_sr", chunk=1000, tol=1e-8,
                  step_cap=5_000_000, schedule="persistent", Pr=0.71, Ma=0.1, keep_fields=False,
                  floor_patience=20, stream=None):
         self.batch = clb.Batch(capacity, precision, budget_bytes=budget_bytes, stream=stream)

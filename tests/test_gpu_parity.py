@@ -91,7 +91,7 @@ def test_cavity_256_fp64(gpu):
         assert max(e.values()) < FP64_TOL, e
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL), ("fp32_sr", FP32_TOL)])
 def test_rayleigh_benard_full_size(gpu, precision, tol):
     """2048 x 1024 Rayleigh-Benard at Ra = 1e6, Ma = 0.3, 4 steps, every node compared."""
     w = W.rayleigh_benard()
@@ -100,17 +100,19 @@ def test_rayleigh_benard_full_size(gpu, precision, tol):
         assert e["u"] < tol and e["T"] < tol, e
 
 
-def test_fp32_taylor_green(gpu):
+@pytest.mark.parametrize("precision", ["fp32", "fp32_sr"])
+def test_fp32_taylor_green(gpu, precision):
     w = W.taylor_green(64)
-    _, _, errs = run_pair(w, "fp32", 1000, chunks=2)
+    _, _, errs = run_pair(w, precision, 1000, chunks=2)
     for e in errs:
         assert e["u"] < FP32_TOL and e["T"] < FP32_TOL, e
 
 
-def test_fp32_cavity(gpu):
+@pytest.mark.parametrize("precision", ["fp32", "fp32_sr"])
+def test_fp32_cavity(gpu, precision):
     """FP32 deviation storage on the 256 x 256 cavity, 3000 steps, against the FP64 oracle."""
     w = W.cavity(256)
-    _, _, errs = run_pair(w, "fp32", 3000, chunks=3)
+    _, _, errs = run_pair(w, precision, 3000, chunks=3)
     for e in errs:
         assert e["u"] < FP32_TOL and e["T"] < FP32_TOL, e
 
@@ -196,7 +198,7 @@ def test_host_side_errors(gpu):
     g.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_sr"])
 def test_every_tile_shape_gives_identical_results(gpu, precision):
     """Each compiled tile shape (and the XCD-ordered tile mapping) computes the same per-node
     update, so the lattice after 50 steps is bitwise identical whatever the shape; shape 0 also

@@ -92,3 +92,26 @@ def test_table1_nusselt_batch_fp32(gpu):
     print("[physics] Table 1 on GPU:", [(ra, round(nu, 4), f"{e:+.2%}") for ra, nu, e in out], flush=True)
     for ra, nu, e in out:
         assert abs(e) < (5e-3 if ra <= 20000 else 1.5e-2), (ra, nu, e)
+
+
+def test_critical_rayleigh_number_batch(gpu):
+    """Sec. 3.3: Rayleigh-Benard cells (60 x 30, Pr = 0.71, Ma = 0.3) at Ra = 1702 ... 1710, all in
+    one FP64 batch.  After the start-up transient the velocity maximum grows or decays exponentially
+    at a rate linear in Ra; the least-squares zero of that rate is the critical Rayleigh number
+    (linear stability 1707.76; the paper measures 1706.82)."""
+    clb = _clb()
+    Ras = [1702.0, 1704.0, 1706.0, 1708.0, 1710.0]
+    b = clb.Batch(len(Ras), "fp64", budget_bytes=64 << 20)
+    slots = [b.add_workload(W.rb_cell(Ra, T_hot=0.05, T_cold=-0.05)) for Ra in Ras]
+    b.step(60000)
+    ts, logs = [], [[] for _ in Ras]
+    for k in range(16):
+        b.step(10000)
+        ts.append(70000 + 10000 * k)
+        for i, s in enumerate(slots):
+            logs[i].append(math.log(b.diagnostics(s)["u_max"]))
+    rates = [np.polyfit(ts, l, 1)[0] for l in logs]
+    slope, icpt = np.polyfit(Ras, rates, 1)
+    ra_c = -icpt / slope
+    print(f"[physics] growth rates {['%.3e' % r for r in rates]} -> Ra_c = {ra_c:.2f}", flush=True)
+    assert abs(ra_c - 1707.76) < 0.005 * 1707.76
