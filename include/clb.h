@@ -276,9 +276,15 @@ int clb_batch_time_steps(clb_batch* b, int mode, long long n, double* ms);
 /* Tile width (64, 128 or 256 nodes per row segment; 256 nodes per tile) of one lattice. */
 int clb_batch_set_tile_width(clb_batch* b, int slot, int tile_width);
 
+/* Store form of the batch's step kernels: 1 = non-temporal stores (populations written this step
+ * are read next step, but at batch footprints they leave every cache before that), 0 = ordinary
+ * stores.  Default: 1 for FP64 storage, 0 for FP32 storage.  Results do not depend on it. */
+int clb_batch_set_nontemporal(clb_batch* b, int nontemporal);
+
 /* For each size class (ceil(log2 nx), ceil(log2 ny)) present, time the grouped step over that
  * class's lattices with each tile width (state unchanged) and keep the fastest for the class;
- * lattices added later take the class's choice.  Synchronises. */
+ * lattices added later take the class's choice.  Then time the grouped step over the whole batch
+ * with ordinary and with non-temporal stores and keep the faster.  Synchronises. */
 int clb_batch_autotune(clb_batch* b, int launches);
 
 /* Lattices resident, pool bytes in use, pool size, total nodes.  Any output may be NULL. */

@@ -297,6 +297,7 @@ _sig("clb_batch_check", ctypes.c_int, [_B])
 _sig("clb_batch_time_steps", ctypes.c_int, [_B, ctypes.c_int, ctypes.c_longlong, _dp])
 _sig("clb_batch_set_tile_width", ctypes.c_int, [_B, ctypes.c_int, ctypes.c_int])
 _sig("clb_batch_autotune", ctypes.c_int, [_B, ctypes.c_int])
+_sig("clb_batch_set_nontemporal", ctypes.c_int, [_B, ctypes.c_int])
 _sig("clb_batch_info", ctypes.c_int, [_B, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t),
                                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_longlong)])
 _sig("clb_batch_synchronize", ctypes.c_int, [_B])
@@ -418,6 +419,9 @@ class Batch:
 
     def autotune(self, launches=5):
         _check(_lib.clb_batch_autotune(self._h, int(launches)))
+
+    def set_nontemporal(self, on):
+        _check(_lib.clb_batch_set_nontemporal(self._h, int(bool(on))))
 
     def synchronize(self):
         _check(_lib.clb_batch_synchronize(self._h))

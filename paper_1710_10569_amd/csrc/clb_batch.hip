@@ -963,7 +963,33 @@ extern "C" int clb_batch_autotune(clb_batch* b, int launches)
         for (int i : kv.second) b->slots[i].tw_log2 = best;
     }
     b->dirty = true;
-    return upload_tables(b);
+    int rc = upload_tables(b);
+    if (rc) return rc;
+    // store form over the whole batch (reads the current state, writes the spare buffers)
+    const int nt = int(b->tiles.size());
+    if (nt == 0) return CLB_OK;
+    double t_store[2] = {0.0, 0.0};
+    for (int v = 0; v < 2; ++v) {
+        b->nontemporal = v != 0;
+        for (int w = 0; w < 2; ++w) CLB_HIP(grouped_any(b, 0, nt, 0));
+        CLB_HIP(hipEventRecord(b->ev[0], b->stream));
+        for (int r = 0; r < launches; ++r) CLB_HIP(grouped_any(b, 0, nt, 0));
+        CLB_HIP(hipEventRecord(b->ev[1], b->stream));
+        CLB_HIP(hipEventSynchronize(b->ev[1]));
+        float ms = 0.0f;
+        CLB_HIP(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+        t_store[v] = ms;
+    }
+    b->nontemporal = t_store[1] < t_store[0];
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_set_nontemporal(clb_batch* b, int nontemporal)
+{
+    clear_error();
+    if (!b) { set_error("batch is NULL"); return CLB_EINVAL; }
+    b->nontemporal = nontemporal != 0;
+    return CLB_OK;
 }
 
 template <typename S, typename Real, bool DEV>

@@ -179,27 +179,45 @@ __host__ __device__ constexpr int ey_of(int i) { return i == 2 || i == 5 || i ==
 //   rho = (sum_{b=0} f + 2 sum_{b=-1} f - F_n/2) / (1 - u_n),  D = rho u_n (2/3 - u_t^2),
 //   f(0,1) = f(0,-1) + D,
 //   f(+-1,1) = f(-+1,-1) -+ (f(1,0) - f(-1,0))/2 +- (rho u_t - F_t/2)/2 + (rho u_n - F_n/2 - D)/2.
-// The loops run over compile-time directions and select by the runtime normal, so f stays in
-// registers (no indexing of f by a runtime value).
+// The four normals are numbered 0: (1, 0) (west wall), 1: (-1, 0) (east), 2: (0, 1) (south),
+// 3: (0, -1) (north).  zdir<K>(a, b) is the direction with wall-frame components (a, b) for normal
+// K, i.e. e = a t + b n; at<A, B>(f, k) gathers f(A, B) for the runtime normal k with one 4-way
+// select, so the formula is evaluated once, in the wall frame, with f in registers.
+__host__ __device__ constexpr int zdir_of(int ex, int ey)
+{
+    return ex == 0 ? (ey == 0 ? 0 : (ey == 1 ? 2 : 4))
+         : ex == 1 ? (ey == 0 ? 1 : (ey == 1 ? 5 : 8))
+                   : (ey == 0 ? 3 : (ey == 1 ? 6 : 7));
+}
+__host__ __device__ constexpr int znx(int k) { return k == 0 ? 1 : (k == 1 ? -1 : 0); }
+__host__ __device__ constexpr int zny(int k) { return k == 2 ? 1 : (k == 3 ? -1 : 0); }
+__host__ __device__ constexpr int zdir(int k, int a, int b)
+{
+    return zdir_of(a * zny(k) + b * znx(k), -a * znx(k) + b * zny(k));
+}
+template <int A, int B, typename Real>
+__device__ __forceinline__ Real at(const Real f[9], int k)
+{
+    return sel4(f[zdir(0, A, B)], f[zdir(1, A, B)], f[zdir(2, A, B)], f[zdir(3, A, B)], k);
+}
+// frame component b = e.n of direction i for normal k, and a = e.t
+__host__ __device__ constexpr int zb(int k, int i) { return ex_of(i) * znx(k) + ey_of(i) * zny(k); }
+__host__ __device__ constexpr int za(int k, int i) { return ex_of(i) * zny(k) - ey_of(i) * znx(k); }
+
 template <typename Real, bool DEV>
 __device__ __forceinline__ void zou_he(Real f[9], int nx, int ny, Real uwx, Real uwy, Real Fx, Real Fy)
 {
-    const int tx = ny, ty = -nx;
+    const int k = nx == 1 ? 0 : (nx == -1 ? 1 : (ny == 1 ? 2 : 3));
+    const Real tx = Real(ny), ty = Real(-nx);
     const Real un = uwx * Real(nx) + uwy * Real(ny);
-    const Real ut = uwx * Real(tx) + uwy * Real(ty);
+    const Real ut = uwx * tx + uwy * ty;
     const Real Fn = Fx * Real(nx) + Fy * Real(ny);
-    const Real Ft = Fx * Real(tx) + Fy * Real(ty);
-    Real K0 = Real(0), Km = Real(0), d0 = Real(0), fZM = Real(0), fPM = Real(0), fMM = Real(0);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int a = ex_of(i) * tx + ey_of(i) * ty, b = ex_of(i) * nx + ey_of(i) * ny;
-        K0 += b == 0 ? f[i] : Real(0);
-        Km += b == -1 ? f[i] : Real(0);
-        d0 += b == 0 ? Real(a) * f[i] : Real(0);          // f(1,0) - f(-1,0)
-        fZM = (b == -1 && a == 0) ? f[i] : fZM;
-        fPM = (b == -1 && a == 1) ? f[i] : fPM;
-        fMM = (b == -1 && a == -1) ? f[i] : fMM;
-    }
+    const Real Ft = Fx * tx + Fy * ty;
+    const Real fP0 = at<1, 0>(f, k), fM0 = at<-1, 0>(f, k);
+    const Real fZM = at<0, -1>(f, k), fPM = at<1, -1>(f, k), fMM = at<-1, -1>(f, k);
+    const Real K0 = (f[0] + fP0) + fM0;
+    const Real Km = (fZM + fPM) + fMM;
+    const Real d0 = fP0 - fM0;
     // the rest weights over b = 0 plus twice those over b = -1 sum to 1
     const Real rho = ((DEV ? Real(1) : Real(0)) + K0 + Real(2) * Km - Real(0.5) * Fn) / (Real(1) - un);
     const Real D = rho * un * (Real(2.0 / 3.0) - ut * ut);
@@ -208,10 +226,14 @@ __device__ __forceinline__ void zou_he(Real f[9], int nx, int ny, Real uwx, Real
     const Real nZP = fZM + D;
     const Real nPP = fMM - Real(0.5) * d0 + half_t + half_n;
     const Real nMP = fPM + Real(0.5) * d0 - half_t + half_n;
+    // the unknowns (b = +1): per normal a compile-time choice, selected by k
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int a = ex_of(i) * tx + ey_of(i) * ty, b = ex_of(i) * nx + ey_of(i) * ny;
-        f[i] = b == 1 ? (a == 0 ? nZP : (a == 1 ? nPP : nMP)) : f[i];
+    for (int i = 1; i < 9; ++i) {
+        const Real v0 = zb(0, i) == 1 ? (za(0, i) == 0 ? nZP : (za(0, i) == 1 ? nPP : nMP)) : f[i];
+        const Real v1 = zb(1, i) == 1 ? (za(1, i) == 0 ? nZP : (za(1, i) == 1 ? nPP : nMP)) : f[i];
+        const Real v2 = zb(2, i) == 1 ? (za(2, i) == 0 ? nZP : (za(2, i) == 1 ? nPP : nMP)) : f[i];
+        const Real v3 = zb(3, i) == 1 ? (za(3, i) == 0 ? nZP : (za(3, i) == 1 ? nPP : nMP)) : f[i];
+        f[i] = sel4(v0, v1, v2, v3, k);
     }
 }
 
@@ -397,6 +419,16 @@ __host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
     return h;
 }
 
+// Marsaglia's xorshift32 with shifts (13, 17, 5): a bijection of the nonzero 32-bit words, so a
+// uniform nonzero word stays uniform; full-rate shifts and xors only.
+__device__ __forceinline__ uint32_t xorshift32(uint32_t x)
+{
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    return x;
+}
+
 // Key of the random words of one time step of a lattice (step: number of steps taken before it).
 __host__ __device__ __forceinline__ uint32_t step_key(uint32_t step) { return fmix32(step * 0x9e3779b9u + 0x7f4a7c15u); }
 
@@ -414,17 +446,19 @@ __device__ __forceinline__ float round_stochastic(double v, uint32_t u)
 }
 
 // Store the 14 post-collision populations of node `node` (= y * nx + x) at offset o.  For FP32
-// storage of FP64 values each pair of populations takes one word fmix32(8 node + pair + key), so
-// the rounding of a node depends only on (node, step), never on the tile shape or the batch.
+// storage of FP64 values the node draws one word fmix32(node + key) and six more by xorshift32
+// from it; each word's two 16-bit halves round two populations.  The rounding of a node thus
+// depends only on (node, step), never on the tile shape or the batch.
 template <typename S, typename Real, bool NT>
 __device__ __forceinline__ void store_node(S* __restrict__ dst, long long PL, int o, const Real f[9], const Real g[5],
                                            uint32_t key, uint32_t node)
 {
     S v[14];
     if constexpr (sizeof(S) == 4 && sizeof(Real) == 8) {
+        uint32_t r = fmix32(node + key);
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
-            const uint32_t r = fmix32(node * 8u + uint32_t(k) + key);
+            if (k > 0) r = xorshift32(r);
             const Real a = 2 * k < 9 ? f[2 * k] : g[2 * k - 9];
             const Real c = 2 * k + 1 < 9 ? f[2 * k + 1] : g[2 * k + 1 - 9];
             v[2 * k] = round_stochastic(a, r);
