@@ -75,7 +75,9 @@ typedef struct {
     int precision;     /* CLB_FP64, CLB_FP32_DEV, CLB_FP64_DEV or CLB_FP32_SR */
     clb_edge west, east, south, north;
     double T0;         /* reference temperature of the Boussinesq force (Eq. 3) */
-    int prescribed_u;  /* reserved, must be 0 */
+    int prescribed_u;  /* 1: temperature-only lattice (Sec. 3.1): the velocity is prescribed,
+                          uniform and constant, and only the D2Q5 equation is advanced; 0: the
+                          coupled flow and temperature problem */
 } clb_desc;
 
 typedef struct clb_lattice clb_lattice;
@@ -107,14 +109,16 @@ typedef struct {
  * NULL for a stream owned by the handle.  Allocates two population buffers (ping-pong), each
  * 14 planes of nx*ny values, and sets the defaults: rho = 1, u = 0, T = T0 everywhere, all
  * relaxation rates 1 (tau = 1), g*beta = 0, no body force.
- * Errors: CLB_EINVAL (NULL desc/out, bad sizes or kinds, prescribed_u != 0), CLB_ENOMEM,
+ * Errors: CLB_EINVAL (NULL desc/out, bad sizes or kinds, prescribed_u not 0 or 1), CLB_ENOMEM,
  * CLB_EDEVICE. */
 int clb_create(const clb_desc* desc, void* hip_stream, clb_lattice** out);
 
 /* Relaxation times and buoyancy.  tau_nu = 1/s_nu, nu = (tau_nu - 1/2)/3 (Sec. 2.1);
  * tau_alpha = 1/lambda1, alpha = (tau_alpha - 1/2)/4 with c_{T,s}^2 = 1/4 (Sec. 2.2, Sec. 3);
  * g_beta: the Boussinesq coefficient of Eq. 3, F_y = g_beta (T - T0).  Ma is informational
- * (the flow's Mach number u_c/c_s of Sec. 3.3) and is kept for reporting only.
+ * (the flow's Mach number u_c/c_s of Sec. 3.3) and is kept for reporting only, except on a
+ * temperature-only lattice (prescribed_u = 1) whose velocity has not been set with
+ * clb_set_prescribed_velocity: there it sets the frame velocity u = (0, Ma c_s) of Sec. 3.1.
  * Errors: CLB_EINVAL if a tau <= 1/2 or any value is not finite. */
 int clb_set_params(clb_lattice* h, double tau_nu, double tau_alpha, double g_beta, double Ma);
 
@@ -147,6 +151,14 @@ int clb_set_relaxation(clb_lattice* h, double s_b, double s3, double s4, double 
 
 /* Constant external force density F_v of Eq. 3. */
 int clb_set_body_force(clb_lattice* h, double Fvx, double Fvy);
+
+/* Prescribed velocity (ux, uy) of a temperature-only lattice (prescribed_u = 1; Sec. 3.1, where
+ * the velocity field is given and only the D2Q5 CLB equation is solved).  The velocity is uniform
+ * and constant; it enters the D2Q5 collision (Sec. 2.2) and the temperature wall step at every
+ * node, and clb_moments returns rho = 1 and u = (ux, uy).  Takes effect at the next clb_init and
+ * clb_step.  Errors: CLB_ESTATE if the lattice is not temperature-only, CLB_EINVAL if a value is
+ * not finite or |u|^2 >= 1/2 (where g^eq would turn negative). */
+int clb_set_prescribed_velocity(clb_lattice* h, double ux, double uy);
 
 /* FP64 diagnostics of the current step; if snapshot != 0, the current u and T become the new
  * residual snapshot after the residual is measured.  Returns CLB_EDIVERGED (with *out filled)

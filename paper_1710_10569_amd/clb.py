@@ -78,6 +78,7 @@ _sig("clb_destroy", None, [_H])
 _sig("clb_init", ctypes.c_int, [_H, _dp, _dp, _dp])
 _sig("clb_set_relaxation", ctypes.c_int, [_H] + [ctypes.c_double] * 4)
 _sig("clb_set_body_force", ctypes.c_int, [_H, ctypes.c_double, ctypes.c_double])
+_sig("clb_set_prescribed_velocity", ctypes.c_int, [_H, ctypes.c_double, ctypes.c_double])
 _sig("clb_diagnostics", ctypes.c_int, [_H, ctypes.c_int, ctypes.POINTER(clb_diag)])
 _sig("clb_get_populations", ctypes.c_int, [_H, _dp, _dp])
 _sig("clb_params_from_physics", ctypes.c_int, [ctypes.c_double] * 5 + [_dp, _dp, _dp])
@@ -139,8 +140,9 @@ def tile_shapes():
     return out
 
 
-def make_desc(nx, ny, precision="fp64", edges=None, T0=0.0):
-    """clb_desc from sizes, a precision name or code, and {edge: (kind, ux, uy, T)}."""
+def make_desc(nx, ny, precision="fp64", edges=None, T0=0.0, prescribed=False):
+    """clb_desc from sizes, a precision name or code, and {edge: (kind, ux, uy, T)}; prescribed:
+    temperature-only lattice with a prescribed velocity."""
     d = clb_desc()
     d.nx, d.ny = int(nx), int(ny)
     d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -149,15 +151,15 @@ def make_desc(nx, ny, precision="fp64", edges=None, T0=0.0):
         kind, ux, uy, T = edges.get(name, ("periodic", 0.0, 0.0, 0.0))
         setattr(d, name, clb_edge(KINDS[kind] if isinstance(kind, str) else int(kind), ux, uy, T))
     d.T0 = float(T0)
-    d.prescribed_u = 0
+    d.prescribed_u = 1 if prescribed else 0
     return d
 
 
 class Lattice:
     """One lattice on the current HIP device (clb_create ... clb_destroy)."""
 
-    def __init__(self, nx, ny, precision="fp64", edges=None, T0=0.0, stream=None):
-        self.desc = make_desc(nx, ny, precision, edges, T0)
+    def __init__(self, nx, ny, precision="fp64", edges=None, T0=0.0, stream=None, prescribed=False):
+        self.desc = make_desc(nx, ny, precision, edges, T0, prescribed)
         self.nx, self.ny = int(nx), int(ny)
         h = _H()
         _check(_lib.clb_create(ctypes.byref(self.desc), None if stream is None else _vp(int(stream)),
@@ -184,6 +186,10 @@ class Lattice:
 
     def set_params(self, tau_nu, tau_alpha, g_beta=0.0, Ma=0.0):
         _check(_lib.clb_set_params(self._h, tau_nu, tau_alpha, g_beta, Ma))
+
+    def set_prescribed_velocity(self, ux, uy):
+        """Velocity of a temperature-only lattice (created with prescribed=True)."""
+        _check(_lib.clb_set_prescribed_velocity(self._h, ux, uy))
 
     def set_relaxation(self, s_b=1.0, s3=1.0, s4=1.0, lambda2=1.0):
         _check(_lib.clb_set_relaxation(self._h, s_b, s3, s4, lambda2))
@@ -261,7 +267,10 @@ class Lattice:
 
 def lattice_from_workload(w, precision="fp64", stream=None):
     """A Lattice set up and initialised from a workload description (see workloads.py)."""
-    lat = Lattice(w["nx"], w["ny"], precision, w["edges"], w["T0"], stream=stream)
+    lat = Lattice(w["nx"], w["ny"], precision, w["edges"], w["T0"], stream=stream,
+                  prescribed="prescribed_u" in w)
+    if "prescribed_u" in w:
+        lat.set_prescribed_velocity(*w["prescribed_u"])
     if "taus" in w:
         t = w["taus"]
         lat.set_params(t["tau_nu"], t["tau_alpha"], t["g_beta"], 0.0)

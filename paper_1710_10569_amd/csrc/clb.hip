@@ -75,7 +75,7 @@ int validate_desc(const clb_desc* d)
         return CLB_EINVAL;
     }
     if (!std::isfinite(d->T0)) { set_error("T0 not finite"); return CLB_EINVAL; }
-    if (d->prescribed_u != 0) { set_error("prescribed_u is reserved and must be 0"); return CLB_EINVAL; }
+    if (d->prescribed_u != 0 && d->prescribed_u != 1) { set_error("prescribed_u must be 0 or 1"); return CLB_EINVAL; }
     return CLB_OK;
 }
 
@@ -104,6 +104,14 @@ static hipError_t launch_one_step(clb_lattice* h, int shape, const void* src, vo
     const clb_desc& d = h->desc;
     const Geo G = make_geo(d, h->pitch, h->plane);
     const uint32_t key = step_key(uint32_t(step));
+    if (d.prescribed_u) {
+        switch (d.precision) {
+        case CLB_FP64: return launch_step_T<double, double, false>(src, dst, G, make_par<double>(d, h->par), key, h->stream);
+        case CLB_FP64_DEV: return launch_step_T<double, double, true>(src, dst, G, make_par<double>(d, h->par), key, h->stream);
+        case CLB_FP32_SR: return launch_step_T<float, double, true>(src, dst, G, make_par<double>(d, h->par), key, h->stream);
+        default: return launch_step_T<float, float, true>(src, dst, G, make_par<float>(d, h->par), key, h->stream);
+        }
+    }
     switch (d.precision) {
     case CLB_FP64: return launch_step_any<double, double, false>(shape, src, dst, G, make_par<double>(d, h->par), key, h->stream);
     case CLB_FP64_DEV: return launch_step_any<double, double, true>(shape, src, dst, G, make_par<double>(d, h->par), key, h->stream);
@@ -264,6 +272,26 @@ extern "C" int clb_set_params(clb_lattice* h, double tau_nu, double tau_alpha, d
     h->par.tau_alpha = tau_alpha;
     h->par.g_beta = g_beta;
     h->par.Ma = Ma;
+    if (h->desc.prescribed_u && !h->par.pu_set) {
+        // the moving frame of Sec. 3.1: u = (0, A) with A = Ma c_s
+        h->par.pux = 0.0;
+        h->par.puy = Ma / std::sqrt(3.0);
+    }
+    return CLB_OK;
+}
+
+extern "C" int clb_set_prescribed_velocity(clb_lattice* h, double ux, double uy)
+{
+    clear_error();
+    if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
+    if (!h->desc.prescribed_u) { set_error("the lattice was not created with prescribed_u = 1"); return CLB_ESTATE; }
+    if (!std::isfinite(ux) || !std::isfinite(uy) || ux * ux + uy * uy >= 0.5) {
+        set_error("prescribed velocity must be finite with |u|^2 < 1/2");
+        return CLB_EINVAL;
+    }
+    h->par.pux = ux;
+    h->par.puy = uy;
+    h->par.pu_set = true;
     return CLB_OK;
 }
 
@@ -305,6 +333,10 @@ extern "C" int clb_init(clb_lattice* h, const double* rho, const double* u, cons
         host[n + k] = u ? u[k] : 0.0;
         host[2 * n + k] = u ? u[n + k] : 0.0;
         host[3 * n + k] = T ? T[k] : d.T0;
+        if (d.prescribed_u) {   // the velocity is the prescribed one everywhere
+            host[n + k] = h->par.pux;
+            host[2 * n + k] = h->par.puy;
+        }
     }
     for (size_t k = 0; k < 4 * n; ++k)
         if (!std::isfinite(host[k]) || (k < n && host[k] <= 0.0)) {

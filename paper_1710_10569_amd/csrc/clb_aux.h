@@ -63,19 +63,31 @@ __global__ void init_kernel(S* __restrict__ buf, Geo G, const double* __restrict
     }
 }
 
-template <typename S, typename Real, bool DEV>
+// PRESC: temperature-only lattice (prescribed velocity): rho = 1 and u = u_p, T after the
+// temperature wall step.
+template <typename S, typename Real, bool DEV, bool PRESC>
 __global__ __launch_bounds__(TX * TY) void moments_kernel(const S* __restrict__ src, Geo G, Par<Real> P,
                                                         double* __restrict__ fields)
 {
     const int x = blockIdx.x * TX + threadIdx.x;
     const int y = blockIdx.y * TY + threadIdx.y;
     if (x >= G.nx || y >= G.ny) return;
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)y * G.nx + x;
+    if (PRESC) {
+        Real g[5];
+        pull_g(src, G, x, y, g);
+        if (on_wall(G, x, y)) wall_step_T<S, Real, DEV>(src, G, P, x, y, g);
+        fields[k] = 1.0;
+        fields[n + k] = double(P.pux);
+        fields[2 * n + k] = double(P.puy);
+        fields[3 * n + k] = double(P.TR) + double((g[0] + g[1]) + (g[2] + g[3]) + g[4]);
+        return;
+    }
     Real f[9], g[5];
     pull(src, G, x, y, f, g);
     if (on_wall(G, x, y)) wall_step<S, Real, DEV>(src, G, P, x, y, f, g);
     const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
-    const long long n = (long long)G.nx * G.ny;
-    const long long k = (long long)y * G.nx + x;
     fields[k] = double(m.rho);
     fields[n + k] = double(m.ux);
     fields[2 * n + k] = double(m.uy);
@@ -214,11 +226,20 @@ inline hipError_t enqueue_moments(const clb_desc& d, const Params& p, const void
                                   hipStream_t st)
 {
     const dim3 grid = node_grid(G), block(TX, TY);
+    if (d.prescribed_u) {
+        switch (d.precision) {
+        case CLB_FP64: moments_kernel<double, double, false, true><<<grid, block, 0, st>>>((const double*)buf, G, make_par<double>(d, p), d_fields); break;
+        case CLB_FP64_DEV: moments_kernel<double, double, true, true><<<grid, block, 0, st>>>((const double*)buf, G, make_par<double>(d, p), d_fields); break;
+        case CLB_FP32_SR: moments_kernel<float, double, true, true><<<grid, block, 0, st>>>((const float*)buf, G, make_par<double>(d, p), d_fields); break;
+        default: moments_kernel<float, float, true, true><<<grid, block, 0, st>>>((const float*)buf, G, make_par<float>(d, p), d_fields); break;
+        }
+        return hipGetLastError();
+    }
     switch (d.precision) {
-    case CLB_FP64: moments_kernel<double, double, false><<<grid, block, 0, st>>>((const double*)buf, G, make_par<double>(d, p), d_fields); break;
-    case CLB_FP64_DEV: moments_kernel<double, double, true><<<grid, block, 0, st>>>((const double*)buf, G, make_par<double>(d, p), d_fields); break;
-    case CLB_FP32_SR: moments_kernel<float, double, true><<<grid, block, 0, st>>>((const float*)buf, G, make_par<double>(d, p), d_fields); break;
-    default: moments_kernel<float, float, true><<<grid, block, 0, st>>>((const float*)buf, G, make_par<float>(d, p), d_fields); break;
+    case CLB_FP64: moments_kernel<double, double, false, false><<<grid, block, 0, st>>>((const double*)buf, G, make_par<double>(d, p), d_fields); break;
+    case CLB_FP64_DEV: moments_kernel<double, double, true, false><<<grid, block, 0, st>>>((const double*)buf, G, make_par<double>(d, p), d_fields); break;
+    case CLB_FP32_SR: moments_kernel<float, double, true, false><<<grid, block, 0, st>>>((const float*)buf, G, make_par<double>(d, p), d_fields); break;
+    default: moments_kernel<float, float, true, false><<<grid, block, 0, st>>>((const float*)buf, G, make_par<float>(d, p), d_fields); break;
     }
     return hipGetLastError();
 }

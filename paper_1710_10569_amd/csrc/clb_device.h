@@ -52,6 +52,7 @@ struct Par {
     Real TR;                        // rest temperature of the storage form
     Real uw[4][2];                  // wall velocities, W E S N
     Real dTw[4];                    // wall temperatures minus TR
+    Real pux, puy;                  // prescribed velocity (temperature-only mode, Sec. 3.1)
 };
 
 template <typename Real> __device__ __forceinline__ Real R0v();
@@ -237,6 +238,26 @@ __device__ __forceinline__ void zou_he(Real f[9], int nx, int ny, Real uwx, Real
     }
 }
 
+// Temperature non-equilibrium extrapolation: g_i = g^eq_i(T_b, a) + g_i(x_f) - g^eq_i(T_f, b) with
+// a the wall velocity and b the velocity at x_f.  g^eq_i(T, u) = T phi_i(u): phi_0 = 1/2 - |u|^2,
+// phi_{1,3} = (1/4 +- u_x + u_x^2)/2, phi_{2,4} = (1/4 +- u_y + u_y^2)/2.  T_b phi(a) - T_f phi(b)
+// is formed as (T_b - T_f) phi(a) + T_f (phi(a) - phi(b)) so that no O(1) terms cancel.
+template <typename Real>
+__device__ __forceinline__ void nee_g(Real g[5], const Real gf[5], Real dTbf, Real Tf, Real ax, Real ay, Real bx, Real by)
+{
+    const Real pw1 = Real(0.5) * (Real(0.25) + ax + ax * ax), pw3 = Real(0.5) * (Real(0.25) - ax + ax * ax);
+    const Real pw2 = Real(0.5) * (Real(0.25) + ay + ay * ay), pw4 = Real(0.5) * (Real(0.25) - ay + ay * ay);
+    const Real pw0 = Real(0.5) - (ax * ax + ay * ay);
+    const Real d0 = (bx * bx + by * by) - (ax * ax + ay * ay);
+    const Real sx = (ax - bx) + (ax * ax - bx * bx), sxm = (bx - ax) + (ax * ax - bx * bx);
+    const Real sy = (ay - by) + (ay * ay - by * by), sym = (by - ay) + (ay * ay - by * by);
+    g[0] = gf[0] + dTbf * pw0 + Tf * d0;
+    g[1] = gf[1] + dTbf * pw1 + Tf * Real(0.5) * sx;
+    g[2] = gf[2] + dTbf * pw2 + Tf * Real(0.5) * sy;
+    g[3] = gf[3] + dTbf * pw3 + Tf * Real(0.5) * sxm;
+    g[4] = gf[4] + dTbf * pw4 + Tf * Real(0.5) * sym;
+}
+
 // Wall step at node (x, y), which must lie on a wall.  f, g hold the pulled populations on entry
 // (unknown ones meaningless) and the reconstructed ones on exit.
 //   1. g: non-equilibrium extrapolation from the inner neighbour x_f (diagonal one at corners):
@@ -279,25 +300,7 @@ __device__ __forceinline__ void wall_step(const S* __restrict__ src, const Geo& 
         const Real dTff = (gff[0] + gff[1]) + (gff[2] + gff[3]) + gff[4];
         dTb = (Real(4) * mf.dT - dTff) * Real(1.0 / 3.0);
     }
-    // g^eq_i(T, u) = T phi_i(u): phi_0 = 1/2 - |u|^2, phi_{1,3} = (1/4 +- u_x + u_x^2)/2,
-    // phi_{2,4} = (1/4 +- u_y + u_y^2)/2.  T_b phi(u_w) - T_f phi(u_f) is formed as
-    // (T_b - T_f) phi(u_w) + T_f (phi(u_w) - phi(u_f)) so that no O(1) terms cancel.
-    {
-        const Real Tf = P.TR + mf.dT;
-        const Real dTbf = dTb - mf.dT;
-        const Real ax = uwx, ay = uwy, bx = mf.ux, by = mf.uy;
-        const Real pw1 = Real(0.5) * (Real(0.25) + ax + ax * ax), pw3 = Real(0.5) * (Real(0.25) - ax + ax * ax);
-        const Real pw2 = Real(0.5) * (Real(0.25) + ay + ay * ay), pw4 = Real(0.5) * (Real(0.25) - ay + ay * ay);
-        const Real pw0 = Real(0.5) - (ax * ax + ay * ay);
-        const Real d0 = (bx * bx + by * by) - (ax * ax + ay * ay);
-        const Real sx = (ax - bx) + (ax * ax - bx * bx), sxm = (bx - ax) + (ax * ax - bx * bx);
-        const Real sy = (ay - by) + (ay * ay - by * by), sym = (by - ay) + (ay * ay - by * by);
-        g[0] = gf[0] + dTbf * pw0 + Tf * d0;
-        g[1] = gf[1] + dTbf * pw1 + Tf * Real(0.5) * sx;
-        g[2] = gf[2] + dTbf * pw2 + Tf * Real(0.5) * sy;
-        g[3] = gf[3] + dTbf * pw3 + Tf * Real(0.5) * sxm;
-        g[4] = gf[4] + dTbf * pw4 + Tf * Real(0.5) * sym;
-    }
+    nee_g(g, gf, dTb - mf.dT, P.TR + mf.dT, uwx, uwy, mf.ux, mf.uy);
     const Real Fxb = P.Fvx;
     const Real Fyb = P.Fvy + P.g_beta * (dTb + P.Toff);
 
@@ -316,6 +319,39 @@ __device__ __forceinline__ void wall_step(const S* __restrict__ src, const Geo& 
 __device__ __forceinline__ bool on_wall(const Geo& G, int x, int y)
 {
     return (!G.perx && (x == 0 || x == G.nx - 1)) || (!G.pery && (y == 0 || y == G.ny - 1));
+}
+
+// Temperature-only wall step (prescribed velocity u_p, Sec. 3.1): the g part of wall_step with
+// the velocity u_p at the wall node and at x_f.
+template <typename S, typename Real, bool DEV>
+__device__ __forceinline__ void wall_step_T(const S* __restrict__ src, const Geo& G, const Par<Real>& P,
+                                            int x, int y, Real g[5])
+{
+    const bool onW = !G.perx && x == 0, onE = !G.perx && x == G.nx - 1;
+    const bool onS = !G.pery && y == 0, onN = !G.pery && y == G.ny - 1;
+    const int xw = onW ? WEST : (onE ? EAST : -1);
+    const int yw = onS ? SOUTH : (onN ? NORTH : -1);
+    const int dx = onW ? 1 : (onE ? -1 : 0);
+    const int dy = onS ? 1 : (onN ? -1 : 0);
+    const bool corner = xw >= 0 && yw >= 0;
+    const int vw = xw >= 0 ? xw : yw;
+    const int kx = xw >= 0 ? sel4(G.kind[0], G.kind[1], G.kind[2], G.kind[3], xw) : K_PERIODIC;
+    const int ky = yw >= 0 ? sel4(G.kind[0], G.kind[1], G.kind[2], G.kind[3], yw) : K_PERIODIC;
+    const int tw = (corner && kx != K_DIRICHLET && ky == K_DIRICHLET) ? yw : vw;
+    const int tkind = tw == xw ? kx : ky;
+    Real gf[5];
+    pull_g(src, G, x + dx, y + dy, gf);
+    const Real dTf = (gf[0] + gf[1]) + (gf[2] + gf[3]) + gf[4];
+    Real dTb;
+    if (tkind == K_DIRICHLET) {
+        dTb = sel4(P.dTw[0], P.dTw[1], P.dTw[2], P.dTw[3], tw);
+    } else {
+        Real gff[5];
+        pull_g(src, G, x + 2 * dx, y + 2 * dy, gff);
+        const Real dTff = (gff[0] + gff[1]) + (gff[2] + gff[3]) + gff[4];
+        dTb = (Real(4) * dTf - dTff) * Real(1.0 / 3.0);
+    }
+    nee_g(g, gf, dTb - dTf, P.TR + dTf, P.pux, P.puy, P.pux, P.puy);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -405,8 +441,7 @@ __device__ __forceinline__ void collide_g(Real g[5], const Macro<Real, DEV>& m, 
 }
 
 // ---------------------------------------------------------------------------------------------
-// The whole node update: pull, wall step (wall nodes only), macroscopic, both collisions, and the
-// store of the 14 post-collision populations at the node itself.  NT selects non-temporal stores.
+// Storage rounding.
 // MurmurHash3's 32-bit finalizer (Appleby): a bijective mixer with full avalanche, used as a
 // counter-based generator (distinct counters give distinct, well-mixed words).
 __host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
@@ -477,6 +512,10 @@ __device__ __forceinline__ void store_node(S* __restrict__ dst, long long PL, in
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// The whole node update: pull, wall step (wall nodes only), macroscopic, both collisions, and the
+// store of the 14 post-collision populations at the node itself.  NT selects non-temporal stores.
+//
 // The whole update of node (x, y) of one step; key = step_key(step) (used by FP32 storage of
 // FP64 arithmetic only).
 template <typename S, typename Real, bool DEV, bool NT>
@@ -514,6 +553,42 @@ __device__ __forceinline__ void node_update2(const S* __restrict__ src, S* __res
         collide_f<Real, DEV>(fb, m, P);
         collide_g<Real, DEV>(gb, m, P);
         store_node<S, Real, NT>(dst, G.plane, y1 * G.pitch + x, fb, gb, key, uint32_t(y1) * uint32_t(G.nx) + uint32_t(x));
+    }
+}
+
+// Temperature-only node update (prescribed velocity u_p, Sec. 3.1): only the D2Q5 equation runs,
+// with u = u_p at every node; only the five g planes are read and written.
+template <typename S, typename Real, bool DEV, bool NT>
+__device__ __forceinline__ void node_update_T(const S* __restrict__ src, S* __restrict__ dst, const Geo& G,
+                                              const Par<Real>& P, int x, int y, uint32_t key)
+{
+    Real g[5];
+    pull_g(src, G, x, y, g);
+    if (on_wall(G, x, y)) wall_step_T<S, Real, DEV>(src, G, P, x, y, g);
+    Macro<Real, DEV> m;
+    m.dT = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+    m.ux = P.pux;
+    m.uy = P.puy;
+    collide_g<Real, DEV>(g, m, P);
+    const long long PL = G.plane;
+    const int o = y * G.pitch + x;
+    S v[5];
+    if constexpr (sizeof(S) == 4 && sizeof(Real) == 8) {
+        uint32_t r = fmix32(uint32_t(y) * uint32_t(G.nx) + uint32_t(x) + key);
+        const uint32_t r2 = xorshift32(r);
+        v[0] = round_stochastic(g[0], r);
+        v[1] = round_stochastic(g[1], r >> 16);
+        v[2] = round_stochastic(g[2], r2);
+        v[3] = round_stochastic(g[3], r2 >> 16);
+        v[4] = round_stochastic(g[4], xorshift32(r2));
+    } else {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) v[i] = S(g[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        if (NT) __builtin_nontemporal_store(v[i], dst + (9 + i) * PL + o);
+        else dst[(9 + i) * PL + o] = v[i];
     }
 }
 

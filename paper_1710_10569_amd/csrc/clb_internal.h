@@ -42,6 +42,8 @@ struct Params {
     double tau_nu = 1.0, tau_alpha = 1.0, g_beta = 0.0, Ma = 0.0;
     double s_b = 1.0, s3 = 1.0, s4 = 1.0, lam2 = 1.0;
     double Fvx = 0.0, Fvy = 0.0;
+    double pux = 0.0, puy = 0.0;   // prescribed velocity (temperature-only lattices)
+    bool pu_set = false;           // set explicitly (else (0, Ma c_s) from clb_set_params)
 };
 
 Geo make_geo(const clb_desc& d, int pitch, long long plane);
@@ -73,6 +75,8 @@ Par<Real> make_par(const clb_desc& d, const Params& p)
         P.uw[i][1] = Real(e[i]->uy);
         P.dTw[i] = Real(e[i]->T - TR);
     }
+    P.pux = Real(p.pux);
+    P.puy = Real(p.puy);
     return P;
 }
 

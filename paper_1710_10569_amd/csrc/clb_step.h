@@ -91,4 +91,28 @@ hipError_t launch_step_any(int shape, const void* src, void* dst, const Geo& G, 
     }
 }
 
+// Temperature-only step (prescribed velocity): 256 x 1 tiles in the same XCD order, five planes
+// read and written per node.
+template <typename S, typename Real, bool DEV>
+__global__ __launch_bounds__(256) void step_T_kernel(const S* __restrict__ src, S* __restrict__ dst, Geo G,
+                                                    Par<Real> P, int tiles_x, int ntiles, uint32_t key)
+{
+    const int q = int(gridDim.x >> 3);
+    const int t = int(blockIdx.x & 7) * q + int(blockIdx.x >> 3);
+    if (t >= ntiles) return;
+    const int y = t / tiles_x;
+    const int x = (t - y * tiles_x) * 256 + int(threadIdx.x);
+    if (x >= G.nx) return;
+    node_update_T<S, Real, DEV, false>(src, dst, G, P, x, y, key);
+}
+
+template <typename S, typename Real, bool DEV>
+hipError_t launch_step_T(const void* src, void* dst, const Geo& G, const Par<Real>& P, uint32_t key, hipStream_t st)
+{
+    const int tx = (G.nx + 255) / 256, ntiles = tx * G.ny;
+    const int q = (ntiles + 7) / 8;
+    step_T_kernel<S, Real, DEV><<<dim3(8 * q), dim3(256), 0, st>>>((const S*)src, (S*)dst, G, P, tx, ntiles, key);
+    return hipGetLastError();
+}
+
 }  // namespace clb

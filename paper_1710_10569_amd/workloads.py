@@ -189,3 +189,32 @@ def normal_plate(L=30, Re=10.0, Pr=0.71, nu=0.1, nx=5, T_L=0.0, T_H=1.0):
             "lambda2": 12.0 * (lam1 - 2.0) / (lam1 - 12.0),
             "u_scale": v0, "Re": Re, "Pr": Pr, "L": L, "u0": v0, "T_L": T_L, "T_H": T_H,
             "fields": {"rho": None, "ux": None, "uy": np.full((L + 1, nx), v0), "T": None}}
+
+
+def moving_frame(L=100, B=0.01, alpha=0.05, T0=1.0, Ma=0.3, nx=4):
+    """Sec. 3.1 (Eq. 24): a temperature wave T = T0 + B sin(phi y), phi = 2 pi / L, on a frame
+    moving with the prescribed velocity u = (0, A), A = Ma c_s; periodic in x and y; only the D2Q5
+    equation runs (temperature-only lattice), tau_alpha from the given alpha with c_T^2 = 1/4."""
+    y = np.arange(L, dtype=np.float64)[:, None]
+    T = np.broadcast_to(T0 + B * np.sin(2 * math.pi * y / L), (L, nx)).copy()
+    A = Ma / math.sqrt(3.0)
+    return {"name": f"moving_frame_L{L}_Ma{Ma:g}", "nx": nx, "ny": L, "T0": T0, "edges": _edges(),
+            "taus": {"tau_nu": 0.8, "tau_alpha": 4.0 * alpha + 0.5, "g_beta": 0.0},
+            "prescribed_u": (0.0, A), "u_scale": max(A, 1e-3),
+            "fields": {"rho": np.ones((L, nx)), "ux": np.zeros((L, nx)), "uy": np.full((L, nx), A), "T": T}}
+
+
+def prescribed_walled(nx, ny, seed, u=(0.03, -0.05), kinds=("dirichlet", "adiabatic", "adiabatic", "dirichlet"),
+                      amp_T=0.1, T0=0.2, tau_alpha=0.9):
+    """Temperature-only lattice with walls (every branch of the temperature wall step: Dirichlet and
+    adiabatic edges, corners of both kinds) and a seeded random temperature field, advected by the
+    uniform prescribed velocity u."""
+    rng = np.random.default_rng(seed)
+    T = T0 + rng.uniform(-amp_T, amp_T, size=(ny, nx))
+    names = ("west", "east", "south", "north")
+    tw = (T0 + 0.5, T0 - 0.5, T0 + 0.25, T0 - 0.25)
+    edges = {nm: ((kd, 0.0, 0.0, tw[i]) if kd != "periodic" else PERIODIC) for i, (nm, kd) in enumerate(zip(names, kinds))}
+    return {"name": f"prescribed_walled_{nx}x{ny}_s{seed}", "nx": nx, "ny": ny, "T0": T0, "edges": edges,
+            "taus": {"tau_nu": 0.8, "tau_alpha": tau_alpha, "g_beta": 0.0},
+            "prescribed_u": tuple(u), "u_scale": 1.0,
+            "fields": {"rho": np.ones((ny, nx)), "ux": np.full((ny, nx), u[0]), "uy": np.full((ny, nx), u[1]), "T": T}}

@@ -10,6 +10,8 @@ def oracle_from_workload(w):
     e = w["edges"]
     lat = O.OracleLattice(w["nx"], w["ny"], *[Edge(*e[k]) for k in ("west", "east", "south", "north")],
                           T0=w["T0"])
+    if "prescribed_u" in w:
+        lat.set_prescribed_velocity(*w["prescribed_u"])
     if "taus" in w:
         t = w["taus"]
         lat.set_params(t["tau_nu"], t["tau_alpha"], t["g_beta"])
