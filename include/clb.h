@@ -106,8 +106,9 @@ typedef struct {
  * ------------------------------------------------------------------------------------------- */
 
 /* Create a lattice on the current HIP device.  hip_stream: a hipStream_t to enqueue work on, or
- * NULL for a stream owned by the handle.  Allocates two population buffers (ping-pong), each
- * 14 planes of nx*ny values, and sets the defaults: rho = 1, u = 0, T = T0 everywhere, all
+ * NULL for a stream owned by the handle.  Allocates two population buffers (ping-pong) of
+ * 14 values per node (rows of 64-node chunks, each chunk holding its nodes' 14 populations as
+ * 14 runs of 64 values), and sets the defaults: rho = 1, u = 0, T = T0 everywhere, all
  * relaxation rates 1 (tau = 1), g*beta = 0, no body force.
  * Errors: CLB_EINVAL (NULL desc/out, bad sizes or kinds, prescribed_u not 0 or 1), CLB_ENOMEM,
  * CLB_EDEVICE. */

@@ -79,13 +79,12 @@ int validate_desc(const clb_desc* d)
     return CLB_OK;
 }
 
-Geo make_geo(const clb_desc& d, int pitch, long long plane)
+Geo make_geo(const clb_desc& d)
 {
     Geo G;
     G.nx = d.nx;
     G.ny = d.ny;
-    G.pitch = pitch;
-    G.plane = plane;
+    G.row = row_elems(d.nx);
     G.perx = d.west.kind == CLB_PERIODIC;
     G.pery = d.south.kind == CLB_PERIODIC;
     G.kind[0] = d.west.kind;
@@ -102,7 +101,7 @@ Geo make_geo(const clb_desc& d, int pitch, long long plane)
 static hipError_t launch_one_step(clb_lattice* h, int shape, const void* src, void* dst, long long step)
 {
     const clb_desc& d = h->desc;
-    const Geo G = make_geo(d, h->pitch, h->plane);
+    const Geo G = make_geo(d);
     const uint32_t key = step_key(uint32_t(step));
     if (d.prescribed_u) {
         switch (d.precision) {
@@ -153,7 +152,7 @@ int default_shape(const clb_desc& d)
 
 static int launch_moments(clb_lattice* h)
 {
-    const Geo G = make_geo(h->desc, h->pitch, h->plane);
+    const Geo G = make_geo(h->desc);
     CLB_HIP(enqueue_moments(h->desc, h->par, h->buf[h->cur], G, h->d_fields, h->stream));
     return CLB_OK;
 }
@@ -230,9 +229,7 @@ static int create_impl(const clb_desc* desc, void* hip_stream, clb_lattice** out
         h->own_stream = true;
     }
     const size_t eb = elem_bytes(desc->precision);
-    h->pitch = row_pitch(desc->nx, eb);
-    h->plane = (long long)h->pitch * desc->ny;
-    h->buf_bytes = size_t(14) * h->plane * eb;
+    h->buf_bytes = size_t(buffer_elems(desc->nx, desc->ny)) * eb;
     const size_t n = size_t(desc->nx) * desc->ny;
     if (hipMalloc(&h->buf[0], h->buf_bytes) != hipSuccess || hipMalloc(&h->buf[1], h->buf_bytes) != hipSuccess ||
         hipMalloc((void**)&h->d_fields, 4 * n * sizeof(double)) != hipSuccess) {
@@ -348,7 +345,7 @@ extern "C" int clb_init(clb_lattice* h, const double* rho, const double* u, cons
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     free(host);
     if (e != hipSuccess) { set_error("upload of initial fields failed: %s", hipGetErrorString(e)); return CLB_EDEVICE; }
-    const Geo G = make_geo(d, h->pitch, h->plane);
+    const Geo G = make_geo(d);
     h->cur = 0;
     CLB_HIP(enqueue_init(d, h->par, h->buf[0], G, h->d_fields, h->stream));
     h->steps = 0;
@@ -531,7 +528,7 @@ extern "C" int clb_get_populations(clb_lattice* h, double* f, double* g)
     const size_t n = size_t(d.nx) * d.ny;
     double* dev = nullptr;
     CLB_HIP(hipMalloc((void**)&dev, 14 * n * sizeof(double)));
-    const Geo G = make_geo(d, h->pitch, h->plane);
+    const Geo G = make_geo(d);
     hipError_t e = enqueue_populations(d, h->buf[h->cur], G, dev, h->stream);
     if (e == hipSuccess && f) e = hipMemcpyAsync(f, dev, 9 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess && g) e = hipMemcpyAsync(g, dev + 9 * n, 5 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
@@ -547,7 +544,7 @@ extern "C" int clb_diagnostics(clb_lattice* h, int snapshot, clb_diag* out)
     if (!h || !out) { set_error("NULL argument"); return CLB_EINVAL; }
     const clb_desc& d = h->desc;
     const size_t n = size_t(d.nx) * d.ny;
-    const Geo G = make_geo(d, h->pitch, h->plane);
+    const Geo G = make_geo(d);
     const int nblocks = diag_blocks(G);
     if (!h->d_snap) CLB_HIP(hipMalloc((void**)&h->d_snap, 3 * n * sizeof(double)));
     if (!h->d_diag) CLB_HIP(hipMalloc((void**)&h->d_diag, DIAG_SLOTS * sizeof(double)));

@@ -49,7 +49,7 @@ __global__ void init_kernel(S* __restrict__ buf, Geo G, const double* __restrict
         if (!source_of(G, x, y, i, sx, sy)) continue;
         double v = rho * psi(EXd[i], vx) * psi(EYd[i], vy);
         if (DEV) v -= W9[i];
-        buf[i * G.plane + (long long)sy * G.pitch + sx] = S(v);
+        buf[pop_at(G, sx, sy) + i * CW] = S(v);
     }
     const double gq[5] = {T * (0.5 - ux * ux - uy * uy), 0.5 * T * (0.25 + ux + ux * ux),
                           0.5 * T * (0.25 + uy + uy * uy), 0.5 * T * (0.25 - ux + ux * ux),
@@ -59,7 +59,7 @@ __global__ void init_kernel(S* __restrict__ buf, Geo G, const double* __restrict
         if (!source_of(G, x, y, i, sx, sy)) continue;
         double v = gq[i];
         if (DEV) v -= W5[i] * TR;
-        buf[(9 + i) * G.plane + (long long)sy * G.pitch + sx] = S(v);
+        buf[pop_at(G, sx, sy) + (9 + i) * CW] = S(v);
     }
 }
 

@@ -1,8 +1,9 @@
 // clb_batch.hip -- many lattices of uneven size resident in one HBM pool, advanced together.
 //
 // Memory: one pool (allocated by the library or handed in, e.g. a torch tensor) is carved by a
-// first-fit free list into per-lattice regions: two population buffers (14 planes each, rows on
-// 256-byte boundaries) and an FP64 snapshot of (u_x, u_y, T) for the residual test.  Admission is
+// first-fit free list into per-lattice regions: two population buffers (rows of 64-node chunks
+// of 14 populations, on 256-byte boundaries) and an FP64 snapshot of (u_x, u_y, T) for the
+// residual test.  Admission is
 // that allocation succeeding inside the budget.
 //
 // Device tables: one entry per slot (geometry, buffer offsets, current buffer, tile width, and the
@@ -200,8 +201,6 @@ struct BatchSlot {
     size_t alloc_off = 0, alloc_bytes = 0;   // byte range in the pool
     long long off[2] = {0, 0};               // element offsets of the population buffers
     size_t snap_off = 0;                     // byte offset of the FP64 snapshot (3 n doubles)
-    int pitch = 0;
-    long long plane = 0;
     int cur = 0;
     long long steps = 0;
     bool has_snap = false;
@@ -211,15 +210,11 @@ struct BatchSlot {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-size_t slot_bytes(const clb_desc& d, int* pitch_out, long long* plane_out, size_t* buf_bytes_out)
+size_t slot_bytes(const clb_desc& d, size_t* buf_bytes_out)
 {
     const size_t eb = elem_bytes(d.precision);
-    const int pitch = row_pitch(d.nx, eb);
-    const long long plane = (long long)pitch * d.ny;
-    const size_t buf = align_up(size_t(14) * plane * eb);
+    const size_t buf = align_up(size_t(buffer_elems(d.nx, d.ny)) * eb);
     const size_t snap = align_up(size_t(3) * d.nx * d.ny * sizeof(double));
-    if (pitch_out) *pitch_out = pitch;
-    if (plane_out) *plane_out = plane;
     if (buf_bytes_out) *buf_bytes_out = buf;
     return 2 * buf + snap;
 }
@@ -316,7 +311,7 @@ template <typename Real>
 BatchEntry<Real> make_entry(const BatchSlot& s, int tw_log2)
 {
     BatchEntry<Real> E;
-    E.L.G = make_geo(s.desc, s.pitch, s.plane);
+    E.L.G = make_geo(s.desc);
     E.L.off[0] = s.off[0];
     E.L.off[1] = s.off[1];
     E.L.snap = (long long)s.snap_off;
@@ -547,7 +542,7 @@ extern "C" int clb_batch_footprint(const clb_desc* desc, size_t* bytes)
     if (!bytes) { set_error("NULL argument"); return CLB_EINVAL; }
     const int rc = validate_desc(desc);
     if (rc) return rc;
-    *bytes = slot_bytes(*desc, nullptr, nullptr, nullptr);
+    *bytes = slot_bytes(*desc, nullptr);
     return CLB_OK;
 }
 
@@ -659,7 +654,7 @@ extern "C" int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, 
     if (free_slot < 0) { set_error("batch is full (%d slots)", b->capacity); return CLB_ENOMEM; }
     BatchSlot s;
     size_t buf_bytes = 0;
-    const size_t bytes = slot_bytes(*desc, &s.pitch, &s.plane, &buf_bytes);
+    const size_t bytes = slot_bytes(*desc, &buf_bytes);
     size_t off = 0;
     if (alloc_range(b, bytes, &off) != CLB_OK) {
         set_error("lattice needs %zu bytes; %zu of %zu bytes in use", bytes, b->used_bytes, b->budget);
@@ -749,7 +744,7 @@ extern "C" int clb_batch_init(clb_batch* b, int slot, const double* rho, const d
     const size_t buf_bytes = size_t(s.off[1] - s.off[0]) * eb;
     CLB_HIP(hipMemsetAsync(b->pool + s.off[0] * eb, 0, 2 * buf_bytes, b->stream));
     CLB_HIP(hipMemcpyAsync(b->d_fields, host.data(), 4 * n * sizeof(double), hipMemcpyHostToDevice, b->stream));
-    const Geo G = make_geo(d, s.pitch, s.plane);
+    const Geo G = make_geo(d);
     CLB_HIP(enqueue_init(d, s.par, b->pool + s.off[0] * eb, G, b->d_fields, b->stream));
     // the snapshot starts as the initial (u_x, u_y, T), so the first residual measures the first chunk
     CLB_HIP(enqueue_moments(d, s.par, b->pool + s.off[0] * eb, G, b->d_fields, b->stream));
@@ -862,7 +857,7 @@ extern "C" int clb_batch_moments(clb_batch* b, int slot, double* rho, double* u,
     rc = ensure_fields(b, 4 * n);
     if (rc) return rc;
     const size_t eb = elem_bytes(d.precision);
-    const Geo G = make_geo(d, s.pitch, s.plane);
+    const Geo G = make_geo(d);
     CLB_HIP(enqueue_moments(d, s.par, b->pool + s.off[s.cur] * eb, G, b->d_fields, b->stream));
     if (rho) CLB_HIP(hipMemcpyAsync(rho, b->d_fields, n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     if (u) CLB_HIP(hipMemcpyAsync(u, b->d_fields + n, 2 * n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
@@ -882,7 +877,7 @@ extern "C" int clb_batch_diagnostics(clb_batch* b, int slot, int snapshot, clb_d
     const size_t n = size_t(d.nx) * d.ny;
     rc = ensure_fields(b, 4 * n);
     if (rc) return rc;
-    const Geo G = make_geo(d, s.pitch, s.plane);
+    const Geo G = make_geo(d);
     const int nb = diag_blocks(G);
     if (b->partials_cap < nb) {
         CLB_HIP(hipStreamSynchronize(b->stream));

@@ -28,8 +28,10 @@ void clear_error();
         }                                                                                     \
     } while (0)
 
-// Row pitch in elements: rows start on 256-byte boundaries.
-inline int row_pitch(int nx, size_t elem) { const int a = int(256 / elem); return (nx + a - 1) / a * a; }
+// Elements per row (ceil(nx / CW) chunks of 14 * CW; every chunk starts on a 256-byte boundary)
+// and per population buffer.
+inline int row_elems(int nx) { return (nx + CW - 1) / CW * CHUNK; }
+inline long long buffer_elems(int nx, int ny) { return (long long)row_elems(nx) * ny; }
 
 inline size_t elem_bytes(int precision) { return (precision == CLB_FP32_DEV || precision == CLB_FP32_SR) ? 4 : 8; }
 inline bool is_dev(int precision) { return precision != CLB_FP64; }
@@ -46,7 +48,7 @@ struct Params {
     bool pu_set = false;           // set explicitly (else (0, Ma c_s) from clb_set_params)
 };
 
-Geo make_geo(const clb_desc& d, int pitch, long long plane);
+Geo make_geo(const clb_desc& d);
 
 // CLB_OK, or CLB_EINVAL with a message, for relaxation times / buoyancy / Mach number.
 int check_params(double tau_nu, double tau_alpha, double g_beta, double Ma);
@@ -90,9 +92,7 @@ struct clb_lattice {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    int pitch = 0;
-    long long plane = 0;      // elements per plane
-    size_t buf_bytes = 0;     // bytes per population buffer (14 planes)
+    size_t buf_bytes = 0;     // bytes per population buffer
     void* buf[2] = {nullptr, nullptr};
     int cur = 0;              // buffer holding the post-collision state of the last step
     int shape = 2;            // tile shape of the step kernel (clb_step.h)

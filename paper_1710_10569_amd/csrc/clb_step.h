@@ -1,13 +1,14 @@
 // clb_step.h -- the tiled step kernel and its launch shapes.
 //
 // A workgroup updates a tile of TXW x (TY * SPT) nodes: TXW consecutive nodes of a row per thread
-// row (TXW is a multiple of the 64-lane wavefront, so every wavefront reads and writes 64
-// consecutive elements of a plane), TY thread rows, and SPT nodes per thread stacked TY rows
-// apart.  Tiles are numbered row-major over the lattice and handed to workgroups XCD by XCD: the
-// dispatcher places workgroup b on XCD b mod 8, so workgroup b takes tile (b mod 8) * q + b / 8
-// (q = tiles per XCD).  Each XCD then sweeps one contiguous band of rows, and the cache line that
-// two neighbouring tiles share at their edge -- every plane with an x component is read one
-// element off alignment -- is fetched once into that XCD's L2 instead of once per XCD.
+// row (TXW is a multiple of the 64-lane wavefront, so every wavefront covers one 64-node storage
+// chunk and reads and writes 64 consecutive values per population), TY thread rows, and SPT nodes
+// per thread stacked TY rows apart.  Tiles are numbered row-major over the lattice and handed to
+// workgroups XCD by XCD: the dispatcher places workgroup b on XCD b mod 8, so workgroup b takes
+// tile (b mod 8) * q + b / 8 (q = tiles per XCD).  Each XCD then sweeps one contiguous band of
+// rows, and the values that two neighbouring tiles share at their edge -- every population with an
+// x component is read one node off the chunk -- are fetched once into that XCD's L2 instead of
+// once per XCD.
 #pragma once
 
 #include "clb_device.h"
@@ -91,8 +92,8 @@ hipError_t launch_step_any(int shape, const void* src, void* dst, const Geo& G, 
     }
 }
 
-// Temperature-only step (prescribed velocity): 256 x 1 tiles in the same XCD order, five planes
-// read and written per node.
+// Temperature-only step (prescribed velocity): 256 x 1 tiles in the same XCD order, the five g
+// populations read and written per node.
 template <typename S, typename Real, bool DEV>
 __global__ __launch_bounds__(256) void step_T_kernel(const S* __restrict__ src, S* __restrict__ dst, Geo G,
                                                     Par<Real> P, int tiles_x, int ntiles, uint32_t key)
