@@ -10,9 +10,11 @@ the library's stream, bracketed by device synchronisation, timed with HIP events
 
 Printed: one JSON line with MLUPS (site updates per second / 1e6; a D2Q9 + D2Q5 update counts as
 one), the roofline of the step kernel (112 algorithmic bytes per FP32 site update: 14 populations
-read + 14 written; 224 in FP64), the same lattice in FP64 beside it, the FP32-vs-FP64 field error,
-an 8192 x 4096 control lattice whose footprint (3.8 GB) is far beyond the 256 MB Infinity Cache,
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+read + 14 written; 224 in FP64), the same lattice in FP64 and in FP32 storage with FP64 collision
+and stochastic rounding ("fp32_sr") beside it, their field errors against FP64, an 8192 x 4096
+control lattice whose footprint (3.8 GB) is far beyond the 256 MB Infinity Cache, the 512-cavity
+batch, two serving runs (Poisson arrivals of small cavities, and a saturated queue of larger
+ones), and the FP64 CPU oracle timed on a bounded sample of the same workload.
 Progress goes to stderr.
 """
 import argparse
@@ -23,13 +25,15 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (D2Q9+D2Q5) and % HBM roofline, FP32 vs FP64; served p50/p99 latency"
 HBM_PEAK_GBPS = 8000.0
-BYTES_PER_SITE = {"fp32": 112, "fp64": 224}
+BYTES_PER_SITE = {"fp32": 112, "fp32_sr": 112, "fp64": 224, "fp64_dev": 224}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_kernel_rb2048x1024.json")
 
 
@@ -133,50 +137,58 @@ def cpu_baseline(W, budget_s=15.0):
             "sample": f"{n} steps of the 2048x1024 Rayleigh-Benard lattice ({sites * n:.3g} site updates), FP64"}
 
 
-def run_batch(clb, W, steps, stream, log_each=True):
-    """The 512 batched cavities (sides from {64, 96, ..., 512}, Ra log-uniform in [1e3, 1e6], seed 7),
-    FP32, in one pool: autotuned tile widths, then the grouped schedule (one launch per step over all
-    cavities) and the one-launch-per-cavity schedule, timed with HIP events on the batch's stream."""
+def run_batch(clb, W, steps, stream, precision="fp32", modes=("grouped", "each")):
+    """The 512 batched cavities (sides from {64, 96, ..., 512}, Ra log-uniform in [1e3, 1e6], seed 7)
+    in one pool: autotuned tile widths and store form, then the grouped schedule (one launch per step
+    over all cavities) and the one-launch-per-cavity schedule, timed with HIP events on the batch's
+    stream."""
     import torch
     specs = W.batch_cavity_specs()
     total = sum(L * L for L, _, _ in specs)
-    budget = sum(clb.footprint(L, L, "fp32") for L, _, _ in specs) + (64 << 20)
-    b = clb.Batch(len(specs), "fp32", budget_bytes=budget, stream=stream)
+    budget = sum(clb.footprint(L, L, precision) for L, _, _ in specs) + (64 << 20)
+    b = clb.Batch(len(specs), precision, budget_bytes=budget, stream=stream)
     t0 = time.perf_counter()
     for L, Ra, seed in specs:
         if b.add_workload(W.cavity(L, Ra=Ra, seed=seed)) is None:
             raise RuntimeError("batch pool too small")
-    log(f"[bench] batch: {len(specs)} cavities, {total:.4g} nodes, pool {budget / 1e9:.2f} GB, "
+    log(f"[bench] batch {precision}: {len(specs)} cavities, {total:.4g} nodes, pool {budget / 1e9:.2f} GB, "
         f"set up in {time.perf_counter() - t0:.1f} s")
     b.step(20)
     b.autotune(3)
     torch.cuda.synchronize()
-    out = {"cavities": len(specs), "sites": total, "steps": steps, "pool_GB": budget / 1e9}
-    for mode in ("grouped", "each"):
+    out = {"precision": precision, "cavities": len(specs), "sites": total, "steps": steps, "pool_GB": budget / 1e9}
+    for mode in modes:
         n = steps if mode != "each" else max(10, steps // 10)
         b.step(2, mode)
         ms = b.time_steps(n, mode)
         mlups = total * n / (ms * 1e-3) / 1e6
-        out[mode] = {"MLUPS": mlups, "ms_per_step": ms / n, "steps_timed": n,
-                     "achieved_GBps": 112 * total * n / (ms * 1e-3) / 1e9}
-        log(f"[bench] batch {mode}: {ms / n:.3f} ms/step, {mlups:.0f} MLUPS")
+        gbps = BYTES_PER_SITE[precision] * total * n / (ms * 1e-3) / 1e9
+        out[mode] = {"MLUPS": mlups, "ms_per_step": ms / n, "steps_timed": n, "achieved_GBps": gbps,
+                     "frac": gbps / HBM_PEAK_GBPS}
+        log(f"[bench] batch {precision} {mode}: {ms / n:.3f} ms/step, {mlups:.0f} MLUPS, {gbps:.0f} GB/s")
     b.close()
     return out
 
 
 def run_serving(clb, W, stream, n=32, lam=8.0, L_range=(32, 128), tol=1e-8, step_cap=200_000, patience=10):
-    """A Poisson stream of cavity requests served with continuous batching (serving.py)."""
+    """A Poisson stream of cavity requests (lam per second; lam = inf: all queued at time 0) served
+    with continuous batching (serving.py), FP32 storage with FP64 collision and stochastic rounding."""
     from paper_1710_10569_amd import serving as S
-    specs = W.serving_requests(n=n, lam=lam, L_range=L_range)
+    specs = W.serving_requests(n=n, lam=lam if math.isfinite(lam) else 1.0, L_range=L_range)
+    if not math.isfinite(lam):
+        for sp in specs:
+            sp["arrival"] = 0.0
     reqs = S.requests_from(specs)
     srv = S.CavityServer(budget_bytes=8 << 30, capacity=256, chunk=1000, tol=tol, step_cap=step_cap,
                          schedule="grouped", floor_patience=patience, stream=stream)
     out = srv.run(reqs)
     summ = S.summarize(out, srv.wall, srv.site_updates)
     srv.close()
-    summ.update({"lambda_per_s": lam, "L_range": list(L_range), "Ra_range": [1e3, 1e6], "tol": tol,
-                 "step_cap": step_cap, "chunk": 1000, "precision": "fp32",
+    summ.update({"lambda_per_s": lam if math.isfinite(lam) else "all at t=0", "L_range": list(L_range),
+                 "Ra_range": [1e3, 1e6], "tol": tol, "step_cap": step_cap, "chunk": 1000,
+                 "precision": srv.precision,
                  "floor_rule": f"residual not halved in {patience} chunks and below 1e-6"})
+    summ["frac_of_hbm_peak"] = summ["aggregate_MLUPS"] * 1e6 * BYTES_PER_SITE[srv.precision] / 1e9 / HBM_PEAK_GBPS
     log(f"[bench] serving: {summ}")
     return summ
 
@@ -255,7 +267,6 @@ def main():
         lat64, r64 = run_precision(clb, W, "fp64", args.steps, args.warmup, stream.cuda_stream, w, args.autotune)
         _, ux32, uy32, T32 = lat32.moments()
         _, ux64, uy64, T64 = lat64.moments()
-        import numpy as np
         umax = max(np.abs(ux64).max(), np.abs(uy64).max())
         eu = max(np.abs(ux32 - ux64).max(), np.abs(uy32 - uy64).max()) / umax
         eT = np.abs(T32 - T64).max() / np.abs(T64 - w["T0"]).max()
@@ -267,21 +278,41 @@ def main():
                                               "after_steps": args.warmup + args.steps,
                                               "note": "max-norm, relative to max|u| and max|T-T0|; the flow "
                                                       "is in its instability-growth phase, where roundoff seeds it"}
+        latsr, rsr = run_precision(clb, W, "fp32_sr", args.steps, args.warmup, stream.cuda_stream, w,
+                                   args.autotune)
+        _, uxs, uys, Ts = latsr.moments()
+        result["fp32_sr"] = {"value": rsr["mlups"], "unit": "MLUPS", "ms_per_step": rsr["ms_per_step"],
+                             "tile_shape": rsr["tile_shape"], "achieved_GBps": rsr["gbps"],
+                             "frac": rsr["gbps"] / HBM_PEAK_GBPS, "bytes_per_site": BYTES_PER_SITE["fp32_sr"],
+                             "field_error_vs_fp64": {
+                                 "u": float(max(np.abs(uxs - ux64).max(), np.abs(uys - uy64).max()) / umax),
+                                 "T": float(np.abs(Ts - T64).max() / np.abs(T64 - w["T0"]).max())}}
+        latsr.close()
         lat64.close()
     lat32.close()
     if not args.no_control:
         wc = W.rayleigh_benard(nx=8192, ny=4096)
-        latc, rc = run_precision(clb, W, "fp32", max(20, args.steps // 40), 10, stream.cuda_stream, wc,
-                                 args.autotune, args.tile_shape)
-        latc.close()
-        result["control_8192x4096"] = {"value": rc["mlups"], "unit": "MLUPS", "achieved_GBps": rc["gbps"],
-                                       "frac": rc["gbps"] / HBM_PEAK_GBPS, "footprint_GB": 2 * 14 * 4 * 8192 * 4096 / 1e9}
-        torch.cuda.empty_cache()
+        result["control_8192x4096"] = {}
+        for prec in ("fp32", "fp32_sr", "fp64"):
+            latc, rc = run_precision(clb, W, prec, max(20, args.steps // 40), 10, stream.cuda_stream, wc,
+                                     args.autotune, args.tile_shape if prec == "fp32" else None)
+            latc.close()
+            torch.cuda.empty_cache()
+            result["control_8192x4096"][prec] = {
+                "value": rc["mlups"], "unit": "MLUPS", "achieved_GBps": rc["gbps"], "tile_shape": rc["tile_shape"],
+                "frac": rc["gbps"] / HBM_PEAK_GBPS,
+                "footprint_GB": 2 * BYTES_PER_SITE[prec] / 2 * 8192 * 4096 / 1e9}
     if not args.no_batch:
-        result["batched_512_cavities"] = run_batch(clb, W, args.batch_steps, stream.cuda_stream)
+        result["batched_512_cavities"] = run_batch(clb, W, args.batch_steps, stream.cuda_stream, "fp32")
+        torch.cuda.empty_cache()
+        result["batched_512_cavities_fp32_sr"] = run_batch(clb, W, args.batch_steps, stream.cuda_stream,
+                                                           "fp32_sr", modes=("grouped",))
         torch.cuda.empty_cache()
     if not args.no_serve:
         result["served"] = run_serving(clb, W, stream.cuda_stream)
+        torch.cuda.empty_cache()
+        result["served_saturated"] = run_serving(clb, W, stream.cuda_stream, n=64, lam=math.inf,
+                                                 L_range=(128, 512), step_cap=20_000)
         torch.cuda.empty_cache()
     if not args.no_copy:
         cb = copy_bandwidth(torch)

@@ -286,16 +286,21 @@ int clb_batch_check(clb_batch* b);
  * on the batch's stream; writes the elapsed milliseconds.  Synchronises. */
 int clb_batch_time_steps(clb_batch* b, int mode, long long n, double* ms);
 
-/* Tile width (64, 128 or 256 nodes per row segment; 256 nodes per tile) of one lattice. */
+/* Tile width of one lattice: 64, 128 or 256 nodes per row segment (256 nodes per tile), or 0 for
+ * wrapped rows: tiles of 256 consecutive nodes in row-major order, shifted by half a wavefront so
+ * that the last node of a row and the first node of the next share one wavefront (on lattices with
+ * walls in x this halves the wavefronts that take the wall branch). */
 int clb_batch_set_tile_width(clb_batch* b, int slot, int tile_width);
 
 /* Store form of the batch's step kernels: 1 = non-temporal stores (populations written this step
  * are read next step, but at batch footprints they leave every cache before that), 0 = ordinary
- * stores.  Default: 1 for FP64 storage, 0 for FP32 storage.  Results do not depend on it. */
+ * stores.  Default (until this call or clb_batch_autotune): non-temporal once the resident lattices
+ * take more than 256 MiB, and always for FP64 storage.  Results do not depend on it. */
 int clb_batch_set_nontemporal(clb_batch* b, int nontemporal);
 
 /* For each size class (ceil(log2 nx), ceil(log2 ny)) present, time the grouped step over that
- * class's lattices with each tile width (state unchanged) and keep the fastest for the class;
+ * class's lattices with each tile width, wrapped rows included (state unchanged), and keep the
+ * fastest for the class;
  * lattices added later take the class's choice.  Then time the grouped step over the whole batch
  * with ordinary and with non-temporal stores and keep the faster.  Synchronises. */
 int clb_batch_autotune(clb_batch* b, int launches);

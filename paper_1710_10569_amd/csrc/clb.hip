@@ -139,14 +139,18 @@ static std::tuple<int, int, int> tune_key(const clb_desc& d)
     return std::make_tuple(d.precision, log2_class(d.nx), log2_class(d.ny));
 }
 
-// Without an autotuner result for the size class: 256 x 1 tiles, occupancy-8 register budget in
-// FP32 and non-temporal stores in FP64; 128 x 4 tiles for FP32 storage with FP64 arithmetic (the
-// fastest in sweeps on MI355X at 2048 x 1024 and 8192 x 4096 in real ping-pong stepping).
+// Without an autotuner result for the size class: when the two buffers fit the 256 MiB Infinity
+// Cache (MALL), ordinary stores, which leave the next step's input there -- 256 x 1 tiles with an
+// occupancy-8 register budget in FP32, 128 x 4 tiles for FP32 storage with FP64 arithmetic; beyond
+// it (and always in FP64) 256 x 1 tiles with non-temporal stores.  These were the fastest in sweeps
+// on MI355X at 2048 x 1024 and 8192 x 4096 in real ping-pong stepping.
 int default_shape(const clb_desc& d)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(tune_key(d));
     if (it != g_tune_cache.end()) return it->second;
+    const double footprint = 2.0 * double(buffer_elems(d.nx, d.ny)) * double(elem_bytes(d.precision));
+    if (footprint > double(256 << 20)) return 6;
     return d.precision == CLB_FP32_DEV ? 8 : d.precision == CLB_FP32_SR ? 4 : 6;
 }
 

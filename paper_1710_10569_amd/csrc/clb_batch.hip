@@ -41,8 +41,9 @@ struct BatchLat {
     long long snap;     // byte offset of the FP64 (u_x, u_y, T) snapshot in the pool
     int cur;            // buffer holding the current post-collision state
     uint32_t step;      // steps taken before the current call (low 32 bits): the rounding key base
-    int tw_log2;        // tile width 1 << tw_log2 (6, 7 or 8); tile rows 256 >> tw_log2
+    int tw_log2;        // tile width 1 << tw_log2 (6, 7 or 8), tile rows 256 >> tw_log2; 0: wrapped rows
     int tiles_x, ntiles;
+    double inv_nx;      // 1 / nx (wrapped rows)
 };
 
 template <typename Real>
@@ -55,13 +56,34 @@ struct TileRef { int lat, tile; };
 
 constexpr int BNT = 256;
 
+// Node of thread `lane` of work item `tile` of a lattice; false if none.  Row tiles: width
+// 1 << tw_log2, BNT >> tw_log2 rows.  Wrapped rows (tw_log2 = 0): tile t covers the row-major node
+// indices [t BNT - 32, (t + 1) BNT - 32), so that a wavefront starts half a chunk into a row: the
+// last node of a row and the first of the next share one wavefront, and only that wavefront takes
+// the wall branch of the two x-wall nodes (in row tiles each of them costs its own wavefront).
+// Wavefronts still read and write whole 32-node halves of storage chunks, i.e. whole cache lines.
+__device__ __forceinline__ bool batch_node(const BatchLat& L, int tile, int lane, int& x, int& y)
+{
+    if (L.tw_log2 == 0) {
+        const int k = tile * BNT + lane - 32;
+        if (k < 0 || k >= L.G.nx * L.G.ny) return false;
+        y = int(double(k) * L.inv_nx);
+        x = k - y * L.G.nx;
+        if (x < 0) { --y; x += L.G.nx; }
+        else if (x >= L.G.nx) { ++y; x -= L.G.nx; }
+        return true;
+    }
+    const int tyi = tile / L.tiles_x, txi = tile - tyi * L.tiles_x;
+    x = (txi << L.tw_log2) + (lane & ((1 << L.tw_log2) - 1));
+    y = tyi * (BNT >> L.tw_log2) + (lane >> L.tw_log2);
+    return x < L.G.nx && y < L.G.ny;
+}
+
 template <typename S, typename Real, bool DEV, bool NT>
 __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntry<Real>& E, int tile, int s)
 {
-    const int tyi = tile / E.L.tiles_x, txi = tile - tyi * E.L.tiles_x;
-    const int x = (txi << E.L.tw_log2) + int(threadIdx.x & ((1u << E.L.tw_log2) - 1));
-    const int y = tyi * (BNT >> E.L.tw_log2) + int(threadIdx.x >> E.L.tw_log2);
-    if (x >= E.L.G.nx || y >= E.L.G.ny) return;
+    int x, y;
+    if (!batch_node(E.L, tile, int(threadIdx.x), x, y)) return;
     // select the buffers without indexing off[] by a runtime value (which would put the entry
     // in private memory)
     const bool c = (E.L.cur ^ (s & 1)) != 0;
@@ -142,11 +164,9 @@ __global__ __launch_bounds__(BNT) void batch_residual_kernel(S* __restrict__ poo
     if (t >= ntiles) return;   // uniform over the workgroup
     const TileRef r = tiles[t];
     const BatchEntry<Real> E = lats[r.lat];
-    const int tyi = r.tile / E.L.tiles_x, txi = r.tile - tyi * E.L.tiles_x;
-    const int x = (txi << E.L.tw_log2) + int(threadIdx.x & ((1u << E.L.tw_log2) - 1));
-    const int y = tyi * (BNT >> E.L.tw_log2) + int(threadIdx.x >> E.L.tw_log2);
+    int x, y;
     double du = 0.0, dT = 0.0, bad = 0.0;
-    if (x < E.L.G.nx && y < E.L.G.ny) {
+    if (batch_node(E.L, r.tile, int(threadIdx.x), x, y)) {
         const S* src = pool + (E.L.cur ? E.L.off[1] : E.L.off[0]);
         Real f[9], g[5];
         pull(src, E.L.G, x, y, f, g);
@@ -204,7 +224,7 @@ struct BatchSlot {
     int cur = 0;
     long long steps = 0;
     bool has_snap = false;
-    int tw_log2 = 8;
+    int tw_log2 = 0;
 };
 
 constexpr size_t kAlign = 256;
@@ -219,7 +239,9 @@ size_t slot_bytes(const clb_desc& d, size_t* buf_bytes_out)
     return 2 * buf + snap;
 }
 
-int default_tw_log2(int nx) { return nx <= 96 ? 6 : (nx <= 192 ? 7 : 8); }
+// Tile mapping of a lattice whose size class has not been autotuned: wrapped rows (as fast as the
+// best row tiles on periodic lattices, faster where x has walls).
+int default_tw_log2(int) { return 0; }
 
 int size_class(const clb_desc& d)
 {
@@ -267,6 +289,7 @@ struct clb_batch {
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::map<int, int> tw_by_class;       // autotuned tile width (log2) per size class
     bool nontemporal = false;
+    bool nt_chosen = false;               // store form set by the caller or the autotuner
 };
 
 namespace {
@@ -318,9 +341,15 @@ BatchEntry<Real> make_entry(const BatchSlot& s, int tw_log2)
     E.L.cur = s.cur;
     E.L.step = uint32_t(s.steps);
     E.L.tw_log2 = tw_log2;
-    const int tw = 1 << tw_log2, th = BNT >> tw_log2;
-    E.L.tiles_x = (s.desc.nx + tw - 1) / tw;
-    E.L.ntiles = E.L.tiles_x * ((s.desc.ny + th - 1) / th);
+    E.L.inv_nx = 1.0 / double(s.desc.nx);
+    if (tw_log2 == 0) {
+        E.L.tiles_x = 0;
+        E.L.ntiles = int(((long long)s.desc.nx * s.desc.ny + 32 + BNT - 1) / BNT);
+    } else {
+        const int tw = 1 << tw_log2, th = BNT >> tw_log2;
+        E.L.tiles_x = (s.desc.nx + tw - 1) / tw;
+        E.L.ntiles = E.L.tiles_x * ((s.desc.ny + th - 1) / th);
+    }
     E.P = make_par<Real>(s.desc, s.par);
     return E;
 }
@@ -334,10 +363,12 @@ int upload_tables(clb_batch* b)
     b->first_tile.assign(cap, 0);
     b->ntiles.assign(cap, 0);
     std::vector<int> active;
+    size_t resident = 0;
     for (int i = 0; i < cap; ++i) {
         BatchSlot& s = b->slots[i];
         if (!s.used) continue;
         active.push_back(i);
+        resident += s.alloc_bytes;
         int nt;
         if (b->precision == CLB_FP32_DEV) {
             BatchEntry<float> E = make_entry<float>(s, s.tw_log2);
@@ -352,6 +383,10 @@ int upload_tables(clb_batch* b)
         b->ntiles[i] = nt;
         for (int t = 0; t < nt; ++t) b->tiles.push_back(TileRef{i, t});
     }
+    // unless chosen: non-temporal stores once the resident lattices outgrow the 256 MiB Infinity
+    // Cache (the next step's input cannot stay there anyway), and always for FP64 storage
+    if (!b->nt_chosen)
+        b->nontemporal = resident > (size_t(256) << 20) || b->precision == CLB_FP64 || b->precision == CLB_FP64_DEV;
     CLB_HIP(hipMemcpyAsync(b->d_lats, host.data(), host.size(), hipMemcpyHostToDevice, b->stream));
     if (b->tiles.size() > b->tiles_cap) {
         CLB_HIP(hipStreamSynchronize(b->stream));
@@ -908,8 +943,8 @@ extern "C" int clb_batch_set_tile_width(clb_batch* b, int slot, int tile_width)
     clear_error();
     int rc = check_slot(b, slot);
     if (rc) return rc;
-    const int lg = tile_width == 64 ? 6 : tile_width == 128 ? 7 : tile_width == 256 ? 8 : -1;
-    if (lg < 0) { set_error("tile width must be 64, 128 or 256"); return CLB_EINVAL; }
+    const int lg = tile_width == 64 ? 6 : tile_width == 128 ? 7 : tile_width == 256 ? 8 : tile_width == 0 ? 0 : -1;
+    if (lg < 0) { set_error("tile width must be 64, 128, 256 or 0 (wrapped rows)"); return CLB_EINVAL; }
     b->slots[slot].tw_log2 = lg;
     b->dirty = true;
     return CLB_OK;
@@ -927,7 +962,7 @@ extern "C" int clb_batch_autotune(clb_batch* b, int launches)
     for (auto& kv : classes) {
         int best = -1;
         double best_t = 0.0;
-        for (int lg = 6; lg <= 8; ++lg) {
+        for (int lg : {6, 7, 8, 0}) {
             std::vector<bool> keep(b->capacity, false);
             for (int i : kv.second) keep[i] = true;
             // restrict the tables to this class with width lg
@@ -977,6 +1012,7 @@ extern "C" int clb_batch_autotune(clb_batch* b, int launches)
         t_store[v] = ms;
     }
     b->nontemporal = t_store[1] < t_store[0];
+    b->nt_chosen = true;
     return CLB_OK;
 }
 
@@ -985,6 +1021,7 @@ extern "C" int clb_batch_set_nontemporal(clb_batch* b, int nontemporal)
     clear_error();
     if (!b) { set_error("batch is NULL"); return CLB_EINVAL; }
     b->nontemporal = nontemporal != 0;
+    b->nt_chosen = true;
     return CLB_OK;
 }
 

@@ -57,6 +57,29 @@ def test_batch_equals_alone(gpu, precision, mode):
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_sr"])
+@pytest.mark.parametrize("width", [0, 64, 256])
+def test_tile_width_keeps_results(gpu, precision, width):
+    """Every batch tile mapping -- row tiles of width 64 or 256 and wrapped rows (0: row-major
+    tiles shifted by half a wavefront) -- covers each node once with the same per-node update: the
+    lattices match the single-lattice path bitwise, and so do the residuals' snapshots."""
+    clb = _clb()
+    ws = mixed_workloads()
+    b = clb.Batch(16, precision, budget_bytes=256 << 20)
+    slots = [b.add_workload(w) for w in ws]
+    for s in slots:
+        b.set_tile_width(s, width)
+    print(f"[batch] {precision} width={width}", flush=True)
+    b.step(31)
+    res = b.residuals()
+    b.step(26)
+    for w, s in zip(ws, slots):
+        for a, r in zip(b.moments(s), alone(w, precision, 57)):
+            assert np.array_equal(a, r), (w["name"], width)
+        assert res[s][2] == 0 and np.isfinite(res[s][0]) and res[s][0] > 0
+    b.close()
+
+
 def test_batch_fp64_matches_oracle(gpu):
     clb = _clb()
     ws = mixed_workloads()[:3]
