@@ -260,7 +260,8 @@ def main():
     result["roofline"] = {"bound": "hbm", "achieved": r32["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                           "frac": r32["gbps"] / HBM_PEAK_GBPS,
                           "traffic": traffic,
-                          "kernel": "step_tile_kernel<float, DEV=true, tile %s>" % (r32["tile_shape"],),
+                          "kernel": "step_tile_kernel<float, float, DEV=true> tile (tx, ty, nodes/thread, "
+                                    "non-temporal) = %s" % (r32["tile_shape"],),
                           "algorithmic_bytes_per_launch": BYTES_PER_SITE["fp32"] * sites,
                           "avg_launch_us": r32["ms_per_step"] * 1e3}
     if not args.no_fp64:
