@@ -305,3 +305,85 @@ def test_zou_he_textbook_case():
     assert out[2] == pytest.approx(f[4], abs=1e-16)
     assert out[5] == pytest.approx(f[7] - (f[1] - f[3]) / 2, abs=1e-16)
     assert out[6] == pytest.approx(f[8] + (f[1] - f[3]) / 2, abs=1e-16)
+
+
+def _solve_exact(A, b):
+    """Gauss-Jordan elimination over the rationals (A: list of rows of Fractions)."""
+    from fractions import Fraction
+    n = len(b)
+    M = [list(A[r]) + [b[r]] for r in range(n)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[p] = M[p], M[c]
+        piv = M[c][c]
+        M[c] = [v / piv for v in M[c]]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                fac = M[r][c]
+                M[r] = [a - fac * bb for a, bb in zip(M[r], M[c])]
+    return [M[r][n] for r in range(n)]
+
+
+def test_one_step_in_exact_rationals():
+    """One whole time step (macroscopic quantities with buoyancy and a body force, both CLB
+    collisions, periodic streaming) on a 4 x 4 lattice evaluated in exact rational arithmetic
+    through the moment definitions (Eqs. 5, 14), Eq. 8 / Eq. 19 and Eqs. 12, 22, against the oracle
+    in FP64: every population agrees to FP64 rounding."""
+    from fractions import Fraction as Fr
+    rng = np.random.default_rng(31)
+    nx = ny = 4
+    f0 = rng.integers(32, 160, size=(9, ny, nx)) / 1024.0        # dyadic: exact in FP64
+    g0 = rng.integers(32, 160, size=(5, ny, nx)) / 1024.0
+    tau_nu, tau_a, g_beta, T0 = 0.625, 0.875, 1.0 / 64, 0.25
+    s_b, s3, s4, lam2 = 1.25, 0.75, 1.5, 0.875
+    Fvx, Fvy = 1.0 / 512, -1.0 / 1024
+    L = O.OracleLattice(nx, ny, T0=T0)
+    L.set_params(tau_nu, tau_a, g_beta)
+    L.set_relaxation(s_b, s3, s4, lam2)
+    L.set_body_force(Fvx, Fvy)
+    L.set_state(f0, g0)
+    L.step(1)
+    f1, g1 = L.get_state()
+    L.close()
+
+    ex = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    ey = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    s_nu, lam1 = 1 / Fr(tau_nu), 1 / Fr(tau_a)
+    S = [[Fr(0)] * 9 for _ in range(9)]
+    S[0][0] = S[1][1] = S[2][2] = Fr(0)
+    S[3][3] = S[4][4] = (Fr(s_b) + s_nu) / 2
+    S[3][4] = S[4][3] = (Fr(s_b) - s_nu) / 2
+    S[5][5], S[6][6], S[7][7], S[8][8] = s_nu, Fr(s3), Fr(s3), Fr(s4)
+    ST = [Fr(1), lam1, lam1, Fr(lam2), Fr(lam2)]
+    ref_f = [[[None] * nx for _ in range(ny)] for _ in range(9)]
+    ref_g = [[[None] * nx for _ in range(ny)] for _ in range(5)]
+    for y in range(ny):
+        for x in range(nx):
+            f = [Fr(float(f0[i, y, x])) for i in range(9)]
+            g = [Fr(float(g0[i, y, x])) for i in range(5)]
+            T = sum(g)
+            Fx = Fr(Fvx)
+            Fy = Fr(Fvy) + Fr(g_beta) * (T - Fr(T0))
+            rho = sum(f)
+            ux = (sum(f[i] * ex[i] for i in range(9)) + Fx / 2) / rho
+            uy = (sum(f[i] * ey[i] for i in range(9)) + Fy / 2) / rho
+            K = [[(ex[i] - ux) ** m * (ey[i] - uy) ** n for i in range(9)] for (m, n) in MN9]
+            k = [sum(K[r][i] * f[i] for i in range(9)) for r in range(9)]
+            keq = [rho, 0, 0, rho / 3, rho / 3, 0, 0, 0, rho / 9]
+            C = [0, Fx, Fy, 0, 0, 0, Fy / 3, Fx / 3, 0]
+            post = [k[r] - sum(S[r][c] * (k[c] - keq[c]) for c in range(9))
+                    + C[r] - sum(S[r][c] * C[c] for c in range(9)) / 2 for r in range(9)]
+            fs = _solve_exact(K, post)
+            K5 = [[(ex[i] - ux) ** m * (ey[i] - uy) ** n for i in range(5)] for (m, n) in MN5]
+            kT = [sum(K5[r][i] * g[i] for i in range(5)) for r in range(5)]
+            kTeq = [T, 0, 0, T / 4, T / 4]
+            postT = [kT[r] - ST[r] * (kT[r] - kTeq[r]) for r in range(5)]
+            gs = _solve_exact(K5, postT)
+            for i in range(9):
+                ref_f[i][(y + ey[i]) % ny][(x + ex[i]) % nx] = fs[i]
+            for i in range(5):
+                ref_g[i][(y + ey[i]) % ny][(x + ex[i]) % nx] = gs[i]
+    rf = np.array([[[float(v) for v in row] for row in pl] for pl in ref_f])
+    rg = np.array([[[float(v) for v in row] for row in pl] for pl in ref_g])
+    # measured 1.7e-16 (f, values up to 0.47) and 5.6e-17 (g): a few ulps of accumulated rounding
+    assert np.abs(f1 - rf).max() < 1e-15 and np.abs(g1 - rg).max() < 1e-15
