@@ -267,3 +267,34 @@ def test_served_fp32_matches_fp64_oracle(gpu):
     for e, e0 in zip(sr, rtn):
         assert e["u"] < 1e-5 and e["T"] < 1e-5, e
         assert max(e["u"], e["T"]) * 10 < max(e0["u"], e0["T"]), (e, e0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_sr"])
+def test_full_batch_sampled_against_oracle(gpu, precision):
+    """The 512-cavity batch in the launch configuration the benchmark times (one grouped launch
+    per step over all cavities, autotuned tile mappings and store form), 200 steps: a sample of
+    cavities (three of side 64, three of 96, two of 128) compared node by node with the oracle
+    within 1e-5 in u and T, and every cavity finite."""
+    clb = _clb()
+    specs = W.batch_cavity_specs()
+    budget = sum(clb.footprint(L, L, precision) for L, _, _ in specs) + (64 << 20)
+    b = clb.Batch(len(specs), precision, budget_bytes=budget)
+    slots = [b.add_workload(W.cavity(L, Ra=Ra, seed=sd)) for L, Ra, sd in specs]
+    assert all(s is not None for s in slots)
+    b.autotune(2)          # leaves the state untouched
+    b.step(200, "grouped")
+    b.check()
+    res = b.residuals()
+    assert not any(v[2] for v in res.values())
+    picked = []
+    for L, count in ((64, 3), (96, 3), (128, 2)):
+        picked += [i for i, sp in enumerate(specs) if sp[0] == L][:count]
+    for i in picked:
+        L, Ra, sd = specs[i]
+        w = W.cavity(L, Ra=Ra, seed=sd)
+        o = oracle_from_workload(w)
+        o.step(200)
+        e = field_errors(b.moments(slots[i]), o.moments(), w["T0"], w["u_scale"])
+        print(f"[batch] full batch {precision} cavity {i} L={L} Ra={Ra:.3g}: {e}", flush=True)
+        assert e["u"] < 1e-5 and e["T"] < 1e-5, (i, e)
+    b.close()
