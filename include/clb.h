@@ -78,6 +78,10 @@ typedef struct {
     int prescribed_u;  /* 1: temperature-only lattice (Sec. 3.1): the velocity is prescribed,
                           uniform and constant, and only the D2Q5 equation is advanced; 0: the
                           coupled flow and temperature problem */
+    int in_place;      /* 1: in-place streaming (one population buffer, half the footprint; same
+                          results bitwise as 0, the two-buffer pull streaming of Eqs. 12 and 22).
+                          Not with prescribed_u; at least 4 nodes across a walled direction;
+                          single lattices only (clb_batch_add rejects it) */
 } clb_desc;
 
 typedef struct clb_lattice clb_lattice;

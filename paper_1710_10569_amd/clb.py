@@ -42,7 +42,7 @@ class clb_edge(ctypes.Structure):
 class clb_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("precision", ctypes.c_int),
                 ("west", clb_edge), ("east", clb_edge), ("south", clb_edge), ("north", clb_edge),
-                ("T0", ctypes.c_double), ("prescribed_u", ctypes.c_int)]
+                ("T0", ctypes.c_double), ("prescribed_u", ctypes.c_int), ("in_place", ctypes.c_int)]
 
 
 class clb_diag(ctypes.Structure):
@@ -140,9 +140,9 @@ def tile_shapes():
     return out
 
 
-def make_desc(nx, ny, precision="fp64", edges=None, T0=0.0, prescribed=False):
+def make_desc(nx, ny, precision="fp64", edges=None, T0=0.0, prescribed=False, in_place=False):
     """clb_desc from sizes, a precision name or code, and {edge: (kind, ux, uy, T)}; prescribed:
-    temperature-only lattice with a prescribed velocity."""
+    temperature-only lattice with a prescribed velocity; in_place: one population buffer."""
     d = clb_desc()
     d.nx, d.ny = int(nx), int(ny)
     d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -152,14 +152,15 @@ def make_desc(nx, ny, precision="fp64", edges=None, T0=0.0, prescribed=False):
         setattr(d, name, clb_edge(KINDS[kind] if isinstance(kind, str) else int(kind), ux, uy, T))
     d.T0 = float(T0)
     d.prescribed_u = 1 if prescribed else 0
+    d.in_place = 1 if in_place else 0
     return d
 
 
 class Lattice:
     """One lattice on the current HIP device (clb_create ... clb_destroy)."""
 
-    def __init__(self, nx, ny, precision="fp64", edges=None, T0=0.0, stream=None, prescribed=False):
-        self.desc = make_desc(nx, ny, precision, edges, T0, prescribed)
+    def __init__(self, nx, ny, precision="fp64", edges=None, T0=0.0, stream=None, prescribed=False, in_place=False):
+        self.desc = make_desc(nx, ny, precision, edges, T0, prescribed, in_place)
         self.nx, self.ny = int(nx), int(ny)
         h = _H()
         _check(_lib.clb_create(ctypes.byref(self.desc), None if stream is None else _vp(int(stream)),
@@ -265,10 +266,10 @@ class Lattice:
         return d.as_dict()
 
 
-def lattice_from_workload(w, precision="fp64", stream=None):
+def lattice_from_workload(w, precision="fp64", stream=None, in_place=False):
     """A Lattice set up and initialised from a workload description (see workloads.py)."""
     lat = Lattice(w["nx"], w["ny"], precision, w["edges"], w["T0"], stream=stream,
-                  prescribed="prescribed_u" in w)
+                  prescribed="prescribed_u" in w, in_place=in_place)
     if "prescribed_u" in w:
         lat.set_prescribed_velocity(*w["prescribed_u"])
     if "taus" in w:

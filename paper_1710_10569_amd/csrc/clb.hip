@@ -76,6 +76,12 @@ int validate_desc(const clb_desc* d)
     }
     if (!std::isfinite(d->T0)) { set_error("T0 not finite"); return CLB_EINVAL; }
     if (d->prescribed_u != 0 && d->prescribed_u != 1) { set_error("prescribed_u must be 0 or 1"); return CLB_EINVAL; }
+    if (d->in_place != 0 && d->in_place != 1) { set_error("in_place must be 0 or 1"); return CLB_EINVAL; }
+    if (d->in_place && d->prescribed_u) { set_error("in-place streaming is not available for temperature-only lattices"); return CLB_EINVAL; }
+    if (d->in_place && ((d->west.kind != CLB_PERIODIC && d->nx < 4) || (d->south.kind != CLB_PERIODIC && d->ny < 4))) {
+        set_error("in-place streaming needs at least 4 nodes across a walled direction");
+        return CLB_EINVAL;
+    }
     return CLB_OK;
 }
 
@@ -103,6 +109,21 @@ static hipError_t launch_one_step(clb_lattice* h, int shape, const void* src, vo
     const clb_desc& d = h->desc;
     const Geo G = make_geo(d);
     const uint32_t key = step_key(uint32_t(step));
+    if (d.in_place) {
+        // src is the buffer, dst the snapshot pair; the parity of the step picks the form and the copies
+        const bool odd = (step & 1) != 0;
+        const bool nt = h->buf_bytes > (size_t(256) << 20);
+        const size_t sb = size_t(snap_elems(d.nx, d.ny)) * elem_bytes(d.precision);
+        void* A = const_cast<void*>(src);
+        const void* snow = (const char*)dst + (odd ? sb : 0);
+        void* snext = (char*)dst + (odd ? 0 : sb);
+        switch (d.precision) {
+        case CLB_FP64: return launch_step_aa<double, double, false>(odd, nt, A, snow, snext, G, make_par<double>(d, h->par), key, h->stream);
+        case CLB_FP64_DEV: return launch_step_aa<double, double, true>(odd, nt, A, snow, snext, G, make_par<double>(d, h->par), key, h->stream);
+        case CLB_FP32_SR: return launch_step_aa<float, double, true>(odd, nt, A, snow, snext, G, make_par<double>(d, h->par), key, h->stream);
+        default: return launch_step_aa<float, float, true>(odd, nt, A, snow, snext, G, make_par<float>(d, h->par), key, h->stream);
+        }
+    }
     if (d.prescribed_u) {
         switch (d.precision) {
         case CLB_FP64: return launch_step_T<double, double, false>(src, dst, G, make_par<double>(d, h->par), key, h->stream);
@@ -121,6 +142,13 @@ static hipError_t launch_one_step(clb_lattice* h, int shape, const void* src, vo
 
 static int launch_step(clb_lattice* h, long long n)
 {
+    if (h->desc.in_place) {
+        for (long long s = 0; s < n; ++s) {
+            CLB_HIP(launch_one_step(h, h->shape, h->buf[0], h->snap, h->steps));
+            h->steps += 1;
+        }
+        return CLB_OK;
+    }
     for (long long s = 0; s < n; ++s) {
         CLB_HIP(launch_one_step(h, h->shape, h->buf[h->cur], h->buf[h->cur ^ 1], h->steps));
         h->cur ^= 1;
@@ -157,6 +185,12 @@ int default_shape(const clb_desc& d)
 static int launch_moments(clb_lattice* h)
 {
     const Geo G = make_geo(h->desc);
+    if (h->desc.in_place) {
+        const size_t sb = size_t(snap_elems(h->desc.nx, h->desc.ny)) * elem_bytes(h->desc.precision);
+        CLB_HIP(enqueue_moments_aa(h->desc, h->par, (h->steps & 1) != 0, h->buf[0], (const char*)h->snap + (h->steps & 1) * sb,
+                                   G, h->d_fields, h->stream));
+        return CLB_OK;
+    }
     CLB_HIP(enqueue_moments(h->desc, h->par, h->buf[h->cur], G, h->d_fields, h->stream));
     return CLB_OK;
 }
@@ -206,6 +240,7 @@ extern "C" void clb_destroy(clb_lattice* h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     (void)hipFree(h->buf[0]);
     (void)hipFree(h->buf[1]);
+    (void)hipFree(h->snap);
     (void)hipFree(h->d_fields);
     (void)hipFree(h->d_snap);
     (void)hipFree(h->d_partials);
@@ -235,14 +270,26 @@ static int create_impl(const clb_desc* desc, void* hip_stream, clb_lattice** out
     const size_t eb = elem_bytes(desc->precision);
     h->buf_bytes = size_t(buffer_elems(desc->nx, desc->ny)) * eb;
     const size_t n = size_t(desc->nx) * desc->ny;
-    if (hipMalloc(&h->buf[0], h->buf_bytes) != hipSuccess || hipMalloc(&h->buf[1], h->buf_bytes) != hipSuccess ||
-        hipMalloc((void**)&h->d_fields, 4 * n * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        set_error("device allocation of %zu bytes failed", 2 * h->buf_bytes + 4 * n * sizeof(double));
-        return CLB_ENOMEM;
+    if (desc->in_place) {
+        const size_t sb = 2 * size_t(snap_elems(desc->nx, desc->ny)) * eb;
+        if (hipMalloc(&h->buf[0], h->buf_bytes) != hipSuccess || hipMalloc(&h->snap, sb) != hipSuccess ||
+            hipMalloc((void**)&h->d_fields, 4 * n * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("device allocation of %zu bytes failed", h->buf_bytes + sb + 4 * n * sizeof(double));
+            return CLB_ENOMEM;
+        }
+        CLB_HIP(hipMemsetAsync(h->buf[0], 0, h->buf_bytes, h->stream));
+        CLB_HIP(hipMemsetAsync(h->snap, 0, sb, h->stream));
+    } else {
+        if (hipMalloc(&h->buf[0], h->buf_bytes) != hipSuccess || hipMalloc(&h->buf[1], h->buf_bytes) != hipSuccess ||
+            hipMalloc((void**)&h->d_fields, 4 * n * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("device allocation of %zu bytes failed", 2 * h->buf_bytes + 4 * n * sizeof(double));
+            return CLB_ENOMEM;
+        }
+        CLB_HIP(hipMemsetAsync(h->buf[0], 0, h->buf_bytes, h->stream));
+        CLB_HIP(hipMemsetAsync(h->buf[1], 0, h->buf_bytes, h->stream));
     }
-    CLB_HIP(hipMemsetAsync(h->buf[0], 0, h->buf_bytes, h->stream));
-    CLB_HIP(hipMemsetAsync(h->buf[1], 0, h->buf_bytes, h->stream));
     CLB_HIP(hipEventCreate(&h->ev[0]));
     CLB_HIP(hipEventCreate(&h->ev[1]));
     return clb_init(h, nullptr, nullptr, nullptr);
@@ -351,7 +398,8 @@ extern "C" int clb_init(clb_lattice* h, const double* rho, const double* u, cons
     if (e != hipSuccess) { set_error("upload of initial fields failed: %s", hipGetErrorString(e)); return CLB_EDEVICE; }
     const Geo G = make_geo(d);
     h->cur = 0;
-    CLB_HIP(enqueue_init(d, h->par, h->buf[0], G, h->d_fields, h->stream));
+    if (d.in_place) CLB_HIP(enqueue_init_aa(d, h->par, h->buf[0], h->snap, G, h->d_fields, h->stream));
+    else CLB_HIP(enqueue_init(d, h->par, h->buf[0], G, h->d_fields, h->stream));
     h->steps = 0;
     h->has_snap = false;
     return CLB_OK;
@@ -469,6 +517,7 @@ extern "C" int clb_autotune(clb_lattice* h, int launches_per_shape, int* best_sh
     clear_error();
     if (!h) { set_error("handle is NULL"); return CLB_EINVAL; }
     if (launches_per_shape <= 0) { set_error("launches_per_shape must be positive"); return CLB_EINVAL; }
+    if (h->desc.in_place) { set_error("in-place lattices have one step kernel; tile shapes apply to two-buffer streaming"); return CLB_ESTATE; }
     void* scratch[2];
     scratch_pair(h, scratch);
     int best = -1;
@@ -495,6 +544,7 @@ extern "C" int clb_time_shape(clb_lattice* h, int shape, int launches, double* u
     clear_error();
     if (!h || !us) { set_error("NULL argument"); return CLB_EINVAL; }
     if (shape < 0 || shape >= kNumShapes || launches <= 0) { set_error("bad shape or launch count"); return CLB_EINVAL; }
+    if (h->desc.in_place) { set_error("in-place lattices have one step kernel; tile shapes apply to two-buffer streaming"); return CLB_ESTATE; }
     void* scratch[2];
     scratch_pair(h, scratch);
     const int rc = time_shape_impl(h, shape, launches, scratch, us);
@@ -533,7 +583,8 @@ extern "C" int clb_get_populations(clb_lattice* h, double* f, double* g)
     double* dev = nullptr;
     CLB_HIP(hipMalloc((void**)&dev, 14 * n * sizeof(double)));
     const Geo G = make_geo(d);
-    hipError_t e = enqueue_populations(d, h->buf[h->cur], G, dev, h->stream);
+    hipError_t e = d.in_place ? enqueue_populations_aa(d, (h->steps & 1) != 0, h->buf[0], G, dev, h->stream)
+                              : enqueue_populations(d, h->buf[h->cur], G, dev, h->stream);
     if (e == hipSuccess && f) e = hipMemcpyAsync(f, dev, 9 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess && g) e = hipMemcpyAsync(g, dev + 9 * n, 5 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

@@ -2,6 +2,7 @@
 // single-lattice and batched front ends, with host-side enqueue helpers.
 #pragma once
 
+#include "clb_inplace.h"
 #include "clb_internal.h"
 
 namespace clb {
@@ -110,6 +111,71 @@ __global__ void populations_kernel(const S* __restrict__ src, Geo G, double TR, 
         const bool known = source_of(G, x, y, i, sx, sy);
         if (fo) fo[i * n + k] = known ? double(f[i]) + (DEV ? W9[i] : 0.0) : __builtin_nan("");
         if (i < 5 && go) go[i * n + k] = known ? double(g[i]) + (DEV ? W5[i] * TR : 0.0) : __builtin_nan("");
+    }
+}
+
+// In-place lattices (clb_inplace.h): initial state in the even-time form (population i of node x
+// in slot i of x) plus snapshot copy 0; moments and exported populations read the form of the
+// current time's parity and take the wall step's neighbours from the current snapshot copy.
+template <typename S, bool DEV>
+__global__ void init_aa_kernel(S* __restrict__ A, S* __restrict__ snap0, Geo G, const double* __restrict__ fields,
+                               double g_beta, double T0, double Fvx, double Fvy, double TR)
+{
+    const int x = blockIdx.x * TX + threadIdx.x;
+    const int y = blockIdx.y * TY + threadIdx.y;
+    if (x >= G.nx || y >= G.ny) return;
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)y * G.nx + x;
+    const double rho = fields[k], ux = fields[n + k], uy = fields[2 * n + k], T = fields[3 * n + k];
+    const double Fx = Fvx, Fy = Fvy + g_beta * (T - T0);
+    const double vx = ux - 0.5 * Fx / rho, vy = uy - 0.5 * Fy / rho;
+    const double gq[5] = {T * (0.5 - ux * ux - uy * uy), 0.5 * T * (0.25 + ux + ux * ux),
+                          0.5 * T * (0.25 + uy + uy * uy), 0.5 * T * (0.25 - ux + ux * ux),
+                          0.5 * T * (0.25 - uy + uy * uy)};
+    const long long o = pop_at(G, x, y);
+    for (int q = 0; q < 14; ++q) {
+        double v = q < 9 ? rho * psi(EXd[q], vx) * psi(EYd[q], vy) : gq[q - 9];
+        if (DEV) v -= q < 9 ? W9[q] : W5[q - 9] * TR;
+        A[o + q * CW] = S(v);
+        snap_put(snap0, G, x, y, q, S(v));
+    }
+}
+
+template <typename S, typename Real, bool DEV, bool ODD>
+__global__ __launch_bounds__(TX * TY) void moments_aa_kernel(const S* __restrict__ A, const S* __restrict__ snow, Geo G,
+                                                           Par<Real> P, double* __restrict__ fields)
+{
+    const int x = blockIdx.x * TX + threadIdx.x;
+    const int y = blockIdx.y * TY + threadIdx.y;
+    if (x >= G.nx || y >= G.ny) return;
+    Real f[9], g[5];
+    load_aa<S, Real, ODD>(A, G, x, y, f, g);
+    if (on_wall(G, x, y)) wall_step_nb<Real, DEV>(SnapSource<S>{snow}, G, P, x, y, f, g);
+    const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)y * G.nx + x;
+    fields[k] = double(m.rho);
+    fields[n + k] = double(m.ux);
+    fields[2 * n + k] = double(m.uy);
+    fields[3 * n + k] = double(P.TR) + double(m.dT);
+}
+
+template <typename S, bool DEV, bool ODD>
+__global__ void populations_aa_kernel(const S* __restrict__ A, Geo G, double TR, double* __restrict__ fo,
+                                      double* __restrict__ go)
+{
+    const int x = blockIdx.x * TX + threadIdx.x;
+    const int y = blockIdx.y * TY + threadIdx.y;
+    if (x >= G.nx || y >= G.ny) return;
+    double f[9], g[5];
+    load_aa<S, double, ODD>(A, G, x, y, f, g);
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)y * G.nx + x;
+    for (int i = 0; i < 9; ++i) {
+        int sx, sy;
+        const bool known = source_of(G, x, y, i, sx, sy);
+        if (fo) fo[i * n + k] = known ? f[i] + (DEV ? W9[i] : 0.0) : __builtin_nan("");
+        if (i < 5 && go) go[i * n + k] = known ? g[i] + (DEV ? W5[i] * TR : 0.0) : __builtin_nan("");
     }
 }
 
@@ -254,6 +320,62 @@ inline hipError_t enqueue_populations(const clb_desc& d, const void* buf, const 
     case CLB_FP64_DEV: populations_kernel<double, true><<<grid, block, 0, st>>>((const double*)buf, G, TR, d_out, d_out + 9 * n); break;
     case CLB_FP32_SR:
     default: populations_kernel<float, true><<<grid, block, 0, st>>>((const float*)buf, G, TR, d_out, d_out + 9 * n); break;
+    }
+    return hipGetLastError();
+}
+
+// In-place counterparts (snapshot copies: elements snap_elems(nx, ny) each, copy c at snap + c * that).
+inline hipError_t enqueue_init_aa(const clb_desc& d, const Params& p, void* A, void* snap0, const Geo& G,
+                                  const double* d_fields, hipStream_t st)
+{
+    const double TR = is_dev(d.precision) ? d.T0 : 0.0;
+    const dim3 grid = node_grid(G), block(TX, TY);
+    switch (d.precision) {
+    case CLB_FP64: init_aa_kernel<double, false><<<grid, block, 0, st>>>((double*)A, (double*)snap0, G, d_fields, p.g_beta, d.T0, p.Fvx, p.Fvy, TR); break;
+    case CLB_FP64_DEV: init_aa_kernel<double, true><<<grid, block, 0, st>>>((double*)A, (double*)snap0, G, d_fields, p.g_beta, d.T0, p.Fvx, p.Fvy, TR); break;
+    default: init_aa_kernel<float, true><<<grid, block, 0, st>>>((float*)A, (float*)snap0, G, d_fields, p.g_beta, d.T0, p.Fvx, p.Fvy, TR); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename S, typename Real, bool DEV>
+inline void moments_aa_launch(bool odd, const void* A, const void* snow, const Geo& G, const Par<Real>& P, double* d_fields,
+                              hipStream_t st)
+{
+    const dim3 grid = node_grid(G), block(TX, TY);
+    if (odd) moments_aa_kernel<S, Real, DEV, true><<<grid, block, 0, st>>>((const S*)A, (const S*)snow, G, P, d_fields);
+    else moments_aa_kernel<S, Real, DEV, false><<<grid, block, 0, st>>>((const S*)A, (const S*)snow, G, P, d_fields);
+}
+
+inline hipError_t enqueue_moments_aa(const clb_desc& d, const Params& p, bool odd, const void* A, const void* snow,
+                                     const Geo& G, double* d_fields, hipStream_t st)
+{
+    switch (d.precision) {
+    case CLB_FP64: moments_aa_launch<double, double, false>(odd, A, snow, G, make_par<double>(d, p), d_fields, st); break;
+    case CLB_FP64_DEV: moments_aa_launch<double, double, true>(odd, A, snow, G, make_par<double>(d, p), d_fields, st); break;
+    case CLB_FP32_SR: moments_aa_launch<float, double, true>(odd, A, snow, G, make_par<double>(d, p), d_fields, st); break;
+    default: moments_aa_launch<float, float, true>(odd, A, snow, G, make_par<float>(d, p), d_fields, st); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename S, bool DEV>
+inline void populations_aa_launch(bool odd, const void* A, const Geo& G, double TR, double* fo, double* go, hipStream_t st)
+{
+    const dim3 grid = node_grid(G), block(TX, TY);
+    if (odd) populations_aa_kernel<S, DEV, true><<<grid, block, 0, st>>>((const S*)A, G, TR, fo, go);
+    else populations_aa_kernel<S, DEV, false><<<grid, block, 0, st>>>((const S*)A, G, TR, fo, go);
+}
+
+inline hipError_t enqueue_populations_aa(const clb_desc& d, bool odd, const void* A, const Geo& G, double* d_out,
+                                         hipStream_t st)
+{
+    const size_t n = size_t(d.nx) * d.ny;
+    const double TR = is_dev(d.precision) ? d.T0 : 0.0;
+    switch (d.precision) {
+    case CLB_FP64: populations_aa_launch<double, false>(odd, A, G, TR, d_out, d_out + 9 * n, st); break;
+    case CLB_FP64_DEV: populations_aa_launch<double, true>(odd, A, G, TR, d_out, d_out + 9 * n, st); break;
+    default: populations_aa_launch<float, true>(odd, A, G, TR, d_out, d_out + 9 * n, st); break;
     }
     return hipGetLastError();
 }

@@ -681,6 +681,7 @@ extern "C" int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, 
     if (rc) return rc;
     if (desc->precision != b->precision) { set_error("lattice precision differs from the batch's"); return CLB_EINVAL; }
     if (desc->prescribed_u) { set_error("temperature-only lattices (prescribed_u) are single-lattice only"); return CLB_EINVAL; }
+    if (desc->in_place) { set_error("in-place lattices are single-lattice only"); return CLB_EINVAL; }
     rc = check_params(tau_nu, tau_alpha, g_beta, Ma);
     if (rc) return rc;
     int free_slot = -1;

@@ -280,9 +280,20 @@ __device__ __forceinline__ void nee_g(Real g[5], const Real gf[5], Real dTbf, Re
 //      at the equilibrium velocities u_w - F_b/(2 rho_f) and u_f - F_f/(2 rho_f).
 // Corner data: velocity of the west/east wall; temperature of a Dirichlet wall if one meets
 // there, the west/east wall's otherwise.
-template <typename S, typename Real, bool DEV>
-__device__ __forceinline__ void wall_step(const S* __restrict__ src, const Geo& G, const Par<Real>& P,
-                                       int x, int y, Real f[9], Real g[5])
+// Post-streaming populations of a node other than the one being updated (the wall step's inner
+// neighbours), read by pull from the previous step's buffer.
+template <typename S>
+struct PullSource {
+    const S* src;
+    template <typename Real>
+    __device__ __forceinline__ void all(const Geo& G, int x, int y, Real f[9], Real g[5]) const { pull(src, G, x, y, f, g); }
+    template <typename Real>
+    __device__ __forceinline__ void temp(const Geo& G, int x, int y, Real g[5]) const { pull_g(src, G, x, y, g); }
+};
+
+template <typename Real, bool DEV, typename NB>
+__device__ __forceinline__ void wall_step_nb(const NB& nb, const Geo& G, const Par<Real>& P,
+                                             int x, int y, Real f[9], Real g[5])
 {
     const bool onW = !G.perx && x == 0, onE = !G.perx && x == G.nx - 1;
     const bool onS = !G.pery && y == 0, onN = !G.pery && y == G.ny - 1;
@@ -300,7 +311,7 @@ __device__ __forceinline__ void wall_step(const S* __restrict__ src, const Geo& 
     const Real uwy = sel4(P.uw[0][1], P.uw[1][1], P.uw[2][1], P.uw[3][1], vw);
 
     Real ff[9], gf[5];
-    pull(src, G, x + dx, y + dy, ff, gf);
+    nb.all(G, x + dx, y + dy, ff, gf);
     const Macro<Real, DEV> mf = macro<Real, DEV>(ff, gf, P);
 
     Real dTb;
@@ -308,7 +319,7 @@ __device__ __forceinline__ void wall_step(const S* __restrict__ src, const Geo& 
         dTb = sel4(P.dTw[0], P.dTw[1], P.dTw[2], P.dTw[3], tw);
     } else {
         Real gff[5];
-        pull_g(src, G, x + 2 * dx, y + 2 * dy, gff);
+        nb.temp(G, x + 2 * dx, y + 2 * dy, gff);
         const Real dTff = (gff[0] + gff[1]) + (gff[2] + gff[3]) + gff[4];
         dTb = (Real(4) * mf.dT - dTff) * Real(1.0 / 3.0);
     }
@@ -326,6 +337,13 @@ __device__ __forceinline__ void wall_step(const S* __restrict__ src, const Geo& 
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = ff[i] + mf.rho * d[i];
     }
+}
+
+template <typename S, typename Real, bool DEV>
+__device__ __forceinline__ void wall_step(const S* __restrict__ src, const Geo& G, const Par<Real>& P,
+                                       int x, int y, Real f[9], Real g[5])
+{
+    wall_step_nb<Real, DEV>(PullSource<S>{src}, G, P, x, y, f, g);
 }
 
 __device__ __forceinline__ bool on_wall(const Geo& G, int x, int y)
@@ -492,16 +510,13 @@ __device__ __forceinline__ float round_stochastic(double v, uint32_t u)
     return float(__longlong_as_double((long long)b));
 }
 
-// Store the 14 post-collision populations of node `node` (= y * nx + x) whose population 0 is at
-// offset o.  For FP32
+// Round the 14 post-collision populations of node `node` (= y * nx + x) to the storage type; for FP32
 // storage of FP64 values the node draws one word fmix32(node + key) and six more by xorshift32
 // from it; each word's two 16-bit halves round two populations.  The rounding of a node thus
 // depends only on (node, step), never on the tile shape or the batch.
-template <typename S, typename Real, bool NT>
-__device__ __forceinline__ void store_node(S* __restrict__ dst, long long o, const Real f[9], const Real g[5],
-                                           uint32_t key, uint32_t node)
+template <typename S, typename Real>
+__device__ __forceinline__ void round_node(const Real f[9], const Real g[5], uint32_t key, uint32_t node, S v[14])
 {
-    S v[14];
     if constexpr (sizeof(S) == 4 && sizeof(Real) == 8) {
         uint32_t r = fmix32(node + key);
 #pragma unroll
@@ -518,6 +533,15 @@ __device__ __forceinline__ void store_node(S* __restrict__ dst, long long o, con
 #pragma unroll
         for (int i = 0; i < 5; ++i) v[9 + i] = S(g[i]);
     }
+}
+
+// Round and store them with population 0 at offset o (population i at o + i CW).
+template <typename S, typename Real, bool NT>
+__device__ __forceinline__ void store_node(S* __restrict__ dst, long long o, const Real f[9], const Real g[5],
+                                           uint32_t key, uint32_t node)
+{
+    S v[14];
+    round_node<S, Real>(f, g, key, node, v);
 #pragma unroll
     for (int i = 0; i < 14; ++i) {
         if (NT) __builtin_nontemporal_store(v[i], dst + o + i * CW);

@@ -93,7 +93,8 @@ struct clb_lattice {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     size_t buf_bytes = 0;     // bytes per population buffer
-    void* buf[2] = {nullptr, nullptr};
+    void* buf[2] = {nullptr, nullptr};   // in-place lattices: buf[0] only
+    void* snap = nullptr;     // in-place lattices: two copies of snap_elems(nx, ny) values
     int cur = 0;              // buffer holding the post-collision state of the last step
     int shape = 2;            // tile shape of the step kernel (clb_step.h)
     clb::Params par;
