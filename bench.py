@@ -13,8 +13,9 @@ one), the roofline of the step kernel (112 algorithmic bytes per FP32 site updat
 read + 14 written; 224 in FP64), the same lattice in FP64 and in FP32 storage with FP64 collision
 and stochastic rounding ("fp32_sr") beside it, their field errors against FP64, an 8192 x 4096
 control lattice whose footprint (3.8 GB) is far beyond the 256 MB Infinity Cache, the 512-cavity
-batch, two serving runs (Poisson arrivals of small cavities, and a saturated queue of larger
-ones), and the FP64 CPU oracle timed on a bounded sample of the same workload.
+batch, in-place streaming (one population buffer) on the same lattices, two serving runs
+(Poisson arrivals of small cavities, and a saturated queue of larger ones), and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
 Progress goes to stderr.
 """
 import argparse
@@ -65,11 +66,13 @@ def measured_traffic(sites):
     return t.get("bytes_per_launch")
 
 
-def run_precision(clb, W, precision, steps, warmup, stream, workload, autotune=False, shape=None):
-    lat = clb.lattice_from_workload(workload, precision, stream=stream)
+def run_precision(clb, W, precision, steps, warmup, stream, workload, autotune=False, shape=None, in_place=False):
+    lat = clb.lattice_from_workload(workload, precision, stream=stream, in_place=in_place)
     if warmup:
         lat.step(warmup)
-    if shape is not None:
+    if in_place:
+        pass                     # one in-place step kernel, no tile shapes
+    elif shape is not None:
         lat.tile_shape = shape
     elif autotune:
         # times every compiled tile shape on scratch copies of the state, keeps the fastest; part
@@ -86,7 +89,8 @@ def run_precision(clb, W, precision, steps, warmup, stream, workload, autotune=F
     sites = workload["nx"] * workload["ny"]
     mlups = sites * steps / (ms * 1e-3) / 1e6
     gbps = BYTES_PER_SITE[precision] * sites / (ms * 1e-3 / steps) / 1e9
-    log(f"[bench] {workload['name']} {precision}: tile shape {shape} {clb.tile_shapes()[shape]}, "
+    kern = "in-place kernel" if in_place else f"tile shape {shape} {clb.tile_shapes()[shape]}"
+    log(f"[bench] {workload['name']} {precision}{' in-place' if in_place else ''}: {kern}, "
         f"{ms / steps * 1e3:.2f} us/step, {mlups:.0f} MLUPS, {gbps:.0f} GB/s algorithmic "
         f"(wall {wall:.3f} s for {steps} steps)")
     return lat, {"ms_total": ms, "ms_per_step": ms / steps, "wall_s": wall, "mlups": mlups, "gbps": gbps,
@@ -203,6 +207,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
     ap.add_argument("--no-copy", action="store_true", help="skip the plain-copy bandwidth reference")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-cavity batch")
+    ap.add_argument("--no-inplace", action="store_true", help="skip the in-place streaming runs")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--autotune", action="store_true",
@@ -303,6 +308,17 @@ def main():
                 "value": rc["mlups"], "unit": "MLUPS", "achieved_GBps": rc["gbps"], "tile_shape": rc["tile_shape"],
                 "frac": rc["gbps"] / HBM_PEAK_GBPS,
                 "footprint_GB": 2 * BYTES_PER_SITE[prec] / 2 * 8192 * 4096 / 1e9}
+    if not args.no_inplace:
+        # in-place streaming: one population buffer (half the footprint), same results bitwise
+        result["in_place"] = {}
+        for prec, wl, steps in (("fp32", w, args.steps), ("fp32_sr", w, args.steps), ("fp64", w, args.steps),
+                                ("fp32", W.rayleigh_benard(nx=8192, ny=4096), max(20, args.steps // 40))):
+            lati, ri = run_precision(clb, W, prec, steps, 10, stream.cuda_stream, wl, in_place=True)
+            lati.close()
+            torch.cuda.empty_cache()
+            result["in_place"][f"{prec}_{wl['nx']}x{wl['ny']}"] = {
+                "value": ri["mlups"], "unit": "MLUPS", "ms_per_step": ri["ms_per_step"], "achieved_GBps": ri["gbps"],
+                "frac": ri["gbps"] / HBM_PEAK_GBPS, "footprint_GB": BYTES_PER_SITE[prec] / 2 * wl["nx"] * wl["ny"] / 1e9}
     if not args.no_batch:
         result["batched_512_cavities"] = run_batch(clb, W, args.batch_steps, stream.cuda_stream, "fp32")
         torch.cuda.empty_cache()

@@ -224,7 +224,7 @@ struct BatchSlot {
     int cur = 0;
     long long steps = 0;
     bool has_snap = false;
-    int tw_log2 = 0;
+    int tw_log2 = 8;
 };
 
 constexpr size_t kAlign = 256;
@@ -239,9 +239,12 @@ size_t slot_bytes(const clb_desc& d, size_t* buf_bytes_out)
     return 2 * buf + snap;
 }
 
-// Tile mapping of a lattice whose size class has not been autotuned: wrapped rows (as fast as the
-// best row tiles on periodic lattices, faster where x has walls).
-int default_tw_log2(int) { return 0; }
+// Tile mapping of a lattice whose size class has not been autotuned: row tiles about as wide as the
+// lattice.  (Wrapped rows are the autotuner's choice where they pay: they halve the wavefronts that
+// take the x-wall branch, but where nx is not a multiple of the 64-node chunk their wavefronts
+// straddle chunks and write partial cache lines -- 64 cavities of sides 128-512 ran at 31 GLUPS
+// with wrapped rows and 42 with row tiles.)
+int default_tw_log2(int nx) { return nx <= 96 ? 6 : (nx <= 192 ? 7 : 8); }
 
 int size_class(const clb_desc& d)
 {
