@@ -52,10 +52,16 @@ def test_params_from_physics_matches_sec33_relations():
     dict(nx=10, ny=10, precision=7),
     dict(nx=10, ny=10, edges={"south": ("dirichlet", 0.6, 0, 0), "north": ("dirichlet", 0, 0, 0)}),
     dict(nx=10, ny=10, T0=float("nan")),
+    dict(nx=10, ny=10, prescribed=True, in_place=True),                  # in-place is flow lattices only
+    dict(nx=3, ny=10, in_place=True, edges={"west": ("dirichlet", 0, 0, 1), "east": ("dirichlet", 0, 0, 0)}),
+    dict(nx=10, ny=10, in_place=2),
 ])
 def test_create_rejects_bad_descriptions_on_host(bad):
     from paper_1710_10569_amd import clb
-    d = clb.make_desc(bad["nx"], bad["ny"], bad.get("precision", "fp64"), bad.get("edges"), bad.get("T0", 0.0))
+    d = clb.make_desc(bad["nx"], bad["ny"], bad.get("precision", "fp64"), bad.get("edges"), bad.get("T0", 0.0),
+                      bad.get("prescribed", False), bad.get("in_place", False))
+    if bad.get("in_place") == 2:
+        d.in_place = 2
     h = ctypes.c_void_p()
     rc = clb._lib.clb_create(ctypes.byref(d), None, ctypes.byref(h))
     assert rc == clb.CLB_EINVAL
@@ -72,12 +78,13 @@ def test_null_arguments():
 
 
 def test_batch_footprint_and_host_side_rejections():
-    """Pool bytes per lattice: two 14-plane population buffers with 256-byte rows plus an FP64
-    (u_x, u_y, T) snapshot; bad batch arguments are rejected before any device call."""
+    """Pool bytes per lattice: two population buffers (rows of 64-node chunks of 14 populations:
+    ceil(nx / 64) * 14 * 64 values per row) plus an FP64 (u_x, u_y, T) snapshot; bad batch arguments
+    are rejected before any device call."""
     from paper_1710_10569_amd import clb
     fp = clb.footprint(100, 60, "fp32")
-    pitch = 128                                  # 100 floats rounded up to 64-float rows
-    buf = -(-14 * pitch * 60 * 4 // 256) * 256
+    row = 2 * 14 * 64                            # 100 nodes: two 64-node chunks per row
+    buf = -(-row * 60 * 4 // 256) * 256
     snap = -(-3 * 100 * 60 * 8 // 256) * 256
     assert fp == 2 * buf + snap
     assert clb.footprint(100, 60, "fp64") > fp

@@ -1,0 +1,116 @@
+"""The serving loop's scheduling on the host, with a scripted stand-in for the batch (no GPU):
+admission by free slots and footprint, continuous admission as slots free up, and the stopping
+rules -- converged below the tolerance, stopped at the arithmetic's floor, capped, diverged, and
+rejected when a request could never fit the pool."""
+import math
+
+import pytest
+
+from paper_1710_10569_amd import serving as S
+
+
+class FakeBatch:
+    """Per request a scripted residual: r(steps) = a * exp(-steps / tau) + floor (nan: diverged)."""
+
+    def __init__(self, capacity, precision, budget_bytes=0, stream=None):
+        self.capacity, self.budget = capacity, budget_bytes
+        self.slots = {}
+        self.steps = {}
+        self.log = []
+
+    def info(self):
+        return {"budget_bytes": self.budget}
+
+    def add_workload(self, w):
+        if len(self.slots) >= self.capacity:
+            return None
+        s = min(set(range(self.capacity)) - set(self.slots))
+        self.slots[s] = w
+        self.steps[s] = 0
+        self.log.append(("add", w["req"]))
+        return s
+
+    def step(self, n, mode="grouped"):
+        for s in self.slots:
+            self.steps[s] += n
+
+    def check(self):
+        pass
+
+    def residuals(self):
+        out = {}
+        for s, w in self.slots.items():
+            a, tau, floor = w["script"]
+            r = a * math.exp(-self.steps[s] / tau) + floor
+            out[s] = (r, r, math.isnan(r))
+        return out
+
+    def diagnostics(self, s):
+        return {"wall_flux": [1.5, 0, 0, 0]}
+
+    def moments(self, s):
+        return None
+
+    def remove(self, s):
+        self.log.append(("remove", self.slots[s]["req"]))
+        del self.slots[s]
+
+    def close(self):
+        pass
+
+
+@pytest.fixture
+def server(monkeypatch):
+    scripts = {}
+
+    def workload(self, r):
+        return {"req": r.id, "script": scripts[r.id]}
+
+    monkeypatch.setattr(S.clb, "Batch", FakeBatch)
+    monkeypatch.setattr(S.clb, "footprint", lambda nx, ny, prec: nx * ny * 100)
+    monkeypatch.setattr(S.CavityServer, "_workload", workload)
+    return scripts
+
+
+def test_stopping_rules(server):
+    server.update({0: (1e-3, 500.0, 0.0),        # decays below tol: converged
+                   1: (1e-3, 1e9, 0.0),          # never decays: capped at the step cap
+                   2: (1e-4, 300.0, 3e-7),       # levels off at 3e-7: stopped at the floor
+                   3: (float("nan"), 1.0, 0.0)})  # non-finite: diverged
+    reqs = [S.Request(i, 0.0, 32, 1e4, i) for i in range(4)]
+    srv = S.CavityServer(budget_bytes=1 << 30, capacity=8, chunk=1000, tol=1e-8, step_cap=40000, floor_patience=5)
+    out = {r.id: r for r in srv.run(reqs)}
+    assert out[0].status == "converged" and out[0].steps < 40000
+    assert out[1].status == "capped" and out[1].steps == 40000
+    assert out[2].status == "floor"
+    assert out[3].status == "diverged" and out[3].steps == 1000
+    assert out[0].nu_wall == 1.5
+    s = S.summarize(list(out.values()), srv.wall, srv.site_updates)
+    assert s["status"] == {"converged": 1, "capped": 1, "floor": 1, "diverged": 1}
+
+
+def test_continuous_admission_by_slots(server):
+    """Three slots, six requests: the later ones are admitted as earlier ones finish, in arrival order."""
+    for i in range(6):
+        server[i] = (1e-3, 300.0 * (1 + i % 3), 0.0)
+    reqs = [S.Request(i, 0.0, 32, 1e4, i) for i in range(6)]
+    srv = S.CavityServer(budget_bytes=1 << 30, capacity=3, chunk=1000, tol=1e-8, step_cap=10 ** 6)
+    out = srv.run(reqs)
+    log = srv.batch.log
+    adds = [i for k, i in log if k == "add"]
+    assert adds == list(range(6))
+    # never more than three resident
+    live = 0
+    for k, _ in log:
+        live += 1 if k == "add" else -1
+        assert live <= 3
+    assert all(r.status == "converged" for r in out)
+    assert all(r.admitted >= r.arrival for r in out)
+
+
+def test_request_larger_than_the_pool_is_rejected(server):
+    server.update({0: (1e-3, 300.0, 0.0), 1: (1e-3, 300.0, 0.0)})
+    reqs = [S.Request(0, 0.0, 32, 1e4, 0), S.Request(1, 0.0, 4096, 1e4, 1)]
+    srv = S.CavityServer(budget_bytes=32 * 32 * 100 * 4, capacity=4, chunk=1000, tol=1e-8, step_cap=10 ** 5)
+    out = {r.id: r for r in srv.run(reqs)}
+    assert out[1].status == "rejected" and out[0].status == "converged"
