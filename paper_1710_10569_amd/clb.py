@@ -317,9 +317,9 @@ _sig("clb_batch_destroy", None, [_B])
 MODES = {"grouped": 0, "each": 1, "persistent": 2}
 
 
-def footprint(nx, ny, precision="fp32", edges=None, T0=0.0):
+def footprint(nx, ny, precision="fp32", edges=None, T0=0.0, in_place=False):
     """Pool bytes one lattice occupies in a batch (clb_batch_footprint)."""
-    d = make_desc(nx, ny, precision, edges, T0)
+    d = make_desc(nx, ny, precision, edges, T0, in_place=in_place)
     v = ctypes.c_size_t()
     _check(_lib.clb_batch_footprint(ctypes.byref(d), ctypes.byref(v)))
     return v.value
@@ -355,8 +355,8 @@ class Batch:
     def __del__(self):
         self.close()
 
-    def add(self, nx, ny, edges=None, T0=0.0, tau_nu=1.0, tau_alpha=1.0, g_beta=0.0, Ma=0.0):
-        d = make_desc(nx, ny, self.precision, edges, T0)
+    def add(self, nx, ny, edges=None, T0=0.0, tau_nu=1.0, tau_alpha=1.0, g_beta=0.0, Ma=0.0, in_place=False):
+        d = make_desc(nx, ny, self.precision, edges, T0, in_place=in_place)
         s = ctypes.c_int()
         _check(_lib.clb_batch_add(self._h, ctypes.byref(d), tau_nu, tau_alpha, g_beta, Ma, ctypes.byref(s)))
         self.shapes[s.value] = (int(nx), int(ny))
@@ -371,9 +371,9 @@ class Batch:
                 return None
             raise
 
-    def add_workload(self, w):
+    def add_workload(self, w, in_place=False):
         """Admit and initialise a workload description (see workloads.py); returns the slot or None
-        when it does not fit."""
+        when it does not fit.  in_place: one population buffer (half the pool bytes)."""
         if "taus" in w:
             t = w["taus"]
             tn, ta, gb, Ma = t["tau_nu"], t["tau_alpha"], t["g_beta"], 0.0
@@ -381,7 +381,7 @@ class Batch:
             p = w["physics"]
             tn, ta, gb = params_from_physics(p["Ra"], p["Pr"], p["Ma"], p["H"], p["dT"])
             Ma = p["Ma"]
-        slot = self.try_add(w["nx"], w["ny"], w["edges"], w["T0"], tn, ta, gb, Ma)
+        slot = self.try_add(w["nx"], w["ny"], w["edges"], w["T0"], tn, ta, gb, Ma, in_place=in_place)
         if slot is None:
             return None
         if "body_force" in w:

@@ -44,6 +44,8 @@ struct BatchLat {
     int tw_log2;        // tile width 1 << tw_log2 (6, 7 or 8), tile rows 256 >> tw_log2; 0: wrapped rows
     int tiles_x, ntiles;
     double inv_nx;      // 1 / nx (wrapped rows)
+    int aa;             // 1: in-place lattice (off[0] only, snapshot copies at sn[0], sn[1])
+    long long sn[2];    // element offsets of the in-place snapshot copies
 };
 
 template <typename Real>
@@ -79,11 +81,24 @@ __device__ __forceinline__ bool batch_node(const BatchLat& L, int tile, int lane
     return x < L.G.nx && y < L.G.ny;
 }
 
-template <typename S, typename Real, bool DEV, bool NT>
+// AA: the batch holds in-place lattices (a separate instantiation, so that batches without them keep
+// the register budget of the two-buffer update alone).
+template <typename S, typename Real, bool DEV, bool NT, bool AA>
 __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntry<Real>& E, int tile, int s)
 {
     int x, y;
     if (!batch_node(E.L, tile, int(threadIdx.x), x, y)) return;
+    if (AA && E.L.aa) {
+        // the lattice's own step count sets the in-place form and the snapshot copies
+        const uint32_t t = E.L.step + uint32_t(s);
+        const bool odd = (t & 1u) != 0;
+        S* A = pool + E.L.off[0];
+        const S* snow = pool + (odd ? E.L.sn[1] : E.L.sn[0]);
+        S* snext = pool + (odd ? E.L.sn[0] : E.L.sn[1]);
+        if (odd) node_update_aa<S, Real, DEV, true, NT>(A, snow, snext, E.L.G, E.P, x, y, step_key(t));
+        else node_update_aa<S, Real, DEV, false, NT>(A, snow, snext, E.L.G, E.P, x, y, step_key(t));
+        return;
+    }
     // select the buffers without indexing off[] by a runtime value (which would put the entry
     // in private memory)
     const bool c = (E.L.cur ^ (s & 1)) != 0;
@@ -92,7 +107,7 @@ __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntr
     node_update<S, Real, DEV, NT>(pool + o_src, pool + o_dst, E.L.G, E.P, x, y, step_key(E.L.step + uint32_t(s)));
 }
 
-template <typename S, typename Real, bool DEV, bool NT>
+template <typename S, typename Real, bool DEV, bool NT, bool AA>
 __global__ __launch_bounds__(BNT) void batch_step_kernel(S* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
                                                        const TileRef* __restrict__ tiles, int tile_base, int ntiles,
                                                        int s)
@@ -102,7 +117,7 @@ __global__ __launch_bounds__(BNT) void batch_step_kernel(S* __restrict__ pool, c
     if (t >= ntiles) return;
     const TileRef r = tiles[tile_base + t];
     const BatchEntry<Real> E = lats[r.lat];
-    batch_tile<S, Real, DEV, NT>(pool, E, r.tile, s);
+    batch_tile<S, Real, DEV, NT, AA>(pool, E, r.tile, s);
 }
 
 // After a call of nsteps steps: flip the current-buffer index of every listed slot if nsteps is
@@ -127,7 +142,7 @@ __global__ void batch_zero_kernel(unsigned* p, int n)
 constexpr int RNT = 1024;
 constexpr long long kResidentMaxNodes = 128 * 128;
 
-template <typename S, typename Real, bool DEV>
+template <typename S, typename Real, bool DEV, bool AA>
 __global__ __launch_bounds__(RNT) void batch_resident_kernel(S* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
                                                            const int* __restrict__ slots, int nslots, int nsteps)
 {
@@ -135,6 +150,20 @@ __global__ __launch_bounds__(RNT) void batch_resident_kernel(S* __restrict__ poo
     const BatchEntry<Real> E = lats[slots[blockIdx.x]];
     const int nx = E.L.G.nx, n = E.L.G.nx * E.L.G.ny;
     for (int s = 0; s < nsteps; ++s) {
+        if (AA && E.L.aa) {
+            const uint32_t t = E.L.step + uint32_t(s);
+            const bool odd = (t & 1u) != 0;
+            S* A = pool + E.L.off[0];
+            const S* snow = pool + (odd ? E.L.sn[1] : E.L.sn[0]);
+            S* snext = pool + (odd ? E.L.sn[0] : E.L.sn[1]);
+            for (int k = int(threadIdx.x); k < n; k += RNT) {
+                const int y = k / nx, x = k - y * nx;
+                if (odd) node_update_aa<S, Real, DEV, true, false>(A, snow, snext, E.L.G, E.P, x, y, step_key(t));
+                else node_update_aa<S, Real, DEV, false, false>(A, snow, snext, E.L.G, E.P, x, y, step_key(t));
+            }
+            __syncthreads();
+            continue;
+        }
         const bool c = (E.L.cur ^ (s & 1)) != 0;
         const S* src = pool + (c ? E.L.off[1] : E.L.off[0]);
         S* dst = pool + (c ? E.L.off[0] : E.L.off[1]);
@@ -154,7 +183,7 @@ __global__ __launch_bounds__(RNT) void batch_resident_kernel(S* __restrict__ poo
 // |T - T'| and a non-finite flag are combined with atomic max on their IEEE bit patterns (all
 // values are non-negative, so the integer order is the numeric order and the result does not
 // depend on the order of the updates).
-template <typename S, typename Real, bool DEV>
+template <typename S, typename Real, bool DEV, bool AA>
 __global__ __launch_bounds__(BNT) void batch_residual_kernel(S* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
                                                            const TileRef* __restrict__ tiles, int ntiles,
                                                            unsigned long long* __restrict__ res)
@@ -167,10 +196,19 @@ __global__ __launch_bounds__(BNT) void batch_residual_kernel(S* __restrict__ poo
     int x, y;
     double du = 0.0, dT = 0.0, bad = 0.0;
     if (batch_node(E.L, r.tile, int(threadIdx.x), x, y)) {
-        const S* src = pool + (E.L.cur ? E.L.off[1] : E.L.off[0]);
         Real f[9], g[5];
-        pull(src, E.L.G, x, y, f, g);
-        if (on_wall(E.L.G, x, y)) wall_step<S, Real, DEV>(src, E.L.G, E.P, x, y, f, g);
+        if (AA && E.L.aa) {
+            const bool odd = (E.L.step & 1u) != 0;
+            const S* A = pool + E.L.off[0];
+            if (odd) load_aa<S, Real, true>(A, E.L.G, x, y, f, g);
+            else load_aa<S, Real, false>(A, E.L.G, x, y, f, g);
+            if (on_wall(E.L.G, x, y))
+                wall_step_nb<Real, DEV>(SnapSource<S>{pool + (odd ? E.L.sn[1] : E.L.sn[0])}, E.L.G, E.P, x, y, f, g);
+        } else {
+            const S* src = pool + (E.L.cur ? E.L.off[1] : E.L.off[0]);
+            pull(src, E.L.G, x, y, f, g);
+            if (on_wall(E.L.G, x, y)) wall_step<S, Real, DEV>(src, E.L.G, E.P, x, y, f, g);
+        }
         const Macro<Real, DEV> m = macro<Real, DEV>(f, g, E.P);
         const double ux = double(m.ux), uy = double(m.uy), T = double(E.P.TR) + double(m.dT);
         double* snap = reinterpret_cast<double*>(reinterpret_cast<char*>(pool) + E.L.snap);
@@ -221,6 +259,7 @@ struct BatchSlot {
     size_t alloc_off = 0, alloc_bytes = 0;   // byte range in the pool
     long long off[2] = {0, 0};               // element offsets of the population buffers
     size_t snap_off = 0;                     // byte offset of the FP64 snapshot (3 n doubles)
+    long long sn[2] = {0, 0};                // in-place lattices: element offsets of the snapshot copies
     int cur = 0;
     long long steps = 0;
     bool has_snap = false;
@@ -230,13 +269,17 @@ struct BatchSlot {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-size_t slot_bytes(const clb_desc& d, size_t* buf_bytes_out)
+// Pool bytes of one lattice: two population buffers (in place: one, plus two snapshot copies of
+// the wall-adjacent bands) and the FP64 residual snapshot.
+size_t slot_bytes(const clb_desc& d, size_t* buf_bytes_out, size_t* band_bytes_out = nullptr)
 {
     const size_t eb = elem_bytes(d.precision);
     const size_t buf = align_up(size_t(buffer_elems(d.nx, d.ny)) * eb);
+    const size_t band = align_up(size_t(snap_elems(d.nx, d.ny)) * eb);
     const size_t snap = align_up(size_t(3) * d.nx * d.ny * sizeof(double));
     if (buf_bytes_out) *buf_bytes_out = buf;
-    return 2 * buf + snap;
+    if (band_bytes_out) *band_bytes_out = band;
+    return d.in_place ? buf + 2 * band + snap : 2 * buf + snap;
 }
 
 // Tile mapping of a lattice whose size class has not been autotuned: row tiles about as wide as the
@@ -293,6 +336,7 @@ struct clb_batch {
     std::map<int, int> tw_by_class;       // autotuned tile width (log2) per size class
     bool nontemporal = false;
     bool nt_chosen = false;               // store form set by the caller or the autotuner
+    bool has_aa = false;                  // some resident lattice streams in place
 };
 
 namespace {
@@ -341,6 +385,9 @@ BatchEntry<Real> make_entry(const BatchSlot& s, int tw_log2)
     E.L.off[0] = s.off[0];
     E.L.off[1] = s.off[1];
     E.L.snap = (long long)s.snap_off;
+    E.L.aa = s.desc.in_place ? 1 : 0;
+    E.L.sn[0] = s.sn[0];
+    E.L.sn[1] = s.sn[1];
     E.L.cur = s.cur;
     E.L.step = uint32_t(s.steps);
     E.L.tw_log2 = tw_log2;
@@ -367,11 +414,13 @@ int upload_tables(clb_batch* b)
     b->ntiles.assign(cap, 0);
     std::vector<int> active;
     size_t resident = 0;
+    b->has_aa = false;
     for (int i = 0; i < cap; ++i) {
         BatchSlot& s = b->slots[i];
         if (!s.used) continue;
         active.push_back(i);
         resident += s.alloc_bytes;
+        b->has_aa = b->has_aa || s.desc.in_place;
         int nt;
         if (b->precision == CLB_FP32_DEV) {
             BatchEntry<float> E = make_entry<float>(s, s.tw_log2);
@@ -438,12 +487,16 @@ template <typename S, typename Real, bool DEV>
 hipError_t grouped_launch(clb_batch* b, const TileRef* tiles, int tile_base, int ntiles, int s)
 {
     const int q = (ntiles + 7) / 8;
-    if (b->nontemporal)
-        batch_step_kernel<S, Real, DEV, true><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
-            (S*)b->pool, (const BatchEntry<Real>*)b->d_lats, tiles, tile_base, ntiles, s);
-    else
-        batch_step_kernel<S, Real, DEV, false><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
-            (S*)b->pool, (const BatchEntry<Real>*)b->d_lats, tiles, tile_base, ntiles, s);
+    const dim3 grid(8 * q), block(BNT);
+    S* pool = (S*)b->pool;
+    const BatchEntry<Real>* lats = (const BatchEntry<Real>*)b->d_lats;
+    if (b->has_aa) {
+        if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, true><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+        else batch_step_kernel<S, Real, DEV, false, true><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+    } else {
+        if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, false><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+        else batch_step_kernel<S, Real, DEV, false, false><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+    }
     return hipGetLastError();
 }
 
@@ -463,8 +516,12 @@ template <typename S, typename Real, bool DEV>
 hipError_t resident_launch(clb_batch* b, int nsteps, hipStream_t st)
 {
     const int ns = int(b->small_slots.size());
-    batch_resident_kernel<S, Real, DEV><<<dim3(ns), dim3(RNT), 0, st>>>((S*)b->pool, (const BatchEntry<Real>*)b->d_lats,
-                                                                     b->d_small, ns, nsteps);
+    if (b->has_aa)
+        batch_resident_kernel<S, Real, DEV, true><<<dim3(ns), dim3(RNT), 0, st>>>(
+            (S*)b->pool, (const BatchEntry<Real>*)b->d_lats, b->d_small, ns, nsteps);
+    else
+        batch_resident_kernel<S, Real, DEV, false><<<dim3(ns), dim3(RNT), 0, st>>>(
+            (S*)b->pool, (const BatchEntry<Real>*)b->d_lats, b->d_small, ns, nsteps);
     return hipGetLastError();
 }
 
@@ -684,7 +741,6 @@ extern "C" int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, 
     if (rc) return rc;
     if (desc->precision != b->precision) { set_error("lattice precision differs from the batch's"); return CLB_EINVAL; }
     if (desc->prescribed_u) { set_error("temperature-only lattices (prescribed_u) are single-lattice only"); return CLB_EINVAL; }
-    if (desc->in_place) { set_error("in-place lattices are single-lattice only"); return CLB_EINVAL; }
     rc = check_params(tau_nu, tau_alpha, g_beta, Ma);
     if (rc) return rc;
     int free_slot = -1;
@@ -692,8 +748,8 @@ extern "C" int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, 
         if (!b->slots[i].used) { free_slot = i; break; }
     if (free_slot < 0) { set_error("batch is full (%d slots)", b->capacity); return CLB_ENOMEM; }
     BatchSlot s;
-    size_t buf_bytes = 0;
-    const size_t bytes = slot_bytes(*desc, &buf_bytes);
+    size_t buf_bytes = 0, band_bytes = 0;
+    const size_t bytes = slot_bytes(*desc, &buf_bytes, &band_bytes);
     size_t off = 0;
     if (alloc_range(b, bytes, &off) != CLB_OK) {
         set_error("lattice needs %zu bytes; %zu of %zu bytes in use", bytes, b->used_bytes, b->budget);
@@ -712,8 +768,15 @@ extern "C" int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, 
     s.alloc_off = off;
     s.alloc_bytes = bytes;
     s.off[0] = (long long)(off / eb);
-    s.off[1] = (long long)((off + buf_bytes) / eb);
-    s.snap_off = off + 2 * buf_bytes;
+    if (desc->in_place) {
+        s.off[1] = s.off[0];
+        s.sn[0] = (long long)((off + buf_bytes) / eb);
+        s.sn[1] = (long long)((off + buf_bytes + band_bytes) / eb);
+        s.snap_off = off + buf_bytes + 2 * band_bytes;
+    } else {
+        s.off[1] = (long long)((off + buf_bytes) / eb);
+        s.snap_off = off + 2 * buf_bytes;
+    }
     auto it = b->tw_by_class.find(size_class(*desc));
     s.tw_log2 = it != b->tw_by_class.end() ? it->second : default_tw_log2(desc->nx);
     b->slots[free_slot] = s;
@@ -757,6 +820,20 @@ extern "C" int clb_batch_set_body_force(clb_batch* b, int slot, double Fvx, doub
     return CLB_OK;
 }
 
+// Moments (rho, u_x, u_y, T) of a slot's current step into b->d_fields.
+static hipError_t slot_moments(clb_batch* b, const BatchSlot& s)
+{
+    const clb_desc& d = s.desc;
+    const size_t eb = elem_bytes(d.precision);
+    const Geo G = make_geo(d);
+    if (d.in_place) {
+        const bool odd = (s.steps & 1) != 0;
+        return enqueue_moments_aa(d, s.par, odd, b->pool + s.off[0] * eb, b->pool + (odd ? s.sn[1] : s.sn[0]) * eb, G,
+                                  b->d_fields, b->stream);
+    }
+    return enqueue_moments(d, s.par, b->pool + s.off[s.cur] * eb, G, b->d_fields, b->stream);
+}
+
 extern "C" int clb_batch_init(clb_batch* b, int slot, const double* rho, const double* u, const double* T)
 {
     clear_error();
@@ -780,13 +857,19 @@ extern "C" int clb_batch_init(clb_batch* b, int slot, const double* rho, const d
     rc = ensure_fields(b, 4 * n);
     if (rc) return rc;
     const size_t eb = elem_bytes(d.precision);
-    const size_t buf_bytes = size_t(s.off[1] - s.off[0]) * eb;
-    CLB_HIP(hipMemsetAsync(b->pool + s.off[0] * eb, 0, 2 * buf_bytes, b->stream));
+    // both population buffers, or the in-place buffer and its snapshot copies: everything below the
+    // residual snapshot
+    CLB_HIP(hipMemsetAsync(b->pool + s.off[0] * eb, 0, s.snap_off - size_t(s.off[0]) * eb, b->stream));
     CLB_HIP(hipMemcpyAsync(b->d_fields, host.data(), 4 * n * sizeof(double), hipMemcpyHostToDevice, b->stream));
     const Geo G = make_geo(d);
-    CLB_HIP(enqueue_init(d, s.par, b->pool + s.off[0] * eb, G, b->d_fields, b->stream));
+    s.cur = 0;
+    s.steps = 0;
+    if (d.in_place)
+        CLB_HIP(enqueue_init_aa(d, s.par, b->pool + s.off[0] * eb, b->pool + s.sn[0] * eb, G, b->d_fields, b->stream));
+    else
+        CLB_HIP(enqueue_init(d, s.par, b->pool + s.off[0] * eb, G, b->d_fields, b->stream));
     // the snapshot starts as the initial (u_x, u_y, T), so the first residual measures the first chunk
-    CLB_HIP(enqueue_moments(d, s.par, b->pool + s.off[0] * eb, G, b->d_fields, b->stream));
+    CLB_HIP(slot_moments(b, s));
     CLB_HIP(hipMemcpyAsync(b->pool + s.snap_off, b->d_fields + n, 3 * n * sizeof(double), hipMemcpyDeviceToDevice,
                            b->stream));
     CLB_HIP(hipStreamSynchronize(b->stream));
@@ -895,9 +978,7 @@ extern "C" int clb_batch_moments(clb_batch* b, int slot, double* rho, double* u,
     const size_t n = size_t(d.nx) * d.ny;
     rc = ensure_fields(b, 4 * n);
     if (rc) return rc;
-    const size_t eb = elem_bytes(d.precision);
-    const Geo G = make_geo(d);
-    CLB_HIP(enqueue_moments(d, s.par, b->pool + s.off[s.cur] * eb, G, b->d_fields, b->stream));
+    CLB_HIP(slot_moments(b, s));
     if (rho) CLB_HIP(hipMemcpyAsync(rho, b->d_fields, n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     if (u) CLB_HIP(hipMemcpyAsync(u, b->d_fields + n, 2 * n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     if (T) CLB_HIP(hipMemcpyAsync(T, b->d_fields + 3 * n, n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
@@ -925,9 +1006,8 @@ extern "C" int clb_batch_diagnostics(clb_batch* b, int slot, int snapshot, clb_d
         CLB_HIP(hipMalloc((void**)&b->d_partials, size_t(nb) * DIAG_SLOTS * sizeof(double)));
         b->partials_cap = nb;
     }
-    const size_t eb = elem_bytes(d.precision);
     double* snap = (double*)(b->pool + s.snap_off);
-    CLB_HIP(enqueue_moments(d, s.par, b->pool + s.off[s.cur] * eb, G, b->d_fields, b->stream));
+    CLB_HIP(slot_moments(b, s));
     CLB_HIP(enqueue_diag(b->d_fields, snap, s.has_snap ? 1 : 0, G, b->d_partials, b->d_diag, b->stream));
     double r[DIAG_SLOTS];
     CLB_HIP(hipMemcpyAsync(r, b->d_diag, sizeof r, hipMemcpyDeviceToHost, b->stream));
@@ -956,10 +1036,12 @@ extern "C" int clb_batch_set_tile_width(clb_batch* b, int slot, int tile_width)
 
 // For every size class present, time the grouped step over that class's lattices with each tile
 // width (state unchanged: reads the current buffers, writes the spare ones) and keep the fastest.
-extern "C" int clb_batch_autotune(clb_batch* b, int launches)
+// Tile mappings and store form are timed on the two-buffer lattices only: their timing launches
+// read the current state and write the spare buffer, so the state is untouched.  An in-place
+// lattice would be advanced by them; in-place lattices keep their mappings (and take the store
+// form chosen for the rest).
+static int autotune_two_buffer(clb_batch* b, int launches)
 {
-    clear_error();
-    if (!b || launches <= 0) { set_error("bad arguments"); return CLB_EINVAL; }
     std::map<int, std::vector<int>> classes;
     for (int i = 0; i < b->capacity; ++i)
         if (b->slots[i].used) classes[size_class(b->slots[i].desc)].push_back(i);
@@ -1000,7 +1082,7 @@ extern "C" int clb_batch_autotune(clb_batch* b, int launches)
     b->dirty = true;
     int rc = upload_tables(b);
     if (rc) return rc;
-    // store form over the whole batch (reads the current state, writes the spare buffers)
+    // store form over the whole batch
     const int nt = int(b->tiles.size());
     if (nt == 0) return CLB_OK;
     double t_store[2] = {0.0, 0.0};
@@ -1020,6 +1102,24 @@ extern "C" int clb_batch_autotune(clb_batch* b, int launches)
     return CLB_OK;
 }
 
+extern "C" int clb_batch_autotune(clb_batch* b, int launches)
+{
+    clear_error();
+    if (!b || launches <= 0) { set_error("bad arguments"); return CLB_EINVAL; }
+    // hide the in-place lattices for the duration
+    std::vector<int> hidden;
+    for (int i = 0; i < b->capacity; ++i)
+        if (b->slots[i].used && b->slots[i].desc.in_place) {
+            b->slots[i].used = false;
+            hidden.push_back(i);
+        }
+    const int rc = autotune_two_buffer(b, launches);
+    for (int i : hidden) b->slots[i].used = true;
+    b->dirty = true;
+    if (rc) return rc;
+    return upload_tables(b);
+}
+
 extern "C" int clb_batch_set_nontemporal(clb_batch* b, int nontemporal)
 {
     clear_error();
@@ -1034,8 +1134,12 @@ static hipError_t residual_launch(clb_batch* b)
 {
     const int nt = int(b->tiles.size());
     const int q = (nt + 7) / 8;
-    batch_residual_kernel<S, Real, DEV><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
-        (S*)b->pool, (const BatchEntry<Real>*)b->d_lats, b->d_tiles, nt, b->d_res);
+    if (b->has_aa)
+        batch_residual_kernel<S, Real, DEV, true><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
+            (S*)b->pool, (const BatchEntry<Real>*)b->d_lats, b->d_tiles, nt, b->d_res);
+    else
+        batch_residual_kernel<S, Real, DEV, false><<<dim3(8 * q), dim3(BNT), 0, b->stream>>>(
+            (S*)b->pool, (const BatchEntry<Real>*)b->d_lats, b->d_tiles, nt, b->d_res);
     return hipGetLastError();
 }
 

@@ -52,16 +52,18 @@ class CavityServer:
     budget_bytes: HBM pool for resident lattices; capacity: slots; precision: storage/arithmetic
     mode (default FP32 storage, FP64 collision, stochastic rounding on store, whose steady states stay
     within ~1e-7 of the FP64 ones; plain FP32 drifts to ~1e-5); chunk: steps between residual
-    checks; tol: max-norm change of u and of T per chunk that counts as steady; step_cap: give up
+    checks; in_place: lattices stream in place (one population buffer: about half the pool bytes per
+    request, so twice as many resident); tol: max-norm change of u and of T per chunk that counts as steady; step_cap: give up
     after this many steps; schedule: 'grouped' or 'persistent'; keep_fields: return (rho, ux, uy, T)."""
 
     def __init__(self, budget_bytes=16 << 30, capacity=1024, precision="fp32_sr", chunk=1000, tol=1e-8,
                  step_cap=5_000_000, schedule="persistent", Pr=0.71, Ma=0.1, keep_fields=False,
-                 floor_patience=20, stream=None):
+                 floor_patience=20, stream=None, in_place=False):
         self.batch = clb.Batch(capacity, precision, budget_bytes=budget_bytes, stream=stream)
         self.precision, self.chunk, self.tol, self.step_cap = precision, int(chunk), float(tol), int(step_cap)
         self.schedule, self.Pr, self.Ma, self.keep_fields = schedule, Pr, Ma, keep_fields
         self.floor_patience = int(floor_patience)
+        self.in_place = bool(in_place)
         self.site_updates = 0
 
     def close(self):
@@ -85,12 +87,12 @@ class CavityServer:
                 waiting.append(pending.popleft())
             while waiting:
                 r = waiting[0]
-                fp = footprint_cache.setdefault(r.L, clb.footprint(r.L, r.L, self.precision))
+                fp = footprint_cache.setdefault(r.L, clb.footprint(r.L, r.L, self.precision, in_place=self.in_place))
                 if fp > budget:
                     r.status, r.finished = "rejected", clock() - t0
                     waiting.popleft()
                     continue
-                slot = self.batch.add_workload(self._workload(r))
+                slot = self.batch.add_workload(self._workload(r), in_place=self.in_place)
                 if slot is None:
                     break           # wait until memory or a slot frees up
                 waiting.popleft()

@@ -298,3 +298,32 @@ def test_full_batch_sampled_against_oracle(gpu, precision):
         print(f"[batch] full batch {precision} cavity {i} L={L} Ra={Ra:.3g}: {e}", flush=True)
         assert e["u"] < 1e-5 and e["T"] < 1e-5, (i, e)
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_sr"])
+@pytest.mark.parametrize("mode", ["grouped", "each", "persistent"])
+def test_in_place_lattices_in_a_batch(gpu, precision, mode):
+    """In-place and two-buffer lattices in one batch, admitted at different times (so their step
+    counts, and with them the in-place form, differ): each matches the same lattice alone with
+    two-buffer streaming bitwise, in every schedule; the in-place ones take about half the pool."""
+    clb = _clb()
+    ws = mixed_workloads()
+    b = clb.Batch(16, precision, budget_bytes=256 << 20)
+    first = [b.add_workload(w, in_place=(i % 2 == 0)) for i, w in enumerate(ws[:3])]
+    b.step(13, mode)
+    later = [b.add_workload(w, in_place=(i % 2 == 1)) for i, w in enumerate(ws[3:])]
+    b.step(20, mode)
+    b.step(24, mode)
+    if mode == "persistent":
+        b.check()
+    res = b.residuals()
+    for w, s in zip(ws[:3], first):
+        for a, r in zip(b.moments(s), alone(w, precision, 57)):
+            assert np.array_equal(a, r), (w["name"], mode)
+    for w, s in zip(ws[3:], later):
+        for a, r in zip(b.moments(s), alone(w, precision, 44)):
+            assert np.array_equal(a, r), (w["name"], mode)
+    assert not any(v[2] for v in res.values())
+    b.close()
+    two, one = clb.footprint(300, 200, precision), clb.footprint(300, 200, precision, in_place=True)
+    assert one < 0.62 * two

@@ -97,7 +97,7 @@ def test_in_place_errors(gpu):
         lat.autotune(2)
     lat.close()
     b = clb.Batch(2, "fp64", budget_bytes=16 << 20)
-    d = clb.make_desc(8, 8, "fp64", in_place=True)
+    d = clb.make_desc(3, 8, "fp64", edges, in_place=True)      # too narrow for in-place walls
     slot = ctypes.c_int(-1)
     rc = clb._lib.clb_batch_add(b._h, ctypes.byref(d), 0.8, 0.8, 0.0, 0.0, ctypes.byref(slot))
     assert rc == clb.CLB_EINVAL

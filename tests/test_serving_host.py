@@ -21,7 +21,7 @@ class FakeBatch:
     def info(self):
         return {"budget_bytes": self.budget}
 
-    def add_workload(self, w):
+    def add_workload(self, w, in_place=False):
         if len(self.slots) >= self.capacity:
             return None
         s = min(set(range(self.capacity)) - set(self.slots))
@@ -67,7 +67,7 @@ def server(monkeypatch):
         return {"req": r.id, "script": scripts[r.id]}
 
     monkeypatch.setattr(S.clb, "Batch", FakeBatch)
-    monkeypatch.setattr(S.clb, "footprint", lambda nx, ny, prec: nx * ny * 100)
+    monkeypatch.setattr(S.clb, "footprint", lambda nx, ny, prec, in_place=False: nx * ny * 100)
     monkeypatch.setattr(S.CavityServer, "_workload", workload)
     return scripts
 
