@@ -175,11 +175,28 @@ __device__ __forceinline__ void store_aa(S* __restrict__ A, S* __restrict__ snex
     // only nodes within one step of a band can stream into it
     const bool near = (!G.perx && (x <= 3 || x >= G.nx - 4)) || (!G.pery && (y <= 3 || y >= G.ny - 4));
     if (!near) return;
+    // per neighbour offset d = -1, 0, +1: the snapshot base of the column band holding column x + d
+    // (or -1) and the position of row y + d along it (or -1 outside a wall), and likewise for rows
+    const long long len = G.nx > G.ny ? G.nx : G.ny;
+    long long cbase[3], rbase[3];
+    int ypos[3], xpos[3];
+#pragma unroll
+    for (int d = -1; d <= 1; ++d) {
+        const int tx = x + d, ty = y + d;
+        cbase[d + 1] = G.perx ? -1 : (tx == 1 || tx == 2) ? (0 * 2 + tx - 1) * len * 14
+                                  : (tx == G.nx - 2 || tx == G.nx - 3) ? (1 * 2 + G.nx - 2 - tx) * len * 14 : -1;
+        rbase[d + 1] = G.pery ? -1 : (ty == 1 || ty == 2) ? (2 * 2 + ty - 1) * len * 14
+                                  : (ty == G.ny - 2 || ty == G.ny - 3) ? (3 * 2 + G.ny - 2 - ty) * len * 14 : -1;
+        ypos[d + 1] = ty >= 0 && ty < G.ny ? ty * 14 : (G.pery ? (ty < 0 ? G.ny - 1 : 0) * 14 : -1);
+        xpos[d + 1] = tx >= 0 && tx < G.nx ? tx * 14 : (G.perx ? (tx < 0 ? G.nx - 1 : 0) * 14 : -1);
+    }
 #pragma unroll
     for (int q = 0; q < 14; ++q) {
         const int i = q < 9 ? q : q - 9;
-        int tx, ty;
-        if (step_to(G, x, y, ex_of(i), ey_of(i), tx, ty)) snap_put(snext, G, tx, ty, q, v[q]);
+        const int dx = ex_of(i) + 1, dy = ey_of(i) + 1;
+        // a node can lie in a column band and a row band: both copies are written
+        if (cbase[dx] >= 0 && ypos[dy] >= 0) snext[cbase[dx] + ypos[dy] + q] = v[q];
+        if (rbase[dy] >= 0 && xpos[dx] >= 0) snext[rbase[dy] + xpos[dx] + q] = v[q];
     }
 }
 
