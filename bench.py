@@ -141,7 +141,7 @@ def cpu_baseline(W, budget_s=15.0):
             "sample": f"{n} steps of the 2048x1024 Rayleigh-Benard lattice ({sites * n:.3g} site updates), FP64"}
 
 
-def run_batch(clb, W, steps, stream, precision="fp32", modes=("grouped", "each")):
+def run_batch(clb, W, steps, stream, precision="fp32", modes=("grouped", "each"), in_place=False):
     """The 512 batched cavities (sides from {64, 96, ..., 512}, Ra log-uniform in [1e3, 1e6], seed 7)
     in one pool: autotuned tile widths and store form, then the grouped schedule (one launch per step
     over all cavities) and the one-launch-per-cavity schedule, timed with HIP events on the batch's
@@ -149,18 +149,19 @@ def run_batch(clb, W, steps, stream, precision="fp32", modes=("grouped", "each")
     import torch
     specs = W.batch_cavity_specs()
     total = sum(L * L for L, _, _ in specs)
-    budget = sum(clb.footprint(L, L, precision) for L, _, _ in specs) + (64 << 20)
+    budget = sum(clb.footprint(L, L, precision, in_place=in_place) for L, _, _ in specs) + (64 << 20)
     b = clb.Batch(len(specs), precision, budget_bytes=budget, stream=stream)
     t0 = time.perf_counter()
     for L, Ra, seed in specs:
-        if b.add_workload(W.cavity(L, Ra=Ra, seed=seed)) is None:
+        if b.add_workload(W.cavity(L, Ra=Ra, seed=seed), in_place=in_place) is None:
             raise RuntimeError("batch pool too small")
     log(f"[bench] batch {precision}: {len(specs)} cavities, {total:.4g} nodes, pool {budget / 1e9:.2f} GB, "
         f"set up in {time.perf_counter() - t0:.1f} s")
     b.step(20)
     b.autotune(3)
     torch.cuda.synchronize()
-    out = {"precision": precision, "cavities": len(specs), "sites": total, "steps": steps, "pool_GB": budget / 1e9}
+    out = {"precision": precision, "in_place": in_place, "cavities": len(specs), "sites": total, "steps": steps,
+           "pool_GB": budget / 1e9}
     for mode in modes:
         n = steps if mode != "each" else max(10, steps // 10)
         b.step(2, mode)
@@ -325,6 +326,10 @@ def main():
         result["batched_512_cavities_fp32_sr"] = run_batch(clb, W, args.batch_steps, stream.cuda_stream,
                                                            "fp32_sr", modes=("grouped",))
         torch.cuda.empty_cache()
+        if not args.no_inplace:
+            result["batched_512_cavities_in_place"] = run_batch(clb, W, args.batch_steps, stream.cuda_stream,
+                                                                "fp32", modes=("grouped",), in_place=True)
+            torch.cuda.empty_cache()
     if not args.no_serve:
         result["served"] = run_serving(clb, W, stream.cuda_stream)
         torch.cuda.empty_cache()
