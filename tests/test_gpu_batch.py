@@ -218,22 +218,37 @@ def test_served_result_same_alone_and_in_mix(gpu):
     assert all(r.status in ("converged", "floor", "capped") for r in out)
 
 
-def test_persistent_with_small_and_large_lattices(gpu):
-    """The persistent schedule splits a mix: lattices up to 128 x 128 nodes run workgroup-resident on
-    a second stream while larger ones take grouped launches; both kinds match their runs alone."""
+@pytest.mark.parametrize("precision", ["fp32", "fp32_sr"])
+def test_persistent_with_small_and_large_lattices(gpu, precision):
+    """The persistent schedule splits a mix: with at least 256 lattices of at most 64 x 64 nodes
+    resident, those run workgroup-resident on a second stream while larger ones take grouped
+    launches; sampled lattices of both kinds (and in-place ones) match their runs alone bitwise."""
     clb = _clb()
-    ws = [W.cavity(64, Ra=1e4, seed=1), W.random_walled(200, 100, seed=2, wall_u=0.01),
-          W.rayleigh_benard(320, 65, Ra=1e4, seed=3), W.random_periodic(128, 128, seed=4),
-          W.cavity(130, Ra=1e5, seed=5)]
-    b = clb.Batch(8, "fp32", budget_bytes=128 << 20)
-    slots = [b.add_workload(w) for w in ws]
+    rng = np.random.default_rng(17)
+    small = []
+    for i in range(256):
+        nx, ny = int(rng.integers(16, 65)), int(rng.integers(16, 65))
+        kind = i % 3
+        if kind == 0:
+            small.append(W.cavity(min(nx, ny), Ra=1e4, seed=i))
+        elif kind == 1:
+            small.append(W.random_walled(nx, ny, seed=i, wall_u=0.01, g_beta=1e-3))
+        else:
+            small.append(W.random_periodic(nx, ny, seed=i))
+    big = [W.random_walled(200, 100, seed=2, wall_u=0.01), W.rayleigh_benard(320, 65, Ra=1e4, seed=3),
+           W.cavity(130, Ra=1e5, seed=5)]
+    b = clb.Batch(300, precision, budget_bytes=512 << 20)
+    ss = [b.add_workload(w, in_place=(i % 5 == 4)) for i, w in enumerate(small)]
+    bs = [b.add_workload(w) for w in big]
     b.step(101, "persistent")
     b.step(40, "grouped")
     b.step(7, "persistent")
     b.check()
-    for w, s in zip(ws, slots):
-        for a, r in zip(b.moments(s), alone(w, "fp32", 148)):
+    picked = [(small[i], ss[i]) for i in (0, 1, 2, 4, 9, 100, 201, 255)] + list(zip(big, bs))
+    for w, s in picked:
+        for a, r in zip(b.moments(s), alone(w, precision, 148)):
             assert np.array_equal(a, r), w["name"]
+    b.close()
 
 
 def _serve_against_oracle(precision, cases, step_cap):
