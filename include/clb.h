@@ -80,8 +80,9 @@ typedef struct {
                           coupled flow and temperature problem */
     int in_place;      /* 1: in-place streaming (one population buffer, half the footprint; same
                           results bitwise as 0, the two-buffer pull streaming of Eqs. 12 and 22).
-                          Not with prescribed_u; at least 4 nodes across a walled direction;
-                          single lattices only (clb_batch_add rejects it) */
+                          Not with prescribed_u; at least 4 nodes across a walled direction.  An
+                          in-place lattice runs one step kernel (256 x 1 tiles): of its tile shape
+                          only the non-temporal-store flag applies, and it is not autotuned */
 } clb_desc;
 
 typedef struct clb_lattice clb_lattice;

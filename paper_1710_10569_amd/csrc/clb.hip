@@ -112,7 +112,7 @@ static hipError_t launch_one_step(clb_lattice* h, int shape, const void* src, vo
     if (d.in_place) {
         // src is the buffer, dst the snapshot pair; the parity of the step picks the form and the copies
         const bool odd = (step & 1) != 0;
-        const bool nt = h->buf_bytes > (size_t(256) << 20);
+        const bool nt = tile_shape(shape).nt != 0;   // the one in-place kernel takes only the store form
         const size_t sb = size_t(snap_elems(d.nx, d.ny)) * elem_bytes(d.precision);
         void* A = const_cast<void*>(src);
         const void* snow = (const char*)dst + (odd ? sb : 0);
@@ -177,7 +177,7 @@ int default_shape(const clb_desc& d)
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(tune_key(d));
     if (it != g_tune_cache.end()) return it->second;
-    const double footprint = 2.0 * double(buffer_elems(d.nx, d.ny)) * double(elem_bytes(d.precision));
+    const double footprint = (d.in_place ? 1.0 : 2.0) * double(buffer_elems(d.nx, d.ny)) * double(elem_bytes(d.precision));
     if (footprint > double(256 << 20)) return 6;
     return d.precision == CLB_FP32_DEV ? 8 : d.precision == CLB_FP32_SR ? 4 : 6;
 }
