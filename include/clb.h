@@ -278,10 +278,11 @@ int clb_batch_step(clb_batch* b, long long n);
 /* The same n steps with one launch per lattice per step (the one-lattice-at-a-time schedule). */
 int clb_batch_step_each(clb_batch* b, long long n);
 
-/* The same n steps with small lattices (at most 128*128 nodes) workgroup-resident: one launch runs
- * all n steps, each such lattice owned by one 1024-thread workgroup with a workgroup barrier
- * between steps; larger lattices take the grouped launches concurrently on the batch's stream.
- * Suited to many small lattices, where per-step launches would dominate. */
+/* The same n steps with small lattices workgroup-resident when there are many of them (at least 256
+ * lattices of at most 64*64 nodes): one launch runs all n steps, each such lattice owned by one
+ * 1024-thread workgroup with a workgroup barrier between steps, on a second stream; larger
+ * lattices (and all of them when the small ones are fewer) take the grouped launches concurrently
+ * on the batch's stream.  Suited to many tiny lattices, whose grouped steps are latency-bound. */
 int clb_batch_step_persistent(clb_batch* b, long long n);
 
 /* Synchronise the batch's stream and report any pending launch error (CLB_EDEVICE). */

@@ -594,7 +594,7 @@ __device__ __forceinline__ void node_update2(const S* __restrict__ src, S* __res
 }
 
 // Temperature-only node update (prescribed velocity u_p, Sec. 3.1): only the D2Q5 equation runs,
-// with u = u_p at every node; only the five g planes are read and written.
+// with u = u_p at every node; only the five g populations of a node are read and written.
 template <typename S, typename Real, bool DEV, bool NT>
 __device__ __forceinline__ void node_update_T(const S* __restrict__ src, S* __restrict__ dst, const Geo& G,
                                               const Par<Real>& P, int x, int y, uint32_t key)
