@@ -175,7 +175,7 @@ def run_batch(clb, W, steps, stream, precision="fp32", modes=("grouped", "each")
     return out
 
 
-def run_serving(clb, W, stream, n=32, lam=8.0, L_range=(32, 128), tol=1e-8, step_cap=200_000, patience=10):
+def run_serving(clb, W, stream, n=32, lam=8.0, L_range=(32, 128), tol=1e-8, step_cap=200_000, patience=20):
     """A Poisson stream of cavity requests (lam per second; lam = inf: all queued at time 0) served
     with continuous batching (serving.py), FP32 storage with FP64 collision and stochastic rounding."""
     from paper_1710_10569_amd import serving as S
@@ -185,14 +185,14 @@ def run_serving(clb, W, stream, n=32, lam=8.0, L_range=(32, 128), tol=1e-8, step
             sp["arrival"] = 0.0
     reqs = S.requests_from(specs)
     srv = S.CavityServer(budget_bytes=8 << 30, capacity=256, chunk=1000, tol=tol, step_cap=step_cap,
-                         schedule="grouped", floor_patience=patience, stream=stream)
+                         schedule="grouped", plateau_patience=patience, stream=stream)
     out = srv.run(reqs)
     summ = S.summarize(out, srv.wall, srv.site_updates)
     srv.close()
     summ.update({"lambda_per_s": lam if math.isfinite(lam) else "all at t=0", "L_range": list(L_range),
                  "Ra_range": [1e3, 1e6], "tol": tol, "step_cap": step_cap, "chunk": 1000,
                  "precision": srv.precision,
-                 "floor_rule": f"residual not halved in {patience} chunks and below 1e-6"})
+                 "plateau_rule": f"change below {srv.plateau_max:g} and not below 0.9 x its best for {patience} chunks"})
     summ["frac_of_hbm_peak"] = summ["aggregate_MLUPS"] * 1e6 * BYTES_PER_SITE[srv.precision] / 1e9 / HBM_PEAK_GBPS
     log(f"[bench] serving: {summ}")
     return summ

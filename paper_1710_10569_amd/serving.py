@@ -5,8 +5,8 @@ request is admitted as soon as a batch slot and enough pool memory are free (adm
 footprint, first come first served); admitted lattices stay resident and are advanced together by
 the batched kernel in chunks of `chunk` steps; after every chunk each resident lattice's FP64
 max-norm change of u and T over that chunk is measured on the device, and a lattice whose change
-is below `tol` (or that hits the step cap, or goes non-finite) is read out and its slot and memory
-are released for the next request.  A request therefore overlaps on the device with whatever else
+is below `tol` (or whose change has stopped falling, or that hits the step cap, or goes non-finite)
+is read out and its slot and memory are released for the next request.  A request therefore overlaps on the device with whatever else
 is resident, and its result does not depend on the mix: every lattice takes the same per-node
 update and the same chunk-aligned stopping test alone or with others.
 
@@ -35,9 +35,10 @@ class Request:
     admitted: float = math.nan
     finished: float = math.nan
     steps: int = 0
-    status: str = "pending"   # converged | floor | capped | diverged | rejected
+    status: str = "pending"   # converged | plateau | capped | diverged | rejected
     du: float = math.nan
     dT: float = math.nan
+    best: float = math.inf    # smallest max(du, dT) seen: the plateau level of a "plateau" request
     nu_wall: float = math.nan
     fields: tuple = field(default=None, repr=False)
 
@@ -53,16 +54,24 @@ class CavityServer:
     mode (default FP32 storage, FP64 collision, stochastic rounding on store, whose steady states stay
     within ~1e-7 of the FP64 ones; plain FP32 drifts to ~1e-5); chunk: steps between residual
     checks; in_place: lattices stream in place (one population buffer: about half the pool bytes per
-    request, so twice as many resident); tol: max-norm change of u and of T per chunk that counts as steady; step_cap: give up
-    after this many steps; schedule: 'grouped' or 'persistent'; keep_fields: return (rho, ux, uy, T)."""
+    request, so twice as many resident); tol: max-norm change of u and of T per chunk that counts as
+    steady; step_cap: give up after this many steps; schedule: 'grouped' or 'persistent';
+    keep_fields: return (rho, ux, uy, T).
+
+    Plateau: a request whose change per chunk is below plateau_max and has not fallen below
+    0.9 times its best value for plateau_patience chunks has stopped approaching a fixed point and
+    is finished as "plateau", its best change recorded.  Closed buoyant cavities level off this way
+    even in FP64 (the corner closure lets mass drain slowly, so the discrete problem has no exact
+    steady state); FP32 storage adds its rounding noise to the level.  A slow but steady decay
+    (halving in fewer than about 6 * plateau_patience chunks) keeps running."""
 
     def __init__(self, budget_bytes=16 << 30, capacity=1024, precision="fp32_sr", chunk=1000, tol=1e-8,
                  step_cap=5_000_000, schedule="persistent", Pr=0.71, Ma=0.1, keep_fields=False,
-                 floor_patience=20, stream=None, in_place=False):
+                 plateau_patience=20, plateau_max=1e-5, stream=None, in_place=False):
         self.batch = clb.Batch(capacity, precision, budget_bytes=budget_bytes, stream=stream)
         self.precision, self.chunk, self.tol, self.step_cap = precision, int(chunk), float(tol), int(step_cap)
         self.schedule, self.Pr, self.Ma, self.keep_fields = schedule, Pr, Ma, keep_fields
-        self.floor_patience = int(floor_patience)
+        self.plateau_patience, self.plateau_max = int(plateau_patience), float(plateau_max)
         self.in_place = bool(in_place)
         self.site_updates = 0
 
@@ -113,17 +122,19 @@ class CavityServer:
                 r.steps += self.chunk
                 r.du, r.dT, nonfinite = resid[slot]
                 res = max(r.du, r.dT)
+                if not nonfinite:
+                    r.best = min(r.best, res)
                 if nonfinite:
                     r.status = "diverged"
                 elif res < self.tol:
                     r.status = "converged"
                 else:
-                    if res < 0.5 * st[1]:
+                    if res < 0.9 * st[1]:
                         st[1], st[2] = res, 0
                     else:
                         st[2] += 1
-                    if st[2] >= self.floor_patience and res < 1e-6:
-                        r.status = "floor"      # stopped decreasing at the arithmetic's resolution
+                    if st[2] >= self.plateau_patience and res < self.plateau_max:
+                        r.status = "plateau"    # stopped approaching a fixed point
                     elif r.steps >= self.step_cap:
                         r.status = "capped"
                 if r.status != "pending":
@@ -145,15 +156,20 @@ class CavityServer:
 
 
 def summarize(reqs, wall, site_updates):
-    """p50/p99 latency of finished requests, solves/s, aggregate MLUPS, counts by status."""
-    fin = [r for r in reqs if r.status in ("converged", "floor", "capped")]
+    """p50/p99 latency of finished requests (converged, plateau, capped), solves/s, aggregate MLUPS,
+    counts by status and the levels at which plateau requests stopped."""
+    fin = [r for r in reqs if r.status in ("converged", "plateau", "capped")]
     lat = np.array([r.latency for r in fin]) if fin else np.array([math.nan])
     counts = {}
     for r in reqs:
         counts[r.status] = counts.get(r.status, 0) + 1
-    return {"requests": len(reqs), "p50_latency_s": float(np.percentile(lat, 50)),
-            "p99_latency_s": float(np.percentile(lat, 99)), "solves_per_s": len(fin) / wall if wall > 0 else 0.0,
-            "aggregate_MLUPS": site_updates / wall / 1e6 if wall > 0 else 0.0, "wall_s": wall, "status": counts}
+    plateau = [r.best for r in reqs if r.status == "plateau"]
+    out = {"requests": len(reqs), "p50_latency_s": float(np.percentile(lat, 50)),
+           "p99_latency_s": float(np.percentile(lat, 99)), "solves_per_s": len(fin) / wall if wall > 0 else 0.0,
+           "aggregate_MLUPS": site_updates / wall / 1e6 if wall > 0 else 0.0, "wall_s": wall, "status": counts}
+    if plateau:
+        out["plateau_level"] = {"p50": float(np.percentile(plateau, 50)), "max": float(max(plateau))}
+    return out
 
 
 def requests_from(specs):

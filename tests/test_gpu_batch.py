@@ -215,7 +215,7 @@ def test_served_result_same_alone_and_in_mix(gpu):
     assert a.status == m.status and a.steps == m.steps and a.nu_wall == m.nu_wall
     for x, y in zip(a.fields, m.fields):
         assert np.array_equal(x, y)
-    assert all(r.status in ("converged", "floor", "capped") for r in out)
+    assert all(r.status in ("converged", "plateau", "capped") for r in out)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp32_sr"])
@@ -255,7 +255,7 @@ def _serve_against_oracle(precision, cases, step_cap):
     from paper_1710_10569_amd import serving as S
     reqs = [S.Request(i, 0.0, L, Ra, seed) for i, (L, Ra, seed) in enumerate(cases)]
     srv = S.CavityServer(budget_bytes=64 << 20, capacity=8, precision=precision, chunk=1000, tol=1e-9,
-                         step_cap=step_cap, schedule="grouped", keep_fields=True, floor_patience=10 ** 9)
+                         step_cap=step_cap, schedule="grouped", keep_fields=True, plateau_patience=10 ** 9)
     out = srv.run(reqs)
     srv.close()
     errs = []

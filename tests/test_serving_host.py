@@ -1,7 +1,7 @@
 """The serving loop's scheduling on the host, with a scripted stand-in for the batch (no GPU):
 admission by free slots and footprint, continuous admission as slots free up, and the stopping
-rules -- converged below the tolerance, stopped at the arithmetic's floor, capped, diverged, and
-rejected when a request could never fit the pool."""
+rules -- converged below the tolerance, stopped on a plateau, capped, diverged, and rejected when a
+request could never fit the pool."""
 import math
 
 import pytest
@@ -75,18 +75,30 @@ def server(monkeypatch):
 def test_stopping_rules(server):
     server.update({0: (1e-3, 500.0, 0.0),        # decays below tol: converged
                    1: (1e-3, 1e9, 0.0),          # never decays: capped at the step cap
-                   2: (1e-4, 300.0, 3e-7),       # levels off at 3e-7: stopped at the floor
-                   3: (float("nan"), 1.0, 0.0)})  # non-finite: diverged
-    reqs = [S.Request(i, 0.0, 32, 1e4, i) for i in range(4)]
-    srv = S.CavityServer(budget_bytes=1 << 30, capacity=8, chunk=1000, tol=1e-8, step_cap=40000, floor_patience=5)
+                   2: (1e-4, 300.0, 3e-7),       # levels off at 3e-7: plateau
+                   3: (float("nan"), 1.0, 0.0),  # non-finite: diverged
+                   4: (1e-3, 1e9, 2e-5)})        # stalls above plateau_max: runs to the cap
+    reqs = [S.Request(i, 0.0, 32, 1e4, i) for i in range(5)]
+    srv = S.CavityServer(budget_bytes=1 << 30, capacity=8, chunk=1000, tol=1e-8, step_cap=40000, plateau_patience=5)
     out = {r.id: r for r in srv.run(reqs)}
     assert out[0].status == "converged" and out[0].steps < 40000
     assert out[1].status == "capped" and out[1].steps == 40000
-    assert out[2].status == "floor"
+    assert out[2].status == "plateau" and out[2].best == pytest.approx(3e-7, rel=1e-3)
     assert out[3].status == "diverged" and out[3].steps == 1000
+    assert out[4].status == "capped" and out[4].steps == 40000
     assert out[0].nu_wall == 1.5
     s = S.summarize(list(out.values()), srv.wall, srv.site_updates)
-    assert s["status"] == {"converged": 1, "capped": 1, "floor": 1, "diverged": 1}
+    assert s["status"] == {"converged": 1, "capped": 2, "plateau": 1, "diverged": 1}
+    assert s["plateau_level"]["p50"] == pytest.approx(3e-7, rel=1e-3)
+
+
+def test_slow_decay_is_not_a_plateau(server):
+    """A residual that halves only every 60 chunks (e-folding 87 chunks) keeps falling by 10 % within
+    the 20-chunk patience, so it runs on to convergence instead of stopping as a plateau."""
+    server.update({0: (1e-6, 87_000.0, 0.0)})
+    srv = S.CavityServer(budget_bytes=1 << 30, capacity=2, chunk=1000, tol=1e-8, step_cap=10 ** 6)
+    out = srv.run([S.Request(0, 0.0, 32, 1e4, 0)])
+    assert out[0].status == "converged" and 350_000 < out[0].steps < 450_000
 
 
 def test_continuous_admission_by_slots(server):
