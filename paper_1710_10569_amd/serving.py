@@ -174,3 +174,40 @@ def summarize(reqs, wall, site_updates):
 
 def requests_from(specs):
     return [Request(id=s["id"], arrival=s["arrival"], L=s["L"], Ra=s["Ra"], noise_seed=s["noise_seed"]) for s in specs]
+
+
+def main(argv=None):
+    """Serve a seeded Poisson stream of cavity requests and print one line per finished request and
+    a JSON summary: python -m paper_1710_10569_amd.serving --requests 64 --lam inf"""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description=main.__doc__.split(":")[0])
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--lam", type=float, default=math.inf, help="arrivals per second (inf: all at t = 0)")
+    ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--L-min", type=int, default=32)
+    ap.add_argument("--L-max", type=int, default=1024)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--step-cap", type=int, default=5_000_000)
+    ap.add_argument("--budget-gib", type=float, default=16.0)
+    ap.add_argument("--precision", default="fp32_sr", choices=clb.PRECISIONS)
+    ap.add_argument("--schedule", default="grouped", choices=("grouped", "persistent"))
+    ap.add_argument("--in-place", action="store_true")
+    a = ap.parse_args(argv)
+    specs = W.serving_requests(n=a.requests, lam=a.lam if math.isfinite(a.lam) else 1.0, seed=a.seed,
+                               L_range=(a.L_min, a.L_max))
+    if not math.isfinite(a.lam):
+        for sp in specs:
+            sp["arrival"] = 0.0
+    srv = CavityServer(budget_bytes=int(a.budget_gib * (1 << 30)), capacity=1024, precision=a.precision,
+                       tol=a.tol, step_cap=a.step_cap, schedule=a.schedule, in_place=a.in_place)
+    out = srv.run(requests_from(specs), log=lambda m: print(m, flush=True))
+    summ = summarize(out, srv.wall, srv.site_updates)
+    srv.close()
+    summ.update({"lambda_per_s": a.lam if math.isfinite(a.lam) else "all at t=0", "seed": a.seed,
+                 "L_range": [a.L_min, a.L_max], "tol": a.tol, "step_cap": a.step_cap, "precision": a.precision})
+    print(json.dumps(summ), flush=True)
+
+
+if __name__ == "__main__":
+    main()

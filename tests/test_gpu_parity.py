@@ -238,3 +238,50 @@ def test_autotune_leaves_state_unchanged(gpu):
     for x, y in zip(a.moments(), b.moments()):
         assert np.array_equal(x, y)
     assert a.diagnostics()["step"] == 40
+
+
+
+def _hot_wall_nusselt(T3, dT=1.0):
+    """Hot-wall (west) Nusselt number of the cavity from its columns x = 0, 1, 2: the wall's mean of
+    -(H / dT) dT/dx with the second-order one-sided gradient (3 T_0 - 4 T_1 + T_2)/2, i.e. its
+    trapezoidal sum over the wall nodes divided by dT (unit spacing; the wall length H cancels)."""
+    T3 = np.asarray(T3)
+    wy = np.ones(T3.shape[0])
+    wy[[0, -1]] = 0.5
+    return float((wy * 0.5 * (3 * T3[:, 0] - 4 * T3[:, 1] + T3[:, 2])).sum() / dT)
+
+
+def test_cavity_256_full_run(gpu):
+    """The 256 x 256 differentially heated cavity (Ra = 1e5, Pr = 0.71, Ma = 0.1) over its full
+    50 000 steps, against the oracle's state stored by tests/golden/make_cavity256_reference.py
+    (512 sampled nodes and the hot-wall columns): FP64 within 1e-12; FP32 storage collided in FP64
+    with stochastic rounding within 1e-5 in u and T and its hot-wall Nusselt number within 1e-6
+    relative.  Plain FP32 (FP32 collision, round-to-nearest storage) is held to 3e-5: near the steady
+    state its rounding repeats the same error every step, and T drifts to 1.5e-5 of dT by 50 000
+    steps (measured), which is why the stochastic-rounding form serves steady-state solves."""
+    import json
+    import os
+    clb = _clb()
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cavity256_50k_oracle.json")))
+    w = W.cavity(256)
+    assert ref["workload"] == w["name"]
+    ys, xs = np.array(ref["samples"]["y"]), np.array(ref["samples"]["x"])
+    U = max(ref["scale"]["ux"], ref["scale"]["uy"], w["u_scale"])
+    nu_ref = _hot_wall_nusselt(ref["hot_wall_T"])
+    tol = {"fp64": FP64_TOL, "fp32_sr": FP32_TOL, "fp32": 3e-5}
+    for precision in ("fp64", "fp32_sr", "fp32"):
+        print(f"[parity] {w['name']} {precision} steps={ref['steps']}", flush=True)
+        g = clb.lattice_from_workload(w, precision)
+        g.step(ref["steps"])
+        rho, ux, uy, T = g.moments()
+        g.close()
+        eu = max(np.abs(ux[ys, xs] - ref["samples"]["ux"]).max(), np.abs(uy[ys, xs] - ref["samples"]["uy"]).max()) / U
+        eT = max(np.abs(T[ys, xs] - ref["samples"]["T"]).max(),
+                 np.abs(T[:, :3] - np.array(ref["hot_wall_T"])).max()) / ref["scale"]["T"]
+        er = np.abs(rho[ys, xs] - ref["samples"]["rho"]).max()
+        nu = _hot_wall_nusselt(T[:, :3])
+        print(f"[parity]   {precision}: u {eu:.2e} T {eT:.2e} rho {er:.2e} Nu_w {nu:.9f} "
+              f"(oracle {nu_ref:.9f}, rel {abs(nu / nu_ref - 1):.2e})", flush=True)
+        assert eu < tol[precision] and eT < tol[precision], (precision, eu, eT)
+        if precision == "fp32_sr":
+            assert abs(nu / nu_ref - 1) < 1e-6
