@@ -71,7 +71,8 @@ typedef struct {
 } clb_edge;
 
 typedef struct {
-    int nx, ny;        /* nodes; >= 3 each, >= 4 along the normal of an adiabatic wall pair */
+    int nx, ny;        /* nodes; >= 3 each, >= 4 along the normal of an adiabatic wall pair;
+                          nx <= 2^20, ny <= 2^18, nx * ny <= 2^30 */
     int precision;     /* CLB_FP64, CLB_FP32_DEV, CLB_FP64_DEV or CLB_FP32_SR */
     clb_edge west, east, south, north;
     double T0;         /* reference temperature of the Boussinesq force (Eq. 3) */

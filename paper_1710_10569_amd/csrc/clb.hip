@@ -70,7 +70,9 @@ int validate_desc(const clb_desc* d)
         set_error("lattice %dx%d too small (need at least %dx%d)", d->nx, d->ny, minx, miny);
         return CLB_EINVAL;
     }
-    if ((long long)d->nx * d->ny > (1LL << 30) || d->nx > (1 << 20) || d->ny > (1 << 20)) {
+    // ny: the initialisation, moment and export kernels take 4 rows per workgroup along the
+    // grid's y dimension, which holds at most 65536 workgroups
+    if ((long long)d->nx * d->ny > (1LL << 30) || d->nx > (1 << 20) || d->ny > (1 << 18)) {
         set_error("lattice %dx%d too large", d->nx, d->ny);
         return CLB_EINVAL;
     }

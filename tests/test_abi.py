@@ -55,6 +55,9 @@ def test_params_from_physics_matches_sec33_relations():
     dict(nx=10, ny=10, prescribed=True, in_place=True),                  # in-place is flow lattices only
     dict(nx=3, ny=10, in_place=True, edges={"west": ("dirichlet", 0, 0, 1), "east": ("dirichlet", 0, 0, 0)}),
     dict(nx=10, ny=10, in_place=2),
+    dict(nx=3, ny=(1 << 18) + 1),                                         # taller than the launch grids allow
+    dict(nx=(1 << 20) + 1, ny=3),
+    dict(nx=1 << 15, ny=(1 << 15) + 1),                                   # more than 2^30 nodes
 ])
 def test_create_rejects_bad_descriptions_on_host(bad):
     from paper_1710_10569_amd import clb

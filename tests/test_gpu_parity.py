@@ -285,3 +285,30 @@ def test_cavity_256_full_run(gpu):
         assert eu < tol[precision] and eT < tol[precision], (precision, eu, eT)
         if precision == "fp32_sr":
             assert abs(nu / nu_ref - 1) < 1e-6
+
+
+DEGENERATE = [
+    ((3, 3), ("dirichlet", "dirichlet", "dirichlet", "dirichlet")),    # one interior node, four corners
+    ((4, 4), ("adiabatic", "adiabatic", "adiabatic", "adiabatic")),    # smallest adiabatic box
+    ((3, 40), ("periodic", "periodic", "dirichlet", "adiabatic")),     # three periodic columns
+    ((65, 4), ("dirichlet", "adiabatic", "adiabatic", "dirichlet")),   # one node in the last chunk
+    ((129, 3), ("periodic", "periodic", "dirichlet", "dirichlet")),    # one interior row
+    ((4, 200), ("adiabatic", "dirichlet", "periodic", "periodic")),    # tall and narrow
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_sr"])
+@pytest.mark.parametrize("shape,kinds", DEGENERATE)
+def test_degenerate_sizes(gpu, precision, shape, kinds):
+    """The smallest lattices the method allows and chunk-ragged ones, with moving walls and
+    buoyancy: every node against the oracle after 200 steps; step(0) changes nothing."""
+    clb = _clb()
+    w = W.random_walled(*shape, seed=shape[0] * 11 + shape[1], kinds=kinds, wall_u=0.02, g_beta=2e-3)
+    g, o, errs = run_pair(w, precision, 200, chunks=2)
+    for e in errs:
+        assert max(e["u"], e["T"]) < (FP64_TOL if precision == "fp64" else FP32_TOL), e
+    before = g.moments()
+    g.step(0)
+    after = g.moments()
+    assert all(np.array_equal(a, b) for a, b in zip(before, after))
+    g.close()
