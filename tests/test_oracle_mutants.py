@@ -24,7 +24,7 @@ MUTANTS = [
     ("u_without_half_force", "*ux = (jx + 0.5 * (*Fx)) / r;", "*ux = jx / r;", "poiseuille"),
     ("zou_he_force_sign", "+ 0.5 * (rho * ut - 0.5 * Ft) + 0.5 * (rho * un - 0.5 * Fn - Dn);",
      "+ 0.5 * (rho * ut + 0.5 * Ft) + 0.5 * (rho * un - 0.5 * Fn - Dn);", "poiseuille"),
-    ("adiabatic_first_order", "Tb = (4.0 * Tf - Tff) / 3.0;", "Tb = Tf;", "walls"),
+    ("adiabatic_first_order", "Tb = (4.0 * Tf - Tff) / 3.0;", "Tb = Tf;", "adiabatic"),
     ("streaming_reversed", "int tx = x + EX[i], ty = y + EY[i];", "int tx = x - EX[i], ty = y - EY[i];", "walls"),
 ]
 
@@ -130,7 +130,13 @@ def pin_shear():
     return abs(r / (0.1 * k * k) - 1) < 3e-3
 
 
-PINS = {"shear": pin_shear, "moments": pin_moments, "forcing": pin_forcing, "decay": pin_decay, "poiseuille": pin_poiseuille,
+def pin_adiabatic():
+    """Decay rate of the slowest mode between an adiabatic and a Dirichlet wall at H = 32."""
+    from tests.test_oracle_physics import _neumann_mode_rate_error
+    return abs(_neumann_mode_rate_error(32)) < 5e-5
+
+
+PINS = {"adiabatic": pin_adiabatic, "shear": pin_shear, "moments": pin_moments, "forcing": pin_forcing, "decay": pin_decay, "poiseuille": pin_poiseuille,
         "walls": pin_walls}
 
 

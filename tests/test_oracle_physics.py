@@ -206,6 +206,35 @@ def test_conduction_profile(orient):
     assert np.abs(ux).max() < 1e-14 and np.abs(uy).max() < 1e-14
 
 
+def _neumann_mode_rate_error(H, tau_alpha=1.0):
+    """Relative error of the measured decay rate of T = A cos(pi y / (2H)) between an adiabatic wall
+    on node 0 and a Dirichlet wall (T = 0) on node H, no flow: the exact rate is alpha (pi / 2H)^2.
+    Measured between t = 1 and t = 2 in units of 1 / (alpha k^2), after the higher modes are gone."""
+    lat = O.OracleLattice(3, H + 1, Edge("periodic"), Edge("periodic"), Edge("adiabatic", 0, 0, 0),
+                          Edge("dirichlet", 0, 0, 0), T0=0.0)
+    lat.set_params(0.8, tau_alpha, 0.0)
+    k = math.pi / (2 * H)
+    mode = np.broadcast_to(np.cos(k * np.arange(H + 1))[:, None], (H + 1, 3))
+    lat.init(T=0.01 * mode)
+    alpha = (tau_alpha - 0.5) / 4
+    t0, t1 = int(1.0 / (alpha * k * k)), int(2.0 / (alpha * k * k))
+    lat.step(t0)
+    a = (lat.moments()[3] * mode).sum()
+    lat.step(t1 - t0)
+    b = (lat.moments()[3] * mode).sum()
+    return math.log(a / b) / (t1 - t0) / (alpha * k * k) - 1
+
+
+def test_adiabatic_wall_is_a_second_order_zero_gradient():
+    """The adiabatic wall (R11) is a zero-gradient condition on the wall node: the slowest mode of
+    the slab, cos(pi y / 2H), decays at alpha (pi / 2H)^2 with an error that falls at least as fast
+    as H^-2 (a first-order extrapolation T_b = T_1 moves the wall by half a cell and misses by about
+    1/H: 6.5 % at H = 16, 3.2 % at H = 32)."""
+    e = {H: _neumann_mode_rate_error(H) for H in (8, 16, 32)}
+    assert abs(e[8]) < 2e-3 and abs(e[16]) < 2e-4 and abs(e[32]) < 5e-5, e
+    assert abs(e[16]) < abs(e[8]) / 4, e
+
+
 def test_wall_values_imposed():
     """After the wall step, Eq. 13 returns the wall velocity at every wall node (moving and
     permeable walls included) and Eq. 23 the wall temperature on Dirichlet walls; adiabatic wall
