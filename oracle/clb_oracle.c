@@ -38,8 +38,8 @@
  *
  * Parity unpinned: no printed value, closed form or invariant fixes these choices, so they hold only
  * as readings, shared by construction with the GPU library: the default s_b = 1, the corner data
- * (which wall's velocity and temperature a corner takes, and the diagonal extrapolation), the
- * initialisation convention, and the wall velocity of the temperature-only mode.
+ * (which wall's velocity and temperature a corner takes, and the diagonal extrapolation) and the
+ * wall velocity of the temperature-only mode.
  *
  * State convention: the arrays f[9][n] and g[5][n] hold the populations of time t after streaming
  * and before the wall step ("state(t)").  One step = wall step -> macroscopic -> collision ->

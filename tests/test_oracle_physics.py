@@ -13,6 +13,8 @@ import pytest
 
 import oracle as O
 from oracle import Edge
+
+EY9 = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
 from paper_1710_10569_amd import workloads as W
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -233,6 +235,28 @@ def test_adiabatic_wall_is_a_second_order_zero_gradient():
     e = {H: _neumann_mode_rate_error(H) for H in (8, 16, 32)}
     assert abs(e[8]) < 2e-3 and abs(e[16]) < 2e-4 and abs(e[32]) < 5e-5, e
     assert abs(e[16]) < abs(e[8]) / 4, e
+
+
+def test_initial_state_returns_the_given_fields():
+    """Initialisation (R8): the populations are the equilibria at (rho0, u0 - F/(2 rho0)) and
+    (T, u0), so the moments of the initial state -- Eq. 13 with the force of Eq. 3 from the same T --
+    are exactly the given rho0, u0, T on a periodic lattice with buoyancy and a body force (taking
+    u0 itself as the equilibrium velocity would be off by F/(2 rho0))."""
+    rng = np.random.default_rng(21)
+    ny, nx = 9, 11
+    rho = 1 + rng.uniform(-0.02, 0.02, (ny, nx))
+    ux, uy = rng.uniform(-0.03, 0.03, (ny, nx)), rng.uniform(-0.03, 0.03, (ny, nx))
+    T = 0.4 + rng.uniform(-0.1, 0.1, (ny, nx))
+    lat = O.OracleLattice(nx, ny, T0=0.3)
+    lat.set_params(0.8, 0.9, 5e-3)
+    lat.set_body_force(2e-4, -1e-4)
+    lat.init(rho, ux, uy, T)
+    r, u, v, t = lat.moments()
+    for a, b in ((r, rho), (u, ux), (v, uy), (t, T)):
+        assert np.abs(a - b).max() < 2e-16 * 8
+    f, _ = lat.get_state()
+    F_y = -1e-4 + 5e-3 * (T - 0.3)
+    assert np.abs((f * EY9[:, None, None]).sum(0) - (rho * uy - 0.5 * F_y)).max() < 1e-16 * 8
 
 
 def test_wall_values_imposed():
