@@ -82,8 +82,9 @@ typedef struct {
     int in_place;      /* 1: in-place streaming (one population buffer, half the footprint; same
                           results bitwise as 0, the two-buffer pull streaming of Eqs. 12 and 22).
                           Not with prescribed_u; at least 4 nodes across a walled direction.  An
-                          in-place lattice runs one step kernel (256 x 1 tiles): of its tile shape
-                          only the non-temporal-store flag applies, and it is not autotuned */
+                          in-place lattice runs one step kernel in rows of 64 or 256 nodes: of its
+                          tile shape only the width (64, else 256) and the non-temporal-store flag
+                          apply, and it is not autotuned */
 } clb_desc;
 
 typedef struct clb_lattice clb_lattice;

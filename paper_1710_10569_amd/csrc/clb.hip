@@ -114,16 +114,18 @@ static hipError_t launch_one_step(clb_lattice* h, int shape, const void* src, vo
     if (d.in_place) {
         // src is the buffer, dst the snapshot pair; the parity of the step picks the form and the copies
         const bool odd = (step & 1) != 0;
-        const bool nt = tile_shape(shape).nt != 0;   // the one in-place kernel takes only the store form
+        // the in-place kernel takes the store form and the workgroup width (64 or 256) of the shape
+        const bool nt = tile_shape(shape).nt != 0;
+        const int txw = tile_shape(shape).tx == 64 ? 64 : 256;
         const size_t sb = size_t(snap_elems(d.nx, d.ny)) * elem_bytes(d.precision);
         void* A = const_cast<void*>(src);
         const void* snow = (const char*)dst + (odd ? sb : 0);
         void* snext = (char*)dst + (odd ? 0 : sb);
         switch (d.precision) {
-        case CLB_FP64: return launch_step_aa<double, double, false>(odd, nt, A, snow, snext, G, make_par<double>(d, h->par), key, h->stream);
-        case CLB_FP64_DEV: return launch_step_aa<double, double, true>(odd, nt, A, snow, snext, G, make_par<double>(d, h->par), key, h->stream);
-        case CLB_FP32_SR: return launch_step_aa<float, double, true>(odd, nt, A, snow, snext, G, make_par<double>(d, h->par), key, h->stream);
-        default: return launch_step_aa<float, float, true>(odd, nt, A, snow, snext, G, make_par<float>(d, h->par), key, h->stream);
+        case CLB_FP64: return launch_step_aa<double, double, false>(odd, nt, txw, A, snow, snext, G, make_par<double>(d, h->par), key, h->stream);
+        case CLB_FP64_DEV: return launch_step_aa<double, double, true>(odd, nt, txw, A, snow, snext, G, make_par<double>(d, h->par), key, h->stream);
+        case CLB_FP32_SR: return launch_step_aa<float, double, true>(odd, nt, txw, A, snow, snext, G, make_par<double>(d, h->par), key, h->stream);
+        default: return launch_step_aa<float, float, true>(odd, nt, txw, A, snow, snext, G, make_par<float>(d, h->par), key, h->stream);
         }
     }
     if (d.prescribed_u) {
@@ -169,19 +171,25 @@ static std::tuple<int, int, int> tune_key(const clb_desc& d)
     return std::make_tuple(d.precision, log2_class(d.nx), log2_class(d.ny));
 }
 
-// Without an autotuner result for the size class: when the two buffers fit the 256 MiB Infinity
-// Cache (MALL), ordinary stores, which leave the next step's input there -- 256 x 1 tiles with an
-// occupancy-8 register budget in FP32, 128 x 4 tiles for FP32 storage with FP64 arithmetic; beyond
-// it (and always in FP64) 256 x 1 tiles with non-temporal stores.  These were the fastest in sweeps
-// on MI355X at 2048 x 1024 and 8192 x 4096 in real ping-pong stepping.
+// Without an autotuner result for the size class.  Two-buffer streaming: one-wavefront workgroups
+// (64 x 1 tiles, one storage chunk each); when the two buffers fit the 256 MiB Infinity Cache
+// (MALL) and the populations are FP32, ordinary stores, which leave the next step's input there;
+// in FP64, and beyond the cache, non-temporal stores, with an occupancy-8 register budget in FP32.
+// In real ping-pong stepping on MI355X these beat the 256-thread shapes by 0.5-3 % at 2048 x 1024
+// and 8192 x 4096 in every precision.  In-place streaming: 256-node workgroups (1 % faster than
+// one wavefront at 8192 x 4096), ordinary stores for FP32 populations that fit the cache,
+// non-temporal ones otherwise.
 int default_shape(const clb_desc& d)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(tune_key(d));
     if (it != g_tune_cache.end()) return it->second;
     const double footprint = (d.in_place ? 1.0 : 2.0) * double(buffer_elems(d.nx, d.ny)) * double(elem_bytes(d.precision));
-    if (footprint > double(256 << 20)) return 6;
-    return d.precision == CLB_FP32_DEV ? 8 : d.precision == CLB_FP32_SR ? 4 : 6;
+    const bool fp32 = d.precision == CLB_FP32_DEV || d.precision == CLB_FP32_SR;
+    const bool in_cache = footprint <= double(256 << 20);
+    if (d.in_place) return in_cache && fp32 ? 2 : 6;
+    if (!in_cache) return d.precision == CLB_FP32_DEV ? 13 : 11;
+    return fp32 ? 12 : 11;
 }
 
 static int launch_moments(clb_lattice* h)

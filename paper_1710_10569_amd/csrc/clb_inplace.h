@@ -217,9 +217,10 @@ __device__ __forceinline__ void node_update_aa(S* __restrict__ A, const S* __res
     store_aa<S, ODD, NT>(A, snext, G, x, y, v);
 }
 
-// One in-place step: 256 x 1 tiles handed out XCD by XCD, as the two-buffer step kernel.
-template <typename S, typename Real, bool DEV, bool ODD, bool NT>
-__global__ __launch_bounds__(256) void step_aa_kernel(S* __restrict__ A, const S* __restrict__ snow,
+// One in-place step: TXW x 1 tiles (TXW = 64: one wavefront per workgroup, or 256) handed out XCD
+// by XCD, as the two-buffer step kernel.
+template <typename S, typename Real, bool DEV, bool ODD, bool NT, int TXW>
+__global__ __launch_bounds__(TXW) void step_aa_kernel(S* __restrict__ A, const S* __restrict__ snow,
                                                      S* __restrict__ snext, Geo G, Par<Real> P, int tiles_x,
                                                      int ntiles, uint32_t key)
 {
@@ -227,28 +228,34 @@ __global__ __launch_bounds__(256) void step_aa_kernel(S* __restrict__ A, const S
     const int t = int(blockIdx.x & 7) * q + int(blockIdx.x >> 3);
     if (t >= ntiles) return;
     const int y = t / tiles_x;
-    const int x = (t - y * tiles_x) * 256 + int(threadIdx.x);
+    const int x = (t - y * tiles_x) * TXW + int(threadIdx.x);
     if (x >= G.nx) return;
     node_update_aa<S, Real, DEV, ODD, NT>(A, snow, snext, G, P, x, y, key);
 }
 
-template <typename S, typename Real, bool DEV>
-hipError_t launch_step_aa(bool odd, bool nt, void* A, const void* snow, void* snext, const Geo& G, const Par<Real>& P,
-                          uint32_t key, hipStream_t st)
+template <typename S, typename Real, bool DEV, int TXW>
+void launch_step_aa_w(bool odd, bool nt, S* a, const S* sn, S* sx, const Geo& G, const Par<Real>& P, uint32_t key,
+                      hipStream_t st)
 {
-    const int tx = (G.nx + 255) / 256, ntiles = tx * G.ny;
+    const int tx = (G.nx + TXW - 1) / TXW, ntiles = tx * G.ny;
     const int q = (ntiles + 7) / 8;
-    const dim3 grid(8 * q), block(256);
-    S* a = (S*)A;
-    const S* sn = (const S*)snow;
-    S* sx = (S*)snext;
+    const dim3 grid(8 * q), block(TXW);
     if (odd) {
-        if (nt) step_aa_kernel<S, Real, DEV, true, true><<<grid, block, 0, st>>>(a, sn, sx, G, P, tx, ntiles, key);
-        else step_aa_kernel<S, Real, DEV, true, false><<<grid, block, 0, st>>>(a, sn, sx, G, P, tx, ntiles, key);
+        if (nt) step_aa_kernel<S, Real, DEV, true, true, TXW><<<grid, block, 0, st>>>(a, sn, sx, G, P, tx, ntiles, key);
+        else step_aa_kernel<S, Real, DEV, true, false, TXW><<<grid, block, 0, st>>>(a, sn, sx, G, P, tx, ntiles, key);
     } else {
-        if (nt) step_aa_kernel<S, Real, DEV, false, true><<<grid, block, 0, st>>>(a, sn, sx, G, P, tx, ntiles, key);
-        else step_aa_kernel<S, Real, DEV, false, false><<<grid, block, 0, st>>>(a, sn, sx, G, P, tx, ntiles, key);
+        if (nt) step_aa_kernel<S, Real, DEV, false, true, TXW><<<grid, block, 0, st>>>(a, sn, sx, G, P, tx, ntiles, key);
+        else step_aa_kernel<S, Real, DEV, false, false, TXW><<<grid, block, 0, st>>>(a, sn, sx, G, P, tx, ntiles, key);
     }
+}
+
+// txw: workgroup width, 64 or 256 nodes (from the lattice's tile shape); nt: non-temporal stores.
+template <typename S, typename Real, bool DEV>
+hipError_t launch_step_aa(bool odd, bool nt, int txw, void* A, const void* snow, void* snext, const Geo& G,
+                          const Par<Real>& P, uint32_t key, hipStream_t st)
+{
+    if (txw == 64) launch_step_aa_w<S, Real, DEV, 64>(odd, nt, (S*)A, (const S*)snow, (S*)snext, G, P, key, st);
+    else launch_step_aa_w<S, Real, DEV, 256>(odd, nt, (S*)A, (const S*)snow, (S*)snext, G, P, key, st);
     return hipGetLastError();
 }
 

@@ -20,8 +20,10 @@ namespace clb {
 // both nodes' 28 values before computing either, to double the loads in flight per thread.
 struct TileShape { int tx, ty, spt, nt, wpe; };
 
-// The compiled shapes (the autotuner chooses among them).
-constexpr int kNumShapes = 11;
+// The compiled shapes (the autotuner chooses among them).  11-13 are one-wavefront workgroups (one
+// 64-node chunk of a row each): the finest dispatch granularity, which plain streaming copies
+// on MI355X favour over 256-thread workgroups.
+constexpr int kNumShapes = 14;
 __host__ __device__ constexpr TileShape tile_shape(int i)
 {
     return i == 0 ? TileShape{64, 4, 1, 0, 0}
@@ -34,7 +36,10 @@ __host__ __device__ constexpr TileShape tile_shape(int i)
          : i == 7 ? TileShape{64, 4, 2, 0, 0}
          : i == 8 ? TileShape{256, 1, 1, 0, 8}
          : i == 9 ? TileShape{256, 1, 1, 1, 8}
-                  : TileShape{128, 2, 1, 1, 8};
+         : i == 10 ? TileShape{128, 2, 1, 1, 8}
+         : i == 11 ? TileShape{64, 1, 1, 1, 0}
+         : i == 12 ? TileShape{64, 1, 1, 0, 0}
+                   : TileShape{64, 1, 1, 1, 8};
 }
 
 inline int tiles_x_of(const Geo& G, const TileShape& s) { return (G.nx + s.tx - 1) / s.tx; }
@@ -88,7 +93,10 @@ hipError_t launch_step_any(int shape, const void* src, void* dst, const Geo& G, 
     case 7: return launch_step_shape<S, Real, DEV, 7>(src, dst, G, P, key, st);
     case 8: return launch_step_shape<S, Real, DEV, 8>(src, dst, G, P, key, st);
     case 9: return launch_step_shape<S, Real, DEV, 9>(src, dst, G, P, key, st);
-    default: return launch_step_shape<S, Real, DEV, 10>(src, dst, G, P, key, st);
+    case 10: return launch_step_shape<S, Real, DEV, 10>(src, dst, G, P, key, st);
+    case 11: return launch_step_shape<S, Real, DEV, 11>(src, dst, G, P, key, st);
+    case 12: return launch_step_shape<S, Real, DEV, 12>(src, dst, G, P, key, st);
+    default: return launch_step_shape<S, Real, DEV, 13>(src, dst, G, P, key, st);
     }
 }
 
