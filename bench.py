@@ -339,8 +339,8 @@ def main():
     if not args.no_copy:
         cb = copy_bandwidth(torch)
         log(f"[bench] plain copy: {cb:.0f} GB/s")
-        result["copy_reference_GBps"] = cb
-        result["roofline"]["frac_of_copy"] = r32["gbps"] / cb
+        result["torch_copy_GBps"] = cb
+        result["roofline"]["frac_of_torch_copy"] = r32["gbps"] / cb
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(result), flush=True)
