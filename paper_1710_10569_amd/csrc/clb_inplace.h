@@ -28,11 +28,13 @@ __host__ __device__ constexpr int opp_of(int i)
 }
 
 // Snapshot layout: band b (0 west, 1 east, 2 south, 3 north), depth k (0: next to the wall, 1: one
-// further), position j along the wall, population slot q (0..13): ((b * 2 + k) * len + j) * 14 + q,
-// len = max(nx, ny).  Elements per copy:
+// further), population slot q (0..13), position j along the wall: ((b * 2 + k) * 14 + q) * len + j,
+// len = max(nx, ny).  Population-major, so that neighbouring nodes of a band, which neighbouring
+// lanes write and read, are contiguous.  Elements per copy:
 __host__ __device__ __forceinline__ long long snap_elems(int nx, int ny) { return 8LL * (nx > ny ? nx : ny) * 14; }
 
-// Snapshot offset of node (x, y), or -1 if it lies in no band.  x-bands are tried first.
+// Snapshot offset of population 0 of node (x, y) (population q at + q * len), or -1 if the node lies
+// in no band.  x-bands are tried first.
 __device__ __forceinline__ long long snap_at(const Geo& G, int x, int y)
 {
     const long long len = G.nx > G.ny ? G.nx : G.ny;
@@ -42,7 +44,7 @@ __device__ __forceinline__ long long snap_at(const Geo& G, int x, int y)
     else if (!G.pery && (y == 1 || y == 2)) { b = 2; k = y - 1; j = x; }
     else if (!G.pery && (y == G.ny - 2 || y == G.ny - 3)) { b = 3; k = G.ny - 2 - y; j = x; }
     if (b < 0) return -1;
-    return ((b * 2 + k) * len + j) * 14;
+    return (b * 2 + k) * 14 * len + j;
 }
 
 // snap_at for the wall step's neighbours, which always lie in a band (at least 4 nodes across a
@@ -59,10 +61,10 @@ template <typename S>
 __device__ __forceinline__ void snap_put(S* __restrict__ snap, const Geo& G, int x, int y, int q, S v)
 {
     const long long len = G.nx > G.ny ? G.nx : G.ny;
-    if (!G.perx && (x == 1 || x == 2)) snap[((0 * 2 + x - 1) * len + y) * 14 + q] = v;
-    if (!G.perx && (x == G.nx - 2 || x == G.nx - 3)) snap[((1 * 2 + G.nx - 2 - x) * len + y) * 14 + q] = v;
-    if (!G.pery && (y == 1 || y == 2)) snap[((2 * 2 + y - 1) * len + x) * 14 + q] = v;
-    if (!G.pery && (y == G.ny - 2 || y == G.ny - 3)) snap[((3 * 2 + G.ny - 2 - y) * len + x) * 14 + q] = v;
+    if (!G.perx && (x == 1 || x == 2)) snap[((0 * 2 + x - 1) * 14 + q) * len + y] = v;
+    if (!G.perx && (x == G.nx - 2 || x == G.nx - 3)) snap[((1 * 2 + G.nx - 2 - x) * 14 + q) * len + y] = v;
+    if (!G.pery && (y == 1 || y == 2)) snap[((2 * 2 + y - 1) * 14 + q) * len + x] = v;
+    if (!G.pery && (y == G.ny - 2 || y == G.ny - 3)) snap[((3 * 2 + G.ny - 2 - y) * 14 + q) * len + x] = v;
 }
 
 // The wall step's inner neighbours, read from the snapshot copy of the current time step.
@@ -72,18 +74,20 @@ struct SnapSource {
     template <typename Real>
     __device__ __forceinline__ void all(const Geo& G, int x, int y, Real f[9], Real g[5]) const
     {
+        const long long len = G.nx > G.ny ? G.nx : G.ny;
         const long long o = snap_at_checked(G, x, y);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = Real(snap[o + i]);
+        for (int i = 0; i < 9; ++i) f[i] = Real(snap[o + i * len]);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) g[i] = Real(snap[o + 9 + i]);
+        for (int i = 0; i < 5; ++i) g[i] = Real(snap[o + (9 + i) * len]);
     }
     template <typename Real>
     __device__ __forceinline__ void temp(const Geo& G, int x, int y, Real g[5]) const
     {
+        const long long len = G.nx > G.ny ? G.nx : G.ny;
         const long long o = snap_at_checked(G, x, y);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) g[i] = Real(snap[o + 9 + i]);
+        for (int i = 0; i < 5; ++i) g[i] = Real(snap[o + (9 + i) * len]);
     }
 };
 
@@ -183,20 +187,20 @@ __device__ __forceinline__ void store_aa(S* __restrict__ A, S* __restrict__ snex
 #pragma unroll
     for (int d = -1; d <= 1; ++d) {
         const int tx = x + d, ty = y + d;
-        cbase[d + 1] = G.perx ? -1 : (tx == 1 || tx == 2) ? (0 * 2 + tx - 1) * len * 14
-                                  : (tx == G.nx - 2 || tx == G.nx - 3) ? (1 * 2 + G.nx - 2 - tx) * len * 14 : -1;
-        rbase[d + 1] = G.pery ? -1 : (ty == 1 || ty == 2) ? (2 * 2 + ty - 1) * len * 14
-                                  : (ty == G.ny - 2 || ty == G.ny - 3) ? (3 * 2 + G.ny - 2 - ty) * len * 14 : -1;
-        ypos[d + 1] = ty >= 0 && ty < G.ny ? ty * 14 : (G.pery ? (ty < 0 ? G.ny - 1 : 0) * 14 : -1);
-        xpos[d + 1] = tx >= 0 && tx < G.nx ? tx * 14 : (G.perx ? (tx < 0 ? G.nx - 1 : 0) * 14 : -1);
+        cbase[d + 1] = G.perx ? -1 : (tx == 1 || tx == 2) ? (0 * 2 + tx - 1) * 14 * len
+                                  : (tx == G.nx - 2 || tx == G.nx - 3) ? (1 * 2 + G.nx - 2 - tx) * 14 * len : -1;
+        rbase[d + 1] = G.pery ? -1 : (ty == 1 || ty == 2) ? (2 * 2 + ty - 1) * 14 * len
+                                  : (ty == G.ny - 2 || ty == G.ny - 3) ? (3 * 2 + G.ny - 2 - ty) * 14 * len : -1;
+        ypos[d + 1] = ty >= 0 && ty < G.ny ? ty : (G.pery ? (ty < 0 ? G.ny - 1 : 0) : -1);
+        xpos[d + 1] = tx >= 0 && tx < G.nx ? tx : (G.perx ? (tx < 0 ? G.nx - 1 : 0) : -1);
     }
 #pragma unroll
     for (int q = 0; q < 14; ++q) {
         const int i = q < 9 ? q : q - 9;
         const int dx = ex_of(i) + 1, dy = ey_of(i) + 1;
         // a node can lie in a column band and a row band: both copies are written
-        if (cbase[dx] >= 0 && ypos[dy] >= 0) snext[cbase[dx] + ypos[dy] + q] = v[q];
-        if (rbase[dy] >= 0 && xpos[dx] >= 0) snext[rbase[dy] + xpos[dx] + q] = v[q];
+        if (cbase[dx] >= 0 && ypos[dy] >= 0) snext[cbase[dx] + q * len + ypos[dy]] = v[q];
+        if (rbase[dy] >= 0 && xpos[dx] >= 0) snext[rbase[dy] + q * len + xpos[dx]] = v[q];
     }
 }
 
