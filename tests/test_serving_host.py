@@ -126,3 +126,16 @@ def test_request_larger_than_the_pool_is_rejected(server):
     srv = S.CavityServer(budget_bytes=32 * 32 * 100 * 4, capacity=4, chunk=1000, tol=1e-8, step_cap=10 ** 5)
     out = {r.id: r for r in srv.run(reqs)}
     assert out[1].status == "rejected" and out[0].status == "converged"
+
+
+def test_command_line_summary(server, capsys):
+    """python -m paper_1710_10569_amd.serving: one line per finished request, then a JSON summary."""
+    import json
+    for i in range(5):
+        server[i] = (1e-3, 300.0, 0.0)
+    S.main(["--requests", "5", "--L-max", "64", "--budget-gib", "1"])
+    lines = capsys.readouterr().out.strip().splitlines()
+    assert sum(line.startswith("[serve]") for line in lines) == 5
+    summary = json.loads(lines[-1])
+    assert summary["requests"] == 5 and summary["status"] == {"converged": 5}
+    assert summary["L_range"] == [32, 64] and summary["lambda_per_s"] == "all at t=0"
