@@ -13,9 +13,9 @@ one), the roofline of the step kernel (112 algorithmic bytes per FP32 site updat
 read + 14 written; 224 in FP64), the same lattice in FP64 and in FP32 storage with FP64 collision
 and stochastic rounding ("fp32_sr") beside it, their field errors against FP64, an 8192 x 4096
 control lattice whose footprint (3.8 GB) is far beyond the 256 MB Infinity Cache, the 512-cavity
-batch, in-place streaming (one population buffer) on the same lattices, two serving runs
-(Poisson arrivals of small cavities, and a saturated queue of larger ones), and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+batch, in-place streaming (one population buffer) on the same lattices, two serving runs of 32
+cavity solves from the served size mix (sides 32-1024: all queued at once, then Poisson arrivals at
+about half the capacity), and the FP64 CPU oracle timed on a bounded sample of the same workload.
 Progress goes to stderr.
 """
 import argparse
@@ -175,9 +175,12 @@ def run_batch(clb, W, steps, stream, precision="fp32", modes=("grouped", "each")
     return out
 
 
-def run_serving(clb, W, stream, n=32, lam=8.0, L_range=(32, 128), tol=1e-8, step_cap=200_000, patience=20):
+def run_serving(clb, W, stream, n=32, lam=0.35, L_range=(32, 1024), tol=1e-8, step_cap=5_000_000, patience=20):
     """A Poisson stream of cavity requests (lam per second; lam = inf: all queued at time 0) served
-    with continuous batching (serving.py), FP32 storage with FP64 collision and stochastic rounding."""
+    with continuous batching (serving.py), FP32 storage with FP64 collision and stochastic rounding.
+    Defaults: the served workload's size mix (L log-uniform in 32-1024, Ra log-uniform in 1e3-1e6,
+    step cap 5e6) with 32 requests arriving at 0.35 per second, about half the capacity measured for
+    this mix; one progress line per finished request."""
     from paper_1710_10569_amd import serving as S
     specs = W.serving_requests(n=n, lam=lam if math.isfinite(lam) else 1.0, L_range=L_range)
     if not math.isfinite(lam):
@@ -186,7 +189,7 @@ def run_serving(clb, W, stream, n=32, lam=8.0, L_range=(32, 128), tol=1e-8, step
     reqs = S.requests_from(specs)
     srv = S.CavityServer(budget_bytes=8 << 30, capacity=256, chunk=1000, tol=tol, step_cap=step_cap,
                          schedule="grouped", plateau_patience=patience, stream=stream)
-    out = srv.run(reqs)
+    out = srv.run(reqs, log=log)
     summ = S.summarize(out, srv.wall, srv.site_updates)
     srv.close()
     summ.update({"lambda_per_s": lam if math.isfinite(lam) else "all at t=0", "L_range": list(L_range),
@@ -331,10 +334,9 @@ def main():
                                                                 "fp32", modes=("grouped",), in_place=True)
             torch.cuda.empty_cache()
     if not args.no_serve:
-        result["served"] = run_serving(clb, W, stream.cuda_stream)
+        result["served_saturated"] = run_serving(clb, W, stream.cuda_stream, lam=math.inf)
         torch.cuda.empty_cache()
-        result["served_saturated"] = run_serving(clb, W, stream.cuda_stream, n=64, lam=math.inf,
-                                                 L_range=(128, 512), step_cap=20_000)
+        result["served"] = run_serving(clb, W, stream.cuda_stream)
         torch.cuda.empty_cache()
     if not args.no_copy:
         cb = copy_bandwidth(torch)
