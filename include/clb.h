@@ -17,8 +17,8 @@
  *     element (x, y) of an nx-by-ny field is at index y*nx + x.
  *   - Return value: CLB_OK (0) or a negative error code; a message for the last error of the
  *     calling thread is available from clb_last_error().  No call aborts the process.
- *   - A handle owns its device memory (unless created with clb_create_external) and is used by
- *     one host thread at a time.
+ *   - A lattice handle owns its device memory; a batch owns its pool unless the caller passes one
+ *     to clb_batch_create.  A handle is used by one host thread at a time.
  *   - Work is enqueued on the handle's HIP stream.  clb_step does not block; calls that return
  *     data to the host (clb_moments, clb_get_populations, clb_diagnostics) synchronise the stream.
  *   - Edge order everywhere: west (x = 0), east (x = nx-1), south (y = 0), north (y = ny-1).
