@@ -204,7 +204,10 @@ int clb_tile_shape_info(int shape, int* tx, int* ty, int* spt, int* nontemporal)
 
 /* Select / read the shape used by clb_step.  A new handle starts with the shape the autotuner
  * last chose in this process for the same precision and size class (ceil(log2 nx),
- * ceil(log2 ny)), else shape 8 (FP32) or 6 (FP64). */
+ * ceil(log2 ny)), else a default by footprint: one-wavefront 64 x 1 tiles -- shape 12 (plain
+ * stores) for FP32 populations whose two buffers fit the 256 MiB Infinity Cache, 13 (non-temporal,
+ * occupancy-8 budget) for plain FP32 beyond it, 11 (non-temporal) otherwise; an in-place lattice
+ * takes 256-node rows, shape 2 for FP32 populations that fit the cache, else 6. */
 int clb_set_tile_shape(clb_lattice* h, int shape);
 int clb_get_tile_shape(clb_lattice* h, int* shape);
 
@@ -230,7 +233,8 @@ const char* clb_last_error(void);
  * Batches: many lattices of different sizes resident in one HBM pool and advanced together.
  *
  * A batch owns (or borrows) one device pool and carves it into per-lattice regions: two
- * population buffers and an FP64 snapshot of (u_x, u_y, T) for the residual test.  Adding a lattice
+ * population buffers (an in-place lattice: one, plus its two wall-band snapshots) and an FP64
+ * snapshot of (u_x, u_y, T) for the residual test.  Adding a lattice
  * is admission: it fails with CLB_ENOMEM when its region does not fit in the pool's free space.
  * All lattices of a batch use the batch's precision.  Every schedule below runs the same per-node
  * update, so a lattice's results do not depend on the schedule or on which other lattices share
@@ -251,7 +255,10 @@ int clb_batch_create(int capacity, int precision, size_t hbm_budget_bytes, void*
 
 /* Admit a lattice (desc->precision must equal the batch's) with the parameters of
  * clb_set_params; it starts at rest (rho = 1, u = 0, T = T0) with step count 0.  *slot receives its
- * index.  Errors: CLB_EINVAL; CLB_ENOMEM if the batch is full or the pool lacks space. */
+ * index.  Two-buffer and in-place lattices may share a batch; temperature-only lattices
+ * (prescribed_u = 1) are single-lattice only.  Errors: CLB_EINVAL (bad description, precision
+ * other than the batch's, prescribed_u = 1); CLB_ENOMEM if the batch is full or the pool lacks
+ * space. */
 int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, double tau_alpha, double g_beta, double Ma,
                   int* slot);
 
