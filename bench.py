@@ -152,16 +152,22 @@ def run_batch(clb, W, steps, stream, precision="fp32", modes=("grouped", "each")
     budget = sum(clb.footprint(L, L, precision, in_place=in_place) for L, _, _ in specs) + (64 << 20)
     b = clb.Batch(len(specs), precision, budget_bytes=budget, stream=stream)
     t0 = time.perf_counter()
+    slots = []
     for L, Ra, seed in specs:
-        if b.add_workload(W.cavity(L, Ra=Ra, seed=seed), in_place=in_place) is None:
+        slots.append(b.add_workload(W.cavity(L, Ra=Ra, seed=seed), in_place=in_place))
+        if slots[-1] is None:
             raise RuntimeError("batch pool too small")
     log(f"[bench] batch {precision}: {len(specs)} cavities, {total:.4g} nodes, pool {budget / 1e9:.2f} GB, "
         f"set up in {time.perf_counter() - t0:.1f} s")
     b.step(20)
     b.autotune(3)
     torch.cuda.synchronize()
+    widths = {}
+    for slot, (L, _, _) in zip(slots, specs):
+        widths.setdefault(str(b.tile_width(slot)), []).append(L)
     out = {"precision": precision, "in_place": in_place, "cavities": len(specs), "sites": total, "steps": steps,
-           "pool_GB": budget / 1e9}
+           "pool_GB": budget / 1e9, "nontemporal_stores": b.nontemporal,
+           "tile_width_by_side": {w: sorted(set(Ls)) for w, Ls in sorted(widths.items())}}
     for mode in modes:
         n = steps if mode != "each" else max(10, steps // 10)
         b.step(2, mode)

@@ -307,11 +307,20 @@ int clb_batch_time_steps(clb_batch* b, int mode, long long n, double* ms);
  * walls in x this halves the wavefronts that take the wall branch). */
 int clb_batch_set_tile_width(clb_batch* b, int slot, int tile_width);
 
+/* The lattice's current tile width (64, 128, 256, or 0 for wrapped rows), as set by
+ * clb_batch_set_tile_width, clb_batch_autotune or the default by width (64 up to 96 nodes, 128 up
+ * to 192, 256 beyond).  Errors: CLB_EINVAL for an unused slot or a NULL output. */
+int clb_batch_get_tile_width(clb_batch* b, int slot, int* tile_width);
+
 /* Store form of the batch's step kernels: 1 = non-temporal stores (populations written this step
  * are read next step, but at batch footprints they leave every cache before that), 0 = ordinary
  * stores.  Default (until this call or clb_batch_autotune): non-temporal once the resident lattices
  * take more than 256 MiB, and always for FP64 storage.  Results do not depend on it. */
 int clb_batch_set_nontemporal(clb_batch* b, int nontemporal);
+
+/* The store form the next grouped step uses (1 non-temporal, 0 ordinary), from
+ * clb_batch_set_nontemporal, clb_batch_autotune or the default above.  Errors: CLB_EINVAL. */
+int clb_batch_get_nontemporal(clb_batch* b, int* nontemporal);
 
 /* For each size class (ceil(log2 nx), ceil(log2 ny)) present, time the grouped step over that
  * class's lattices with each tile width, wrapped rows included (state unchanged), and keep the

@@ -308,6 +308,8 @@ _sig("clb_batch_time_steps", ctypes.c_int, [_B, ctypes.c_int, ctypes.c_longlong,
 _sig("clb_batch_set_tile_width", ctypes.c_int, [_B, ctypes.c_int, ctypes.c_int])
 _sig("clb_batch_autotune", ctypes.c_int, [_B, ctypes.c_int])
 _sig("clb_batch_set_nontemporal", ctypes.c_int, [_B, ctypes.c_int])
+_sig("clb_batch_get_tile_width", ctypes.c_int, [_B, ctypes.c_int, ctypes.POINTER(ctypes.c_int)])
+_sig("clb_batch_get_nontemporal", ctypes.c_int, [_B, ctypes.POINTER(ctypes.c_int)])
 _sig("clb_batch_info", ctypes.c_int, [_B, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t),
                                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_longlong)])
 _sig("clb_batch_synchronize", ctypes.c_int, [_B])
@@ -410,6 +412,12 @@ class Batch:
     def set_tile_width(self, slot, width):
         _check(_lib.clb_batch_set_tile_width(self._h, int(slot), int(width)))
 
+    def tile_width(self, slot):
+        """Current tile width of a slot: 64, 128, 256, or 0 for wrapped rows."""
+        v = ctypes.c_int()
+        _check(_lib.clb_batch_get_tile_width(self._h, int(slot), ctypes.byref(v)))
+        return v.value
+
     def remove(self, slot):
         _check(_lib.clb_batch_remove(self._h, int(slot)))
         self.shapes.pop(slot, None)
@@ -432,6 +440,13 @@ class Batch:
 
     def set_nontemporal(self, on):
         _check(_lib.clb_batch_set_nontemporal(self._h, int(bool(on))))
+
+    @property
+    def nontemporal(self):
+        """Store form of the next grouped step (True: non-temporal stores)."""
+        v = ctypes.c_int()
+        _check(_lib.clb_batch_get_nontemporal(self._h, ctypes.byref(v)))
+        return bool(v.value)
 
     def synchronize(self):
         _check(_lib.clb_batch_synchronize(self._h))

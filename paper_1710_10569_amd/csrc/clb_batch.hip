@@ -1043,6 +1043,17 @@ extern "C" int clb_batch_set_tile_width(clb_batch* b, int slot, int tile_width)
     return CLB_OK;
 }
 
+extern "C" int clb_batch_get_tile_width(clb_batch* b, int slot, int* tile_width)
+{
+    clear_error();
+    int rc = check_slot(b, slot);
+    if (rc) return rc;
+    if (!tile_width) { set_error("NULL argument"); return CLB_EINVAL; }
+    const int lg = b->slots[slot].tw_log2;
+    *tile_width = lg == 0 ? 0 : 1 << lg;
+    return CLB_OK;
+}
+
 // For every size class present, time the grouped step over that class's lattices with each tile
 // width (state unchanged: reads the current buffers, writes the spare ones) and keep the fastest.
 // Tile mappings and store form are timed on the two-buffer lattices only: their timing launches
@@ -1135,6 +1146,19 @@ extern "C" int clb_batch_set_nontemporal(clb_batch* b, int nontemporal)
     if (!b) { set_error("batch is NULL"); return CLB_EINVAL; }
     b->nontemporal = nontemporal != 0;
     b->nt_chosen = true;
+    return CLB_OK;
+}
+
+extern "C" int clb_batch_get_nontemporal(clb_batch* b, int* nontemporal)
+{
+    clear_error();
+    if (!b || !nontemporal) { set_error("NULL argument"); return CLB_EINVAL; }
+    if (b->dirty) {
+        // the default store form follows the resident footprint, fixed when the tables are built
+        const int rc = upload_tables(b);
+        if (rc) return rc;
+    }
+    *nontemporal = b->nontemporal ? 1 : 0;
     return CLB_OK;
 }
 

@@ -342,3 +342,21 @@ def test_in_place_lattices_in_a_batch(gpu, precision, mode):
     b.close()
     two, one = clb.footprint(300, 200, precision), clb.footprint(300, 200, precision, in_place=True)
     assert one < 0.62 * two
+
+
+def test_tile_width_and_store_form_read_back(gpu):
+    """The per-slot tile width and the batch's store form read back as set, and as the defaults
+    (width by lattice width; ordinary stores for a small FP32 batch)."""
+    clb = _clb()
+    b = clb.Batch(4, "fp32", budget_bytes=64 << 20)
+    s0 = b.add_workload(W.cavity(64, Ra=1e4))
+    s1 = b.add_workload(W.cavity(150, Ra=1e4))
+    s2 = b.add_workload(W.rayleigh_benard(300, 17, Ra=1e4))
+    assert [b.tile_width(s) for s in (s0, s1, s2)] == [64, 128, 256]
+    assert b.nontemporal is False
+    b.set_tile_width(s1, 0)
+    b.set_nontemporal(True)
+    assert b.tile_width(s1) == 0 and b.nontemporal is True
+    with pytest.raises(clb.CLBError):
+        b.tile_width(3)
+    b.close()
