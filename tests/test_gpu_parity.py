@@ -312,3 +312,41 @@ def test_degenerate_sizes(gpu, precision, shape, kinds):
     after = g.moments()
     assert all(np.array_equal(a, b) for a, b in zip(before, after))
     g.close()
+
+
+def _random_case(seed):
+    """A seeded random configuration: size, wall kinds (periodic pairs or Dirichlet/adiabatic walls,
+    respecting the minimum sizes), moving walls, buoyancy, precision, streaming form and step count."""
+    rng = np.random.default_rng(1000 + seed)
+    kinds = []
+    for axis in range(2):
+        if rng.random() < 0.3:
+            kinds += ["periodic", "periodic"]
+        else:
+            kinds += [str(rng.choice(["dirichlet", "adiabatic"])) for _ in range(2)]
+    need = [4 if "adiabatic" in kinds[2 * a:2 * a + 2] else 3 for a in range(2)]
+    nx = int(rng.integers(need[0], 200))
+    ny = int(rng.integers(need[1], 150))
+    precision = str(rng.choice(["fp64", "fp32_sr", "fp64_dev"]))
+    walled = [kinds[0] != "periodic", kinds[2] != "periodic"]
+    in_place = bool(rng.random() < 0.5) and (not walled[0] or nx >= 4) and (not walled[1] or ny >= 4)
+    w = W.random_walled(nx, ny, seed=int(rng.integers(1 << 30)), kinds=tuple(kinds),
+                        wall_u=float(rng.choice([0.0, 0.02])), g_beta=float(rng.choice([0.0, 2e-3])))
+    return w, precision, in_place, int(rng.integers(1, 61))
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_configurations(gpu, seed):
+    """24 seeded random configurations against the oracle, every node compared."""
+    clb = _clb()
+    w, precision, in_place, steps = _random_case(seed)
+    print(f"[parity] random {seed}: {w['name']} {w['edges']['west'][0]}/{w['edges']['east'][0]}/"
+          f"{w['edges']['south'][0]}/{w['edges']['north'][0]} {precision} in_place={in_place} steps={steps}", flush=True)
+    g = clb.lattice_from_workload(w, precision, in_place=in_place)
+    o = oracle_from_workload(w)
+    g.step(steps)
+    o.step(steps)
+    e = field_errors(g.moments(), o.moments(), w["T0"], w["u_scale"])
+    g.close()
+    tol = FP32_TOL if precision == "fp32_sr" else FP64_TOL
+    assert e["u"] < tol and e["T"] < tol and e["rho"] < tol, e
