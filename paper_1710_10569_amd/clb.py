@@ -12,10 +12,11 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(_HERE, "libclb.so")
+# CLB_LIBRARY selects another build of the same library (the tests load the debug variant this way)
+LIBPATH = os.environ.get("CLB_LIBRARY") or os.path.join(_HERE, "libclb.so")
 
 if not os.path.exists(LIBPATH):
-    raise ImportError(f"libclb.so is not built ({LIBPATH}); run `python -m paper_1710_10569_amd.build`")
+    raise ImportError(f"{os.path.basename(LIBPATH)} is not built ({LIBPATH}); run `python -m paper_1710_10569_amd.build`")
 
 # PyTorch ships its own HIP runtime under the same soname; load it first so that libclb binds to
 # the same runtime instance and torch streams and device memory can be handed to the library.

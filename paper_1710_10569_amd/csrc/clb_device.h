@@ -79,6 +79,29 @@ __device__ __forceinline__ T sel4(T v0, T v1, T v2, T v3, int i)
 }
 
 // ---------------------------------------------------------------------------------------------
+// Debug build only (CLB_POISON_UNKNOWN, libclb_poison.so): every population whose streaming source
+// lies outside a wall is replaced by NaN as soon as it is loaded, so that a wall step that used an
+// unknown population instead of reconstructing it would turn the node's results into NaN.
+template <typename Real>
+__device__ __forceinline__ void poison_unknown(const Geo& G, int x, int y, Real f[9], Real g[5])
+{
+#ifdef CLB_POISON_UNKNOWN
+    const bool wm = !G.perx && x == 0, wp = !G.perx && x == G.nx - 1;
+    const bool sm = !G.pery && y == 0, sp = !G.pery && y == G.ny - 1;
+    const Real nan = Real(__builtin_nan(""));
+    // direction i is unknown when its source x - e_i lies beyond a wall
+    constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const bool unknown = (ex[i] > 0 && wm) || (ex[i] < 0 && wp) || (ey[i] > 0 && sm) || (ey[i] < 0 && sp);
+        if (f && unknown) f[i] = nan;
+        if (i < 5 && unknown) g[i] = nan;
+    }
+#else
+    (void)G; (void)x; (void)y; (void)f; (void)g;
+#endif
+}
+
 // Pull: the 14 post-streaming populations of node (x, y).  Periodic directions wrap; in a
 // walled direction a source outside the domain is clamped to the edge -- the value read is then
 // meaningless and is replaced by the wall step.
@@ -106,6 +129,7 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, in
     g[2] = Real(src[rm + cc + 11 * CW]);
     g[3] = Real(src[rc + cp + 12 * CW]);
     g[4] = Real(src[rp + cc + 13 * CW]);
+    poison_unknown<Real>(G, x, y, f, g);
 }
 
 template <typename S, typename Real>
@@ -122,6 +146,7 @@ __device__ __forceinline__ void pull_g(const S* __restrict__ src, const Geo& G, 
     g[2] = Real(src[rm + cc + 11 * CW]);
     g[3] = Real(src[rc + cp + 12 * CW]);
     g[4] = Real(src[rp + cc + 13 * CW]);
+    poison_unknown<Real>(G, x, y, nullptr, g);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -138,6 +138,7 @@ __device__ __forceinline__ void load_aa(const S* __restrict__ A, const Geo& G, i
         for (int i = 0; i < 9; ++i) f[i] = Real(A[o + i * CW]);
 #pragma unroll
         for (int i = 0; i < 5; ++i) g[i] = Real(A[o + (9 + i) * CW]);
+        poison_unknown<Real>(G, x, y, f, g);
         return;
     }
     const AANbr n = aa_nbr(G, x, y);
@@ -145,6 +146,7 @@ __device__ __forceinline__ void load_aa(const S* __restrict__ A, const Geo& G, i
     for (int i = 0; i < 9; ++i) f[i] = Real(A[aa_at(n, -ex_of(i), -ey_of(i)) + opp_of(i) * CW]);
 #pragma unroll
     for (int i = 0; i < 5; ++i) g[i] = Real(A[aa_at(n, -ex_of(i), -ey_of(i)) + (9 + opp_of(i)) * CW]);
+    poison_unknown<Real>(G, x, y, f, g);
 }
 
 // Store the node's rounded post-collision values v (f* then g*) for the next time step, and copy
