@@ -294,6 +294,17 @@ size_t slot_bytes(const clb_desc& d, size_t* buf_bytes_out, size_t* band_bytes_o
 // with wrapped rows and 42 with row tiles.)
 int default_tw_log2(int nx) { return nx <= 96 ? 6 : (nx <= 192 ? 7 : 8); }
 
+// Default mapping of an in-place lattice, which the autotuner cannot time (its timing launches
+// would advance the lattice): wrapped rows when x has walls and nx is a multiple of 32 (every
+// wavefront then covers whole 32-node halves of chunks, and the two wall ends of a row share one
+// wavefront, halving the wavefronts that run the wall and snapshot branches), else 64-wide rows.
+// Measured on the 512-cavity batch (sides multiples of 32, MI355X): FP32 47.8 GLUPS wrapped, 47.5
+// with 64-wide rows, 46.3 with the two-buffer default widths; SR 44.2, 42.1 and 39.8.
+int default_tw_log2_in_place(const clb_desc& d)
+{
+    return (d.west.kind != CLB_PERIODIC && d.nx % 32 == 0) ? 0 : 6;
+}
+
 int size_class(const clb_desc& d)
 {
     int c = 0;
@@ -787,7 +798,8 @@ extern "C" int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, 
         s.snap_off = off + 2 * buf_bytes;
     }
     auto it = b->tw_by_class.find(size_class(*desc));
-    s.tw_log2 = it != b->tw_by_class.end() ? it->second : default_tw_log2(desc->nx);
+    s.tw_log2 = desc->in_place ? default_tw_log2_in_place(*desc)
+              : it != b->tw_by_class.end() ? it->second : default_tw_log2(desc->nx);
     b->slots[free_slot] = s;
     b->dirty = true;
     *slot = free_slot;

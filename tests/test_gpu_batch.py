@@ -348,15 +348,21 @@ def test_tile_width_and_store_form_read_back(gpu):
     """The per-slot tile width and the batch's store form read back as set, and as the defaults
     (width by lattice width; ordinary stores for a small FP32 batch)."""
     clb = _clb()
-    b = clb.Batch(4, "fp32", budget_bytes=64 << 20)
+    b = clb.Batch(8, "fp32", budget_bytes=64 << 20)
     s0 = b.add_workload(W.cavity(64, Ra=1e4))
     s1 = b.add_workload(W.cavity(150, Ra=1e4))
     s2 = b.add_workload(W.rayleigh_benard(300, 17, Ra=1e4))
     assert [b.tile_width(s) for s in (s0, s1, s2)] == [64, 128, 256]
+    # in-place lattices: wrapped rows when x has walls and nx is a multiple of 32, else 64-wide rows
+    ip = [b.add_workload(w, in_place=True) for w in (W.cavity(96, Ra=1e4), W.cavity(50, Ra=1e4),
+                                                     W.rayleigh_benard(320, 17, Ra=1e4))]
+    assert [b.tile_width(s) for s in ip] == [0, 64, 64]
+    for s in ip:
+        b.remove(s)
     assert b.nontemporal is False
     b.set_tile_width(s1, 0)
     b.set_nontemporal(True)
     assert b.tile_width(s1) == 0 and b.nontemporal is True
     with pytest.raises(clb.CLBError):
-        b.tile_width(3)
+        b.tile_width(7)
     b.close()
