@@ -308,9 +308,9 @@ int clb_batch_time_steps(clb_batch* b, int mode, long long n, double* ms);
 int clb_batch_set_tile_width(clb_batch* b, int slot, int tile_width);
 
 /* The lattice's current tile width (64, 128, 256, or 0 for wrapped rows), as set by
- * clb_batch_set_tile_width, clb_batch_autotune or the default: for two-buffer lattices by width (64
- * up to 96 nodes, 128 up to 192, 256 beyond); for in-place lattices, which the autotuner does not
- * time, wrapped rows when x has walls and nx is a multiple of 32, else 64.  Errors: CLB_EINVAL for an
+ * clb_batch_set_tile_width, clb_batch_autotune or the default: for two-buffer lattices 64 when x has
+ * walls, else by width (64 up to 96 nodes, 128 up to 192, 256 beyond); for in-place lattices, which
+ * the autotuner does not time, wrapped rows when x has walls and nx is a multiple of 32, else 64.  Errors: CLB_EINVAL for an
  * unused slot or a NULL output. */
 int clb_batch_get_tile_width(clb_batch* b, int slot, int* tile_width);
 

@@ -292,7 +292,15 @@ size_t slot_bytes(const clb_desc& d, size_t* buf_bytes_out, size_t* band_bytes_o
 // take the x-wall branch, but where nx is not a multiple of the 64-node chunk their wavefronts
 // straddle chunks and write partial cache lines -- 64 cavities of sides 128-512 ran at 31 GLUPS
 // with wrapped rows and 42 with row tiles.)
-int default_tw_log2(int nx) { return nx <= 96 ? 6 : (nx <= 192 ? 7 : 8); }
+// Default mapping of a two-buffer lattice until the autotuner or the caller sets one: with walls in
+// x, 64-wide rows (on 64 served-style cavities of sides 100-700, MI355X: 47.0 GLUPS FP32 and 42.4 SR
+// against 45.7 and 41.3 with the width-based choice below, which the autotuner matches or beats);
+// periodic in x, by width.
+int default_tw_log2(const clb_desc& d)
+{
+    if (d.west.kind != CLB_PERIODIC) return 6;
+    return d.nx <= 96 ? 6 : (d.nx <= 192 ? 7 : 8);
+}
 
 // Default mapping of an in-place lattice, which the autotuner cannot time (its timing launches
 // would advance the lattice): wrapped rows when x has walls and nx is a multiple of 32 (every
@@ -799,7 +807,7 @@ extern "C" int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, 
     }
     auto it = b->tw_by_class.find(size_class(*desc));
     s.tw_log2 = desc->in_place ? default_tw_log2_in_place(*desc)
-              : it != b->tw_by_class.end() ? it->second : default_tw_log2(desc->nx);
+              : it != b->tw_by_class.end() ? it->second : default_tw_log2(*desc);
     b->slots[free_slot] = s;
     b->dirty = true;
     *slot = free_slot;
