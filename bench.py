@@ -160,7 +160,7 @@ def run_batch(clb, W, steps, stream, precision="fp32", modes=("grouped", "each")
     log(f"[bench] batch {precision}: {len(specs)} cavities, {total:.4g} nodes, pool {budget / 1e9:.2f} GB, "
         f"set up in {time.perf_counter() - t0:.1f} s")
     b.step(20)
-    b.autotune(3)
+    b.autotune(10)
     torch.cuda.synchronize()
     widths = {}
     for slot, (L, _, _) in zip(slots, specs):
