@@ -196,19 +196,27 @@ def test_batch_residual_snapshot(gpu):
     assert d["dT_max"] == pytest.approx(np.abs(T2 - T1).max(), rel=1e-14)
 
 
-def test_served_result_same_alone_and_in_mix(gpu):
+@pytest.mark.parametrize("in_place", [False, True])
+def test_served_result_same_alone_and_in_mix(gpu, in_place):
     """Continuous batching: a request served alone and the same request served while others
-    arrive, run and leave gives bitwise the same fields, stopping step and Nusselt number."""
+    arrive, run and leave gives bitwise the same fields, stopping step and Nusselt number (with
+    two-buffer and with in-place streaming, which must also agree with each other)."""
     from paper_1710_10569_amd import serving as S
     mk = lambda: [S.Request(0, 0.0, 48, 2e4, 11)]
     alone_srv = S.CavityServer(budget_bytes=64 << 20, capacity=16, chunk=500, tol=1e-6, step_cap=40000,
-                               schedule="grouped", keep_fields=True)
+                               schedule="grouped", keep_fields=True, in_place=in_place)
     (a,) = alone_srv.run(mk())
     alone_srv.close()
+    if in_place:
+        ref_srv = S.CavityServer(budget_bytes=64 << 20, capacity=16, chunk=500, tol=1e-6, step_cap=40000,
+                                 schedule="grouped", keep_fields=True)
+        (r,) = ref_srv.run(mk())
+        ref_srv.close()
+        assert r.steps == a.steps and all(np.array_equal(x, y) for x, y in zip(r.fields, a.fields))
     mix = mk() + [S.Request(1, 0.0, 64, 1e5, 12), S.Request(2, 0.0, 40, 3e3, 13), S.Request(3, 0.05, 56, 5e4, 14),
                   S.Request(4, 0.1, 36, 1e3, 15)]
     mix_srv = S.CavityServer(budget_bytes=64 << 20, capacity=16, chunk=500, tol=1e-6, step_cap=40000,
-                             schedule="persistent", keep_fields=True)
+                             schedule="persistent", keep_fields=True, in_place=in_place)
     out = mix_srv.run(mix)
     mix_srv.close()
     m = next(r for r in out if r.id == 0)
