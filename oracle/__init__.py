@@ -55,6 +55,8 @@ def _load(path=None):
     lib.orc_moments.restype = ctypes.c_int
     lib.orc_get_state.argtypes = [vp, _dp, _dp]
     lib.orc_set_state.argtypes = [vp, _dp, _dp]
+    lib.orc_get_outgoing.argtypes = [vp, _dp]
+    lib.orc_set_outgoing.argtypes = [vp, _dp]
     lib.orc_threads.restype = ctypes.c_int
     lib.orc_matrix_M.argtypes = [_dp]
     lib.orc_matrix_N.argtypes = [ctypes.c_double, ctypes.c_double, _dp]
@@ -184,6 +186,17 @@ class OracleLattice:
         f = _f64(f).reshape(9, self.ny, self.nx)
         g = _f64(g).reshape(5, self.ny, self.nx)
         self._lib.orc_set_state(self._h, _ptr(f), _ptr(g))
+
+    def get_outgoing(self):
+        """out[9][ny][nx]: the flow populations f*_k that wall nodes sent out of the domain in the
+        last step (entry k of a node is defined where x + e_k lies beyond a wall)."""
+        out = np.empty((9, self.ny, self.nx))
+        self._lib.orc_get_outgoing(self._h, _ptr(out))
+        return out
+
+    def set_outgoing(self, out):
+        out = _f64(out).reshape(9, self.ny, self.nx)
+        self._lib.orc_set_outgoing(self._h, _ptr(out))
 
     # -- single-node algebra (for the algebra tests) ------------------------------------------
     def matrix_Minv(self):

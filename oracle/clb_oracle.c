@@ -30,7 +30,19 @@
  *   - Walls sit on nodes.  A population is unknown at a wall node when its streaming source lies
  *     outside the domain; those are marked NaN in the state and must be replaced by the wall step.
  *   - Wall step order at a wall node: temperature NEE first (all five g), then the force from the
- *     wall temperature, then the flow: force-corrected Zou-He on edges, NEE on corners.
+ *     wall temperature, then the flow: force-corrected Zou-He on edges, non-equilibrium bounce-back
+ *     of the opposite pairs at corners.
+ *   - Density of a wall node.  Zou-He's own density (from the normal momentum constraint) does not
+ *     conserve mass: along a wall the nodes exchange mass with the fluid, and in a closed buoyant
+ *     cavity the corners and edges leave a net loss at every step, so no steady state exists.  A
+ *     wall node whose wall is impermeable (u_w.n = 0; every corner) therefore takes as its density
+ *     the mass it holds after streaming plus the mass it sent out of the domain the step before,
+ *     rho_b = sum_known f_i(t) + sum_k f*_k(t-1) (k: directions leaving the domain), so the node
+ *     exchanges no mass with the outside.  The unknown populations still satisfy Zou-He's
+ *     constraints (sum f e = rho_b u_w - F/2, so Eq. 13 returns u_w) and the rest population f_0
+ *     takes up the difference, f_0 = rho_b - sum_{i>0} f_i.  For a stationary wall the unknowns do
+ *     not depend on rho_b, so only f_0 differs from plain Zou-He.  Permeable walls keep Zou-He's
+ *     density: mass flows through them.
  *   - Adiabatic walls: T_b = (4 T(x_f) - T(x_ff)) / 3 (second-order zero normal gradient).
  *   - Corners: the inner neighbour is the diagonal one; for temperature a Dirichlet wall wins over
  *     an adiabatic one, and between two walls of the same kind the west/east wall's data is used;
@@ -38,12 +50,15 @@
  *
  * Parity unpinned: no printed value, closed form or invariant fixes these choices, so they hold only
  * as readings, shared by construction with the GPU library: the default s_b = 1, the corner data
- * (which wall's velocity and temperature a corner takes, and the diagonal extrapolation) and the
- * wall velocity of the temperature-only mode.
+ * (which wall's velocity and temperature a corner takes, the diagonal temperature extrapolation and
+ * the split of a corner's unknowns) and the wall velocity of the temperature-only mode.  The wall
+ * density is pinned by exact mass conservation in closed domains and by the steady state it allows.
  *
  * State convention: the arrays f[9][n] and g[5][n] hold the populations of time t after streaming
  * and before the wall step ("state(t)").  One step = wall step -> macroscopic -> collision ->
- * streaming (push) -> state(t+1).  Node (x, y) has index y*nx + x.
+ * streaming (push) -> state(t+1).  Node (x, y) has index y*nx + x.  The array out[9][n] holds the
+ * flow populations f*_k that wall nodes sent out of the domain in the last step (entry k of node x
+ * defined where x + e_k lies beyond a wall); it is part of the state.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -55,6 +70,7 @@
 /* ---- Eq. 4: the D2Q9 velocity set; its first five vectors are the D2Q5 set (Sec. 2.2) ---- */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};   /* e_OPP[i] = -e_i */
 
 #define CS2 (1.0 / 3.0)   /* c_s^2 of the D2Q9 lattice (after Eq. 9) */
 #define CT2 (1.0 / 4.0)   /* c_{T,s}^2 of the D2Q5 lattice (Sec. 3 default c_sT = 1/2) */
@@ -75,6 +91,7 @@ typedef struct {
     double pux, puy;            /* the given velocity */
     double *f, *g;              /* state(t) */
     double *fn, *gn;            /* next state */
+    double *out;                /* f*_k sent out of the domain by wall nodes in the last step */
     double Minv[81], MTinv[25];
     int bad;                    /* set when a NaN survives the wall step */
 } orc_lattice;
@@ -329,27 +346,41 @@ static int dir_of(int ex, int ey)
  * frame: n is the inward unit normal, t the tangent with (t, n) a right-handed pair.  The three
  * populations with e.n = +1 are unknown.  The closure bounces back the non-equilibrium part of the
  * normal population, f(0,+1) - f(0,-1) = f^eq(0,+1) - f^eq(0,-1) at (rho, u_w), and fixes the two
- * diagonal ones so that sum f = rho and sum f e = rho u_w - F/2, which makes Eq. 13 return u_w. */
-static void zou_he(double* f, int nx_, int ny_, double uwx, double uwy, double Fx, double Fy)
+ * diagonal ones so that sum f e = rho u_w - F/2, which makes Eq. 13 return u_w.
+ *
+ * zou_he_density: Zou-He's own density, the one for which in addition sum f = rho:
+ * rho = (sum_{b=0} f + 2 sum_{b=-1} f - F_n/2) / (1 - u_n).
+ * zou_he: the three unknowns for a given density rho. */
+static double zou_he_density(const double* f, int nx_, int ny_, double uwx, double uwy, double Fx, double Fy)
 {
     const int tx = ny_, ty = -nx_;          /* t = n rotated by -90 degrees */
 #define D(a, b) dir_of((a) * tx + (b) * nx_, (a) * ty + (b) * ny_)
-    const int c00 = D(0, 0), cp0 = D(1, 0), cm0 = D(-1, 0);
+    const double K0 = f[D(0, 0)] + f[D(1, 0)] + f[D(-1, 0)];
+    const double Km = f[D(0, -1)] + f[D(1, -1)] + f[D(-1, -1)];
+#undef D
+    const double un = uwx * nx_ + uwy * ny_;
+    const double Fn = Fx * nx_ + Fy * ny_;
+    return (K0 + 2.0 * Km - 0.5 * Fn) / (1.0 - un);
+}
+
+static void zou_he(double* f, int nx_, int ny_, double uwx, double uwy, double Fx, double Fy, double rho)
+{
+    const int tx = ny_, ty = -nx_;          /* t = n rotated by -90 degrees */
+#define D(a, b) dir_of((a) * tx + (b) * nx_, (a) * ty + (b) * ny_)
+    const int cp0 = D(1, 0), cm0 = D(-1, 0);
     const int c0m = D(0, -1), cpm = D(1, -1), cmm = D(-1, -1);
     const int c0p = D(0, 1), cpp = D(1, 1), cmp = D(-1, 1);
 #undef D
     const double un = uwx * nx_ + uwy * ny_, ut = uwx * tx + uwy * ty;
     const double Fn = Fx * nx_ + Fy * ny_, Ft = Fx * tx + Fy * ty;
-    const double K0 = f[c00] + f[cp0] + f[cm0];
-    const double Km = f[c0m] + f[cpm] + f[cmm];
-    const double rho = (K0 + 2.0 * Km - 0.5 * Fn) / (1.0 - un);
     const double Dn = rho * un * (2.0 / 3.0 - ut * ut);
     f[c0p] = f[c0m] + Dn;
     f[cpp] = f[cmm] - 0.5 * (f[cp0] - f[cm0]) + 0.5 * (rho * ut - 0.5 * Ft) + 0.5 * (rho * un - 0.5 * Fn - Dn);
     f[cmp] = f[cpm] + 0.5 * (f[cp0] - f[cm0]) - 0.5 * (rho * ut - 0.5 * Ft) + 0.5 * (rho * un - 0.5 * Fn - Dn);
 }
 
-/* Wall step at node (x, y): replaces the unknown populations of f and all of g in place. */
+/* Wall step at node (x, y): replaces the unknown populations of f (and, on impermeable walls,
+ * the rest population f_0) and all of g in place. */
 static void wall_step(const orc_lattice* L, int x, int y, double* f, double* g)
 {
     const int onW = L->kind[WEST] != W_PERIODIC && x == 0;
@@ -398,17 +429,41 @@ static void wall_step(const orc_lattice* L, int x, int y, double* f, double* g)
     double Fxb, Fyb;
     force_of(L, Tb, &Fxb, &Fyb);
 
-    if (!corner) {
-        /* (1c) Zou-He on the edge; the inward normal is (dx, dy). */
-        zou_he(f, dx, dy, uwx, uwy, Fxb, Fyb);
+    /* (1c) density of the wall node.  Unknown populations are the NaN entries of state(t); the
+     * populations the node sent out of the domain last step are out[opp(i)] for those i. */
+    const int n = L->nx * L->ny, k = idx_of(L, x, y);
+    const int impermeable = corner || (uwx * dx + uwy * dy == 0.0);
+    int unknown[9];
+    double rho_b;
+    for (int i = 0; i < 9; ++i) unknown[i] = isnan(f[i]);
+    if (impermeable) {
+        rho_b = 0.0;
+        for (int i = 0; i < 9; ++i) rho_b += unknown[i] ? L->out[OPP[i] * n + k] : f[i];
     } else {
-        /* (1d) corner: non-equilibrium extrapolation from the diagonal neighbour, with that
-         * neighbour's density; the equilibrium velocities are those that make Eq. 13 return
-         * u_w at the corner and u_f at the neighbour. */
-        double fb[9], fe[9];
-        feq9(L, rf, uwx - 0.5 * Fxb / rf, uwy - 0.5 * Fyb / rf, fb);
-        feq9(L, rf, uxf - 0.5 * Fxf / rf, uyf - 0.5 * Fyf / rf, fe);
-        for (int i = 0; i < 9; ++i) f[i] = fb[i] + (ff[i] - fe[i]);
+        rho_b = zou_he_density(f, dx, dy, uwx, uwy, Fxb, Fyb);
+    }
+
+    if (!corner) {
+        /* (1d) Zou-He on the edge; the inward normal is (dx, dy). */
+        zou_he(f, dx, dy, uwx, uwy, Fxb, Fyb, rho_b);
+    } else {
+        /* (1d) corner: five unknowns.  Those whose opposite is known bounce back the opposite's
+         * non-equilibrium part, f_i = f_opp(i) + f_i^eq - f_opp(i)^eq; the two whose opposite is
+         * unknown too (they point along the diagonal the corner cuts off) take f_i^eq.  The
+         * equilibrium is at (rho_b, u_w - F_b/(2 rho_b)), whose first moment is rho_b u_w - F_b/2,
+         * so Eq. 13 returns u_w at the corner. */
+        double fe[9];
+        feq9(L, rho_b, uwx - 0.5 * Fxb / rho_b, uwy - 0.5 * Fyb / rho_b, fe);
+        for (int i = 1; i < 9; ++i) {
+            if (!unknown[i]) continue;
+            f[i] = unknown[OPP[i]] ? fe[i] : f[OPP[i]] + (fe[i] - fe[OPP[i]]);
+        }
+    }
+    if (impermeable) {
+        /* (1e) the rest population carries the mass balance: sum f = rho_b. */
+        double s = 0.0;
+        for (int i = 1; i < 9; ++i) s += f[i];
+        f[0] = rho_b - s;
     }
 }
 
@@ -464,10 +519,12 @@ orc_lattice* orc_create(int nx, int ny, const int* kind, const double* uw, const
     L->fn = (double*)malloc(9 * n * sizeof(double));
     L->g = (double*)malloc(5 * n * sizeof(double));
     L->gn = (double*)malloc(5 * n * sizeof(double));
-    if (!L->f || !L->fn || !L->g || !L->gn || invert(9, M9, L->Minv) || invert(5, M5, L->MTinv)) {
-        free(L->f); free(L->fn); free(L->g); free(L->gn); free(L);
+    L->out = (double*)malloc(9 * n * sizeof(double));
+    if (!L->f || !L->fn || !L->g || !L->gn || !L->out || invert(9, M9, L->Minv) || invert(5, M5, L->MTinv)) {
+        free(L->f); free(L->fn); free(L->g); free(L->gn); free(L->out); free(L);
         return NULL;
     }
+    for (size_t i = 0; i < 9 * n; ++i) L->out[i] = NAN;
     for (size_t i = 0; i < 9 * n; ++i) L->f[i] = NAN;
     for (size_t i = 0; i < 5 * n; ++i) L->g[i] = NAN;
     return L;
@@ -476,7 +533,7 @@ orc_lattice* orc_create(int nx, int ny, const int* kind, const double* uw, const
 void orc_destroy(orc_lattice* L)
 {
     if (!L) return;
-    free(L->f); free(L->fn); free(L->g); free(L->gn);
+    free(L->f); free(L->fn); free(L->g); free(L->gn); free(L->out);
     free(L);
 }
 
@@ -502,7 +559,10 @@ void orc_set_prescribed_velocity(orc_lattice* L, int on, double ux, double uy)
 }
 
 /* Initial state: g = g^eq(T, u0), f = f^eq(rho0, u0 - F/(2 rho0)) with F from T (Eq. 3), so that
- * Eq. 13 returns (rho0, u0) and Eq. 23 returns T.  NULL arrays mean rho = 1, u = 0, T = T0. */
+ * Eq. 13 returns (rho0, u0) and Eq. 23 returns T.  NULL arrays mean rho = 1, u = 0, T = T0.
+ * The outgoing populations of the step before t = 0 are taken as the initial values of the
+ * unknown populations they pair with, out[opp(i)] = f_i, so that a wall node's mass balance
+ * returns rho0. */
 void orc_init(orc_lattice* L, const double* rho, const double* ux, const double* uy, const double* T)
 {
     const int n = L->nx * L->ny;
@@ -517,6 +577,7 @@ void orc_init(orc_lattice* L, const double* rho, const double* ux, const double*
         geq5(L, t, u, v, ge);
         for (int i = 0; i < 9; ++i) L->f[i * n + k] = fe[i];
         for (int i = 0; i < 5; ++i) L->g[i * n + k] = ge[i];
+        for (int i = 0; i < 9; ++i) L->out[OPP[i] * n + k] = fe[i];
     }
     L->bad = 0;
 }
@@ -541,7 +602,10 @@ int orc_step(orc_lattice* L, long long nsteps)
                     int tx = x + EX[i], ty = y + EY[i];
                     if (L->kind[WEST] == W_PERIODIC) tx = (tx + nx) % nx;
                     if (L->kind[SOUTH] == W_PERIODIC) ty = (ty + ny) % ny;
-                    if (tx < 0 || tx >= nx || ty < 0 || ty >= ny) continue;
+                    if (tx < 0 || tx >= nx || ty < 0 || ty >= ny) {
+                        if (!L->prescribed) L->out[i * n + y * nx + x] = fp[i];
+                        continue;
+                    }
                     const int t = ty * nx + tx;
                     if (!L->prescribed) L->fn[i * n + t] = fp[i];
                     if (i < 5) L->gn[i * n + t] = gp[i];
@@ -586,6 +650,17 @@ void orc_set_state(orc_lattice* L, const double* f, const double* g)
     if (f) memcpy(L->f, f, 9 * n * sizeof(double));
     if (g) memcpy(L->g, g, 5 * n * sizeof(double));
     L->bad = 0;
+}
+
+/* Copy out / in the outgoing populations out[9][ny][nx] (see the state convention). */
+void orc_get_outgoing(const orc_lattice* L, double* out)
+{
+    memcpy(out, L->out, 9 * (size_t)L->nx * L->ny * sizeof(double));
+}
+
+void orc_set_outgoing(orc_lattice* L, const double* out)
+{
+    memcpy(L->out, out, 9 * (size_t)L->nx * L->ny * sizeof(double));
 }
 
 /* ---- single-node access for the algebra tests ---- */
@@ -640,8 +715,8 @@ void orc_collide5(const orc_lattice* L, const double* g, double ux, double uy, d
     collide5(L, g, T, ux, uy, out);
 }
 
-/* Zou-He closure alone, for the closure tests: inward normal (nx_, ny_). */
+/* Zou-He closure alone, for the closure tests: inward normal (nx_, ny_), Zou-He's own density. */
 void orc_zou_he(double* f, int nx_, int ny_, double uwx, double uwy, double Fx, double Fy)
 {
-    zou_he(f, nx_, ny_, uwx, uwy, Fx, Fy);
+    zou_he(f, nx_, ny_, uwx, uwy, Fx, Fy, zou_he_density(f, nx_, ny_, uwx, uwy, Fx, Fy));
 }

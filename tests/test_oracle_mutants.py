@@ -26,6 +26,13 @@ MUTANTS = [
      "+ 0.5 * (rho * ut + 0.5 * Ft) + 0.5 * (rho * un - 0.5 * Fn - Dn);", "poiseuille"),
     ("adiabatic_first_order", "Tb = (4.0 * Tf - Tff) / 3.0;", "Tb = Tf;", "adiabatic"),
     ("streaming_reversed", "int tx = x + EX[i], ty = y + EY[i];", "int tx = x - EX[i], ty = y - EY[i];", "walls"),
+    ("wall_rest_population_not_rebalanced", "f[0] = rho_b - s;", "f[0] += 0.0 * s;", "mass"),
+    ("outgoing_not_paired_with_opposite", "rho_b += unknown[i] ? L->out[OPP[i] * n + k] : f[i];",
+     "rho_b += unknown[i] ? L->out[i * n + k] : f[i];", "mass"),
+    ("zou_he_density_on_closed_walls", "const int impermeable = corner || (uwx * dx + uwy * dy == 0.0);",
+     "const int impermeable = corner;", "mass"),
+    ("corner_bounce_back_sign", "f[i] = unknown[OPP[i]] ? fe[i] : f[OPP[i]] + (fe[i] - fe[OPP[i]]);",
+     "f[i] = unknown[OPP[i]] ? fe[i] : f[OPP[i]] - (fe[i] - fe[OPP[i]]);", "corners"),
 ]
 
 
@@ -136,7 +143,26 @@ def pin_adiabatic():
     return abs(_neumann_mode_rate_error(32)) < 5e-5
 
 
-PINS = {"adiabatic": pin_adiabatic, "shear": pin_shear, "moments": pin_moments, "forcing": pin_forcing, "decay": pin_decay, "poiseuille": pin_poiseuille,
+def pin_mass():
+    """A closed buoyant cavity keeps its mass to rounding."""
+    lat = oracle_from_workload(W.cavity(16, Ra=1e4, seed=11))
+    m0 = lat.moments()[0].sum()
+    lat.step(2000)
+    return abs(lat.moments()[0].sum() - m0) / m0 < 1e-13
+
+
+def pin_corners():
+    """Eq. 13 returns the wall velocity at the corners (moving walls, buoyancy)."""
+    w = W.random_walled(12, 10, seed=5, wall_u=0.02)
+    lat = oracle_from_workload(w)
+    lat.step(9)
+    _, ux, uy, _ = lat.moments()
+    e = w["edges"]
+    return all(abs(ux[j, i] - e[nm][1]) < 1e-14 and abs(uy[j, i] - e[nm][2]) < 1e-14
+               for (j, i, nm) in ((0, 0, "west"), (-1, 0, "west"), (0, -1, "east"), (-1, -1, "east")))
+
+
+PINS = {"mass": pin_mass, "corners": pin_corners, "adiabatic": pin_adiabatic, "shear": pin_shear, "moments": pin_moments, "forcing": pin_forcing, "decay": pin_decay, "poiseuille": pin_poiseuille,
         "walls": pin_walls}
 
 
