@@ -429,13 +429,16 @@ static void wall_step(const orc_lattice* L, int x, int y, double* f, double* g)
     double Fxb, Fyb;
     force_of(L, Tb, &Fxb, &Fyb);
 
-    /* (1c) density of the wall node.  Unknown populations are the NaN entries of state(t); the
-     * populations the node sent out of the domain last step are out[opp(i)] for those i. */
+    /* (1c) density of the wall node.  Population i is unknown when its source x - e_i lies beyond
+     * a wall (after streaming those entries of state(t) are NaN; the initial state holds values
+     * there, which the wall step replaces all the same); the populations the node sent out of the
+     * domain last step are out[opp(i)] for those i. */
     const int n = L->nx * L->ny, k = idx_of(L, x, y);
     const int impermeable = corner || (uwx * dx + uwy * dy == 0.0);
     int unknown[9];
     double rho_b;
-    for (int i = 0; i < 9; ++i) unknown[i] = isnan(f[i]);
+    for (int i = 0; i < 9; ++i)
+        unknown[i] = (onW && EX[i] > 0) || (onE && EX[i] < 0) || (onS && EY[i] > 0) || (onN && EY[i] < 0);
     if (impermeable) {
         rho_b = 0.0;
         for (int i = 0; i < 9; ++i) rho_b += unknown[i] ? L->out[OPP[i] * n + k] : f[i];
