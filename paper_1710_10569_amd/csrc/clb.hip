@@ -99,6 +99,9 @@ Geo make_geo(const clb_desc& d)
     G.kind[1] = d.east.kind;
     G.kind[2] = d.south.kind;
     G.kind[3] = d.north.kind;
+    // a wall is permeable when its velocity has a component along its normal
+    G.perm = (d.west.kind != CLB_PERIODIC && d.west.ux != 0.0 ? 1 : 0) | (d.east.kind != CLB_PERIODIC && d.east.ux != 0.0 ? 2 : 0) |
+             (d.south.kind != CLB_PERIODIC && d.south.uy != 0.0 ? 4 : 0) | (d.north.kind != CLB_PERIODIC && d.north.uy != 0.0 ? 8 : 0);
     return G;
 }
 

@@ -45,11 +45,17 @@ __global__ void init_kernel(S* __restrict__ buf, Geo G, const double* __restrict
     const double Fx = Fvx, Fy = Fvy + g_beta * (T - T0);
     const double vx = ux - 0.5 * Fx / rho, vy = uy - 0.5 * Fy / rho;
     for (int i = 0; i < 9; ++i) {
-        // f_i(x) is read by the next pull from the node x - e_i... so store at the source of x.
+        // f_i(x) is read by the next pull from the node x - e_i... so store at the source of x.  An
+        // unknown f_i (source beyond a wall) is stored in slot opp(i) of x itself, where the wall
+        // step's mass balance reads what x sent out of the domain the step before: the initial
+        // unknowns stand for it, so the balance returns rho at t = 0.
         int sx, sy;
-        if (!source_of(G, x, y, i, sx, sy)) continue;
         double v = rho * psi(EXd[i], vx) * psi(EYd[i], vy);
         if (DEV) v -= W9[i];
+        if (!source_of(G, x, y, i, sx, sy)) {
+            buf[pop_at(G, x, y) + opp_of(i) * CW] = S(v);
+            continue;
+        }
         buf[pop_at(G, sx, sy) + i * CW] = S(v);
     }
     const double gq[5] = {T * (0.5 - ux * ux - uy * uy), 0.5 * T * (0.25 + ux + ux * ux),
@@ -150,7 +156,7 @@ __global__ __launch_bounds__(TX * TY) void moments_aa_kernel(const S* __restrict
     if (x >= G.nx || y >= G.ny) return;
     Real f[9], g[5];
     load_aa<S, Real, ODD>(A, G, x, y, f, g);
-    if (on_wall(G, x, y)) wall_step_nb<Real, DEV>(SnapSource<S>{snow}, G, P, x, y, f, g);
+    if (on_wall(G, x, y)) wall_step_nb<Real, DEV>(SnapSource<S>{snow, A}, G, P, x, y, f, g);
     const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
     const long long n = (long long)G.nx * G.ny;
     const long long k = (long long)y * G.nx + x;

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(BNT) void batch_residual_kernel(S* __restrict__ poo
             if (odd) load_aa<S, Real, true>(A, E.L.G, x, y, f, g);
             else load_aa<S, Real, false>(A, E.L.G, x, y, f, g);
             if (on_wall(E.L.G, x, y))
-                wall_step_nb<Real, DEV>(SnapSource<S>{pool + (odd ? E.L.sn[1] : E.L.sn[0])}, E.L.G, E.P, x, y, f, g);
+                wall_step_nb<Real, DEV>(SnapSource<S>{pool + (odd ? E.L.sn[1] : E.L.sn[0]), A}, E.L.G, E.P, x, y, f, g);
         } else {
             const S* src = pool + (E.L.cur ? E.L.off[1] : E.L.off[0]);
             pull(src, E.L.G, x, y, f, g);

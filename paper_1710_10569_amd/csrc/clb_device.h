@@ -41,6 +41,7 @@ struct Geo {
     int row;             // elements per row: ceil(nx / CW) chunks of 14 * CW
     int perx, pery;      // 1 if the x (resp. y) direction is periodic
     int kind[4];         // W, E, S, N
+    int perm;            // bit w set: wall w is permeable (its velocity has a normal component)
 };
 
 // Chunk width (nodes) and chunk size (elements) of the storage layout.
@@ -242,8 +243,22 @@ __device__ __forceinline__ Real at(const Real f[9], int k)
 __host__ __device__ constexpr int zb(int k, int i) { return ex_of(i) * znx(k) + ey_of(i) * zny(k); }
 __host__ __device__ constexpr int za(int k, int i) { return ex_of(i) * zny(k) - ey_of(i) * znx(k); }
 
+// zou_he_density: Zou-He's own density, for which also sum f = rho (used on permeable walls);
+// zou_he: the three unknowns for a given density rho.
 template <typename Real, bool DEV>
-__device__ __forceinline__ void zou_he(Real f[9], int nx, int ny, Real uwx, Real uwy, Real Fx, Real Fy)
+__device__ __forceinline__ Real zou_he_density(const Real f[9], int nx, int ny, Real uwx, Real uwy, Real Fx, Real Fy)
+{
+    const int k = nx == 1 ? 0 : (nx == -1 ? 1 : (ny == 1 ? 2 : 3));
+    const Real un = uwx * Real(nx) + uwy * Real(ny);
+    const Real Fn = Fx * Real(nx) + Fy * Real(ny);
+    const Real K0 = (f[0] + at<1, 0>(f, k)) + at<-1, 0>(f, k);
+    const Real Km = (at<0, -1>(f, k) + at<1, -1>(f, k)) + at<-1, -1>(f, k);
+    // the rest weights over b = 0 plus twice those over b = -1 sum to 1
+    return ((DEV ? Real(1) : Real(0)) + K0 + Real(2) * Km - Real(0.5) * Fn) / (Real(1) - un);
+}
+
+template <typename Real, bool DEV>
+__device__ __forceinline__ void zou_he(Real f[9], int nx, int ny, Real uwx, Real uwy, Real Fx, Real Fy, Real rho)
 {
     const int k = nx == 1 ? 0 : (nx == -1 ? 1 : (ny == 1 ? 2 : 3));
     const Real tx = Real(ny), ty = Real(-nx);
@@ -253,11 +268,7 @@ __device__ __forceinline__ void zou_he(Real f[9], int nx, int ny, Real uwx, Real
     const Real Ft = Fx * tx + Fy * ty;
     const Real fP0 = at<1, 0>(f, k), fM0 = at<-1, 0>(f, k);
     const Real fZM = at<0, -1>(f, k), fPM = at<1, -1>(f, k), fMM = at<-1, -1>(f, k);
-    const Real K0 = (f[0] + fP0) + fM0;
-    const Real Km = (fZM + fPM) + fMM;
     const Real d0 = fP0 - fM0;
-    // the rest weights over b = 0 plus twice those over b = -1 sum to 1
-    const Real rho = ((DEV ? Real(1) : Real(0)) + K0 + Real(2) * Km - Real(0.5) * Fn) / (Real(1) - un);
     const Real D = rho * un * (Real(2.0 / 3.0) - ut * ut);
     const Real half_t = Real(0.5) * (rho * ut - Real(0.5) * Ft);
     const Real half_n = Real(0.5) * (rho * un - Real(0.5) * Fn - D);
@@ -273,6 +284,26 @@ __device__ __forceinline__ void zou_he(Real f[9], int nx, int ny, Real uwx, Real
         const Real v3 = zb(3, i) == 1 ? (za(3, i) == 0 ? nZP : (za(3, i) == 1 ? nPP : nMP)) : f[i];
         f[i] = sel4(v0, v1, v2, v3, k);
     }
+}
+
+// Corner closure terms for direction (EX, EY) of the product-form equilibrium at velocity v, per unit
+// density, formed without cancellation: odd = psi psi_i - psi psi_opp(i), and dev = psi psi_i - w_i
+// (w_i = psi psi_i at v = 0).  With psi(e, v) = psi(e, 0) + dpsi(e, v), dpsi(0, v) = -v^2 and
+// dpsi(+-1, v) = (+-v + v^2)/2; psi(1, v) - psi(-1, v) = v and psi(1, v) + psi(-1, v) = 1/3 + v^2.
+template <int EX, int EY, typename Real>
+__device__ __forceinline__ Real feq_odd(Real vx, Real vy)
+{
+    if constexpr (EY == 0) return Real(EX) * vx * (Real(2.0 / 3.0) - vy * vy);
+    else if constexpr (EX == 0) return Real(EY) * vy * (Real(2.0 / 3.0) - vx * vx);
+    else return Real(0.5) * (Real(EX) * vx * (Real(1.0 / 3.0) + vy * vy) + Real(EY) * vy * (Real(1.0 / 3.0) + vx * vx));
+}
+template <int EX, int EY, typename Real>
+__device__ __forceinline__ Real feq_dev(Real vx, Real vy)
+{
+    const Real ax = EX == 0 ? Real(2.0 / 3.0) : Real(1.0 / 6.0), ay = EY == 0 ? Real(2.0 / 3.0) : Real(1.0 / 6.0);
+    const Real bx = EX == 0 ? -vx * vx : Real(0.5) * (Real(EX) * vx + vx * vx);
+    const Real by = EY == 0 ? -vy * vy : Real(0.5) * (Real(EY) * vy + vy * vy);
+    return (ax * by + bx * ay) + bx * by;
 }
 
 // Temperature non-equilibrium extrapolation: g_i = g^eq_i(T_b, a) + g_i(x_f) - g^eq_i(T_f, b) with
@@ -301,12 +332,20 @@ __device__ __forceinline__ void nee_g(Real g[5], const Real gf[5], Real dTbf, Re
 //      g_i = g_i^eq(T_b, u_w) + g_i(x_f) - g_i^eq(T_f, u_f), T_b = T_w (Dirichlet) or
 //      (4 T_f - T_ff)/3 (adiabatic; x_ff the second inner node).
 //   2. F at the node from T_b.
-//   3. f: Zou-He on edges; at corners non-equilibrium extrapolation from x_f with x_f's density,
-//      at the equilibrium velocities u_w - F_b/(2 rho_f) and u_f - F_f/(2 rho_f).
+//   3. Density rho_b.  On an impermeable wall (u_w.n = 0) and at every corner: the node's mass
+//      balance, the known populations plus those the node sent out of the domain the step before
+//      (f*_opp(i) for each unknown i), so the node exchanges no mass with the outside; on a
+//      permeable wall: Zou-He's own density.
+//   4. f: Zou-He's unknowns at rho_b on edges; at corners the unknowns whose opposite is known
+//      bounce back its non-equilibrium part, f_i = f_opp(i) + f^eq_i - f^eq_opp(i), and the two along
+//      the cut-off diagonal take f^eq_i, all at (rho_b, u_w - F_b/(2 rho_b)), so Eq. 13 returns u_w.
+//   5. Impermeable: f_0 = rho_b - sum_{i>0} f_i.
 // Corner data: velocity of the west/east wall; temperature of a Dirichlet wall if one meets
 // there, the west/east wall's otherwise.
-// Post-streaming populations of a node other than the one being updated (the wall step's inner
-// neighbours), read by pull from the previous step's buffer.
+//
+// Sources of the wall step's other inputs.  PullSource: two-buffer streaming; the inner
+// neighbours' post-streaming populations by pull from the previous step's buffer, and the node's
+// own outgoing populations from its own slots of that buffer (f*_k(x) is stored at x, slot k).
 template <typename S>
 struct PullSource {
     const S* src;
@@ -314,6 +353,13 @@ struct PullSource {
     __device__ __forceinline__ void all(const Geo& G, int x, int y, Real f[9], Real g[5]) const { pull(src, G, x, y, f, g); }
     template <typename Real>
     __device__ __forceinline__ void temp(const Geo& G, int x, int y, Real g[5]) const { pull_g(src, G, x, y, g); }
+    // f*_opp(i)(x) of the previous step (i = 1..8): the population that left the domain where
+    // the unknown f_i enters
+    template <typename Real>
+    __device__ __forceinline__ Real bounced(const Geo& G, int x, int y, int i) const
+    {
+        return Real(src[pop_at(G, x, y) + (i == 1 ? 3 : i == 2 ? 4 : i == 3 ? 1 : i == 4 ? 2 : i == 5 ? 7 : i == 6 ? 8 : i == 7 ? 5 : 6) * CW]);
+    }
 };
 
 template <typename Real, bool DEV, typename NB>
@@ -352,16 +398,63 @@ __device__ __forceinline__ void wall_step_nb(const NB& nb, const Geo& G, const P
     const Real Fxb = P.Fvx;
     const Real Fyb = P.Fvy + P.g_beta * (dTb + P.Toff);
 
-    if (!corner) {
-        zou_he<Real, DEV>(f, dx, dy, uwx, uwy, Fxb, Fyb);
-    } else {
-        const Real ir = Real(1) / mf.rho;
-        Real d[9];
-        feq_diff(uwx - Real(0.5) * Fxb * ir, uwy - Real(0.5) * Fyb * ir,
-                 mf.ux - Real(0.5) * mf.Fx * ir, mf.uy - Real(0.5) * mf.Fy * ir, d);
+    // unknown directions: source x - e_i beyond a wall
+    bool unk[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = ff[i] + mf.rho * d[i];
+    for (int i = 0; i < 9; ++i)
+        unk[i] = (ex_of(i) > 0 && onW) || (ex_of(i) < 0 && onE) || (ey_of(i) > 0 && onS) || (ey_of(i) < 0 && onN);
+    const Real R0 = DEV ? Real(1) : Real(0);
+    const bool imperm = corner || ((G.perm >> vw) & 1) == 0;
+    Real dr;   // rho_b - R0
+    if (imperm) {
+        dr = f[0];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            if (unk[i]) dr += nb.template bounced<Real>(G, x, y, i);
+            else dr += f[i];
+        }
+    } else {
+        dr = zou_he_density<Real, DEV>(f, dx, dy, uwx, uwy, Fxb, Fyb) - R0;
     }
+    const Real rho = R0 + dr;
+
+    if (!corner) {
+        zou_he<Real, DEV>(f, dx, dy, uwx, uwy, Fxb, Fyb, rho);
+    } else {
+        const Real ir = Real(1) / rho;
+        const Real vx = uwx - Real(0.5) * Fxb * ir, vy = uwy - Real(0.5) * Fyb * ir;
+        // one of each opposite pair on the axes is unknown: bounce back the other's
+        // non-equilibrium part (the odd parts of directions 3, 4 are those of 1, 2 negated)
+        const Real o1 = rho * feq_odd<1, 0>(vx, vy), o2 = rho * feq_odd<0, 1>(vx, vy);
+        f[1] = unk[1] ? f[3] + o1 : f[1];
+        f[3] = unk[3] ? f[1] - o1 : f[3];
+        f[2] = unk[2] ? f[4] + o2 : f[2];
+        f[4] = unk[4] ? f[2] - o2 : f[4];
+        // diagonals: the cut-off one is (-1, 1)/(1, -1) at the south-west and north-east corners
+        // (anti), else (1, 1)/(-1, -1); its two populations take f^eq, the other pair bounces back
+        const bool anti = dx == dy;
+        const Real sx = anti ? Real(-1) : Real(1);
+        // cut-off diagonal (sx, 1) and (-sx, -1): equilibrium deviations from the rest weight 1/36
+        const Real ax = Real(1.0 / 6.0), bpx = Real(0.5) * (sx * vx + vx * vx), bmx = Real(0.5) * (-sx * vx + vx * vx);
+        const Real bpy = Real(0.5) * (vy + vy * vy), bmy = Real(0.5) * (-vy + vy * vy);
+        const Real dpp = (ax * bpy + bpx * ax) + bpx * bpy, dmm = (ax * bmy + bmx * ax) + bmx * bmy;
+        const Real cp = dr * (Real(1.0 / 36.0) + dpp) + R0 * dpp;   // direction (sx, 1)
+        const Real cm = dr * (Real(1.0 / 36.0) + dmm) + R0 * dmm;   // direction (-sx, -1)
+        // bounced diagonal (-sx, 1) and (sx, -1): odd part of (-sx, 1)
+        const Real od = rho * Real(0.5) * (-sx * vx * (Real(1.0 / 3.0) + vy * vy) + vy * (Real(1.0 / 3.0) + vx * vx));
+        if (anti) {   // cut-off 6 = (-1, 1), 8 = (1, -1); bounced 5 = (1, 1), 7 = (-1, -1)
+            f[6] = unk[6] ? cp : f[6];
+            f[8] = unk[8] ? cm : f[8];
+            f[5] = unk[5] ? f[7] + od : f[5];
+            f[7] = unk[7] ? f[5] - od : f[7];
+        } else {      // cut-off 5 = (1, 1), 7 = (-1, -1); bounced 6 = (-1, 1), 8 = (1, -1)
+            f[5] = unk[5] ? cp : f[5];
+            f[7] = unk[7] ? cm : f[7];
+            f[6] = unk[6] ? f[8] + od : f[6];
+            f[8] = unk[8] ? f[6] - od : f[8];
+        }
+    }
+    if (imperm) f[0] = dr - ((((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]))));
 }
 
 template <typename S, typename Real, bool DEV>

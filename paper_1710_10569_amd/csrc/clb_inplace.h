@@ -5,8 +5,11 @@
 // = f*_i(x - e_i, t - 1) is at slot opp(i) of node x - e_i; the step reads it there and writes
 // f*_i(x) to slot i of node x + e_i, where the next even step expects f_i(x + e_i, t + 1).  In both
 // steps a thread reads and writes the same 14 locations and no other thread touches them, so the
-// update is race-free in one buffer.  Populations whose source or target lies outside a wall are
-// neither read nor written (their slots hold stale values, which the wall step replaces).
+// update is race-free in one buffer.  Populations whose source lies outside a wall are not read
+// (the wall step replaces them).  A flow population whose target lies outside a wall stays in slot
+// opp(q) of its own node at either parity, where the wall step's mass balance reads it one step
+// later; that slot is the one the node's unknown population opp(q) occupies, which no other node
+// reads or writes.
 //
 // The wall step needs the post-streaming state of the inner neighbours x_f and x_ff of a wall node
 // at the same time step -- values the neighbours' own threads overwrite during that step.  They
@@ -67,10 +70,19 @@ __device__ __forceinline__ void snap_put(S* __restrict__ snap, const Geo& G, int
     if (!G.pery && (y == G.ny - 2 || y == G.ny - 3)) snap[((3 * 2 + G.ny - 2 - y) * 14 + q) * len + x] = v;
 }
 
-// The wall step's inner neighbours, read from the snapshot copy of the current time step.
+// The wall step's inner neighbours, read from the snapshot copy of the current time step, and the
+// node's own outgoing populations: at either parity f*_k(x) of a direction k that left the domain
+// is in slot opp(k) of x itself (the even step writes every f*_k to slot opp(k); the odd step keeps
+// the outgoing ones there, a slot no other node reads or writes).
 template <typename S>
 struct SnapSource {
     const S* snap;
+    const S* A;
+    template <typename Real>
+    __device__ __forceinline__ Real bounced(const Geo& G, int x, int y, int i) const
+    {
+        return Real(A[pop_at(G, x, y) + i * CW]);
+    }
     template <typename Real>
     __device__ __forceinline__ void all(const Geo& G, int x, int y, Real f[9], Real g[5]) const
     {
@@ -165,7 +177,9 @@ __device__ __forceinline__ void store_aa(S* __restrict__ A, S* __restrict__ snex
         }
     } else {
         const AANbr n = aa_nbr(G, x, y);
-        // targets beyond a wall are dropped; only wall nodes have any
+        // targets beyond a wall: a flow population is kept in slot opp(q) of the node itself (the
+        // wall step's mass balance reads it there), a temperature one is dropped; only wall nodes
+        // have any
         const bool okxm = G.perx || x > 0, okxp = G.perx || x < G.nx - 1;
         const bool okym = G.pery || y > 0, okyp = G.pery || y < G.ny - 1;
 #pragma unroll
@@ -173,7 +187,13 @@ __device__ __forceinline__ void store_aa(S* __restrict__ A, S* __restrict__ snex
             const int i = q < 9 ? q : q - 9;
             const int dx = ex_of(i), dy = ey_of(i);
             const bool ok = (dx < 0 ? okxm : (dx > 0 ? okxp : true)) && (dy < 0 ? okym : (dy > 0 ? okyp : true));
-            if (!ok) continue;
+            if (!ok) {
+                if (q < 9) {
+                    if (NT) __builtin_nontemporal_store(v[q], A + aa_at(n, 0, 0) + opp_of(q) * CW);
+                    else A[aa_at(n, 0, 0) + opp_of(q) * CW] = v[q];
+                }
+                continue;
+            }
             if (NT) __builtin_nontemporal_store(v[q], A + aa_at(n, dx, dy) + q * CW);
             else A[aa_at(n, dx, dy) + q * CW] = v[q];
         }
@@ -214,7 +234,7 @@ __device__ __forceinline__ void node_update_aa(S* __restrict__ A, const S* __res
 {
     Real f[9], g[5];
     load_aa<S, Real, ODD>(A, G, x, y, f, g);
-    if (on_wall(G, x, y)) wall_step_nb<Real, DEV>(SnapSource<S>{snow}, G, P, x, y, f, g);
+    if (on_wall(G, x, y)) wall_step_nb<Real, DEV>(SnapSource<S>{snow, A}, G, P, x, y, f, g);
     const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
     collide_f<Real, DEV>(f, m, P);
     collide_g<Real, DEV>(g, m, P);
