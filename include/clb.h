@@ -173,6 +173,17 @@ int clb_set_prescribed_velocity(clb_lattice* h, double ux, double uy);
  * if any value is non-finite.  Synchronises the stream. */
 int clb_diagnostics(clb_lattice* h, int snapshot, clb_diag* out);
 
+/* clb_diagnostics without allocating: for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Computes the same
+ * record with the same kernels, bitwise equal to clb_diagnostics(h, 0, out); the residual is
+ * measured against the snapshot a clb_diagnostics call took, and no snapshot is taken.  The
+ * reduction's scratch is a fixed device array of the library (4 MiB per GPU, held until the
+ * process ends), so the lattice may have at most 8,388,608 nodes; calls on the same GPU share
+ * it, and overlapping calls on one GPU race.  Synchronises the stream.  Errors: CLB_EINVAL for a
+ * NULL argument or a larger lattice, CLB_EDEVICE if the scratch cannot be located,
+ * CLB_EDIVERGED as clb_diagnostics. */
+int clb_diagnostics_noalloc(clb_lattice* h, clb_diag* out);
+
 /* The post-streaming populations of the current step (before the wall step), as full FP64
  * values: f as 9 planes and g as 5 planes of nx*ny, direction order of Eq. 4.  A population
  * whose streaming source lies outside the domain is unknown and returned as NaN.  Either pointer

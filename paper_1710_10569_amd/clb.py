@@ -81,6 +81,7 @@ _sig("clb_set_relaxation", ctypes.c_int, [_H] + [ctypes.c_double] * 4)
 _sig("clb_set_body_force", ctypes.c_int, [_H, ctypes.c_double, ctypes.c_double])
 _sig("clb_set_prescribed_velocity", ctypes.c_int, [_H, ctypes.c_double, ctypes.c_double])
 _sig("clb_diagnostics", ctypes.c_int, [_H, ctypes.c_int, ctypes.POINTER(clb_diag)])
+_sig("clb_diagnostics_noalloc", ctypes.c_int, [_H, ctypes.POINTER(clb_diag)])
 _sig("clb_get_populations", ctypes.c_int, [_H, _dp, _dp])
 _sig("clb_params_from_physics", ctypes.c_int, [ctypes.c_double] * 5 + [_dp, _dp, _dp])
 _sig("clb_time_steps", ctypes.c_int, [_H, ctypes.c_longlong, _dp])
@@ -262,6 +263,15 @@ class Lattice:
     def diagnostics(self, snapshot=False, raise_on_diverged=True):
         d = clb_diag()
         rc = _lib.clb_diagnostics(self._h, int(bool(snapshot)), ctypes.byref(d))
+        if rc != CLB_OK and (rc != CLB_EDIVERGED or raise_on_diverged):
+            raise CLBError(rc, last_error())
+        return d.as_dict()
+
+    def diagnostics_noalloc(self, raise_on_diverged=True):
+        """clb_diagnostics_noalloc: the record of diagnostics(snapshot=False) computed without
+        allocating device memory (the library's fixed scratch; lattices of at most 8,388,608 nodes)."""
+        d = clb_diag()
+        rc = _lib.clb_diagnostics_noalloc(self._h, ctypes.byref(d))
         if rc != CLB_OK and (rc != CLB_EDIVERGED or raise_on_diverged):
             raise CLBError(rc, last_error())
         return d.as_dict()

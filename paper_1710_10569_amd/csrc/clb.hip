@@ -639,3 +639,72 @@ extern "C" int clb_diagnostics(clb_lattice* h, int snapshot, clb_diag* out)
     }
     return CLB_OK;
 }
+
+// ---------------------------------------------------------------------------------------------
+// Allocation-free diagnostics (clb_diagnostics_noalloc).
+//
+// Its scratch -- the per-block partial records of the diagnostics reduction after the final
+// record -- is a file-scope device array; each GPU the library runs on holds one copy until the
+// process ends.  In host code the array's name is not a device address: the address of a GPU's
+// copy is looked up once, with that GPU current, and kept in g_noalloc_ptr.  Every call on a GPU
+// shares its copy, so calls that overlap on one GPU race.  Nothing in it needs clearing: each
+// call's reduction writes every partial record it reads and the whole final record.
+namespace clb {
+constexpr int NOALLOC_MAX_BLOCKS = 32768;   // one partial record per 256 nodes: 8,388,608 nodes
+constexpr int NOALLOC_DEVICES = 64;
+}  // namespace clb
+
+static __device__ __align__(256) double scratch[(clb::NOALLOC_MAX_BLOCKS + 1) * clb::DIAG_SLOTS];
+static std::mutex g_noalloc_mu;
+static double* g_noalloc_ptr[clb::NOALLOC_DEVICES];
+
+// Device address of `scratch` on GPU `device` (looked up on the first call for that GPU).
+static double* noalloc_scratch(int device)
+{
+    if (device < 0 || device >= NOALLOC_DEVICES) {
+        set_error("device %d is beyond the %d the allocation-free diagnostics support", device, NOALLOC_DEVICES);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e == hipSuccess && prev != device) e = hipSetDevice(device);
+        void* p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != device) (void)hipSetDevice(prev);
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress of the diagnostics scratch failed on device %d: %s", device, hipGetErrorString(e));
+            return nullptr;
+        }
+        g_noalloc_ptr[device] = static_cast<double*>(p);
+    }
+    return g_noalloc_ptr[device];
+}
+
+extern "C" int clb_diagnostics_noalloc(clb_lattice* h, clb_diag* out)
+{
+    clear_error();
+    if (!h || !out) { set_error("NULL argument"); return CLB_EINVAL; }
+    const Geo G = make_geo(h->desc);
+    const int nblocks = diag_blocks(G);
+    if (nblocks > NOALLOC_MAX_BLOCKS) {
+        set_error("lattice of %lld nodes exceeds the allocation-free diagnostics' scratch (at most %lld nodes); use clb_diagnostics",
+                  (long long)G.nx * G.ny, (long long)NOALLOC_MAX_BLOCKS * RED_NT);
+        return CLB_EINVAL;
+    }
+    double* s = noalloc_scratch(h->device);
+    if (!s) return CLB_EDEVICE;
+    int rc = launch_moments(h);
+    if (rc) return rc;
+    CLB_HIP(enqueue_diag(h->d_fields, h->d_snap, h->has_snap ? 1 : 0, G, s + DIAG_SLOTS, s, h->stream));
+    double r[DIAG_SLOTS];
+    CLB_HIP(hipMemcpyAsync(r, s, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    CLB_HIP(hipStreamSynchronize(h->stream));
+    unpack_diag(r, h->steps, out);
+    if (out->nonfinite) {
+        set_error("non-finite density, velocity or temperature at step %lld", h->steps);
+        return CLB_EDIVERGED;
+    }
+    return CLB_OK;
+}
