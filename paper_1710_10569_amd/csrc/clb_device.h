@@ -243,20 +243,8 @@ __device__ __forceinline__ Real at(const Real f[9], int k)
 __host__ __device__ constexpr int zb(int k, int i) { return ex_of(i) * znx(k) + ey_of(i) * zny(k); }
 __host__ __device__ constexpr int za(int k, int i) { return ex_of(i) * zny(k) - ey_of(i) * znx(k); }
 
-// zou_he_density: Zou-He's own density, for which also sum f = rho (used on permeable walls);
-// zou_he: the three unknowns for a given density rho.
-template <typename Real, bool DEV>
-__device__ __forceinline__ Real zou_he_density(const Real f[9], int nx, int ny, Real uwx, Real uwy, Real Fx, Real Fy)
-{
-    const int k = nx == 1 ? 0 : (nx == -1 ? 1 : (ny == 1 ? 2 : 3));
-    const Real un = uwx * Real(nx) + uwy * Real(ny);
-    const Real Fn = Fx * Real(nx) + Fy * Real(ny);
-    const Real K0 = (f[0] + at<1, 0>(f, k)) + at<-1, 0>(f, k);
-    const Real Km = (at<0, -1>(f, k) + at<1, -1>(f, k)) + at<-1, -1>(f, k);
-    // the rest weights over b = 0 plus twice those over b = -1 sum to 1
-    return ((DEV ? Real(1) : Real(0)) + K0 + Real(2) * Km - Real(0.5) * Fn) / (Real(1) - un);
-}
-
+// zou_he: the three unknowns for a given density rho (Zou-He's own density, for which also
+// sum f = rho, is the one permeable walls use).
 template <typename Real, bool DEV>
 __device__ __forceinline__ void zou_he(Real f[9], int nx, int ny, Real uwx, Real uwy, Real Fx, Real Fy, Real rho)
 {
@@ -353,12 +341,11 @@ struct PullSource {
     __device__ __forceinline__ void all(const Geo& G, int x, int y, Real f[9], Real g[5]) const { pull(src, G, x, y, f, g); }
     template <typename Real>
     __device__ __forceinline__ void temp(const Geo& G, int x, int y, Real g[5]) const { pull_g(src, G, x, y, g); }
-    // f*_opp(i)(x) of the previous step (i = 1..8): the population that left the domain where
-    // the unknown f_i enters
+    // f*_k(x) of the previous step for a direction k (runtime) that leaves the domain
     template <typename Real>
-    __device__ __forceinline__ Real bounced(const Geo& G, int x, int y, int i) const
+    __device__ __forceinline__ Real outgoing(const Geo& G, int x, int y, int k) const
     {
-        return Real(src[pop_at(G, x, y) + (i == 1 ? 3 : i == 2 ? 4 : i == 3 ? 1 : i == 4 ? 2 : i == 5 ? 7 : i == 6 ? 8 : i == 7 ? 5 : 6) * CW]);
+        return Real(src[pop_at(G, x, y) + k * CW]);
     }
 };
 
@@ -405,17 +392,25 @@ __device__ __forceinline__ void wall_step_nb(const NB& nb, const Geo& G, const P
         unk[i] = (ex_of(i) > 0 && onW) || (ex_of(i) < 0 && onE) || (ey_of(i) > 0 && onS) || (ey_of(i) < 0 && onN);
     const Real R0 = DEV ? Real(1) : Real(0);
     const bool imperm = corner || ((G.perm >> vw) & 1) == 0;
-    Real dr;   // rho_b - R0
-    if (imperm) {
-        dr = f[0];
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            if (unk[i]) dr += nb.template bounced<Real>(G, x, y, i);
-            else dr += f[i];
-        }
-    } else {
-        dr = zou_he_density<Real, DEV>(f, dx, dy, uwx, uwy, Fxb, Fyb) - R0;
-    }
+    // edge (inward normal k): the known populations are those with e.n <= 0, the outgoing ones
+    // have e.n = -1; corner (inward (dx, dy)): known f_0 and the three populations from inside,
+    // (-dx, 0), (0, -dy), (-dx, -dy), and the five with e_x = -dx or e_y = -dy left the domain.
+    // Both are formed with selects, without branches, and the node's kind picks one.
+    const int k = dx == 1 ? 0 : (dx == -1 ? 1 : (dy == 1 ? 2 : 3));
+    const int c = (dx > 0 ? 0 : 1) + (dy > 0 ? 0 : 2);   // corner: 0 SW, 1 SE, 2 NW, 3 NE
+    const Real K0 = (f[0] + at<1, 0>(f, k)) + at<-1, 0>(f, k);
+    const Real Km = (at<0, -1>(f, k) + at<1, -1>(f, k)) + at<-1, -1>(f, k);
+    const Real un = uwx * Real(dx) + uwy * Real(dy);
+    const Real Fn = Fxb * Real(dx) + Fyb * Real(dy);
+    const Real dr_zh = (R0 + K0 + Real(2) * Km - Real(0.5) * Fn) / (Real(1) - un) - R0;
+    const int o1 = corner ? (dx > 0 ? 3 : 1) : sel4(zdir(0, 0, -1), zdir(1, 0, -1), zdir(2, 0, -1), zdir(3, 0, -1), k);
+    const int o2 = corner ? (dy > 0 ? 4 : 2) : sel4(zdir(0, 1, -1), zdir(1, 1, -1), zdir(2, 1, -1), zdir(3, 1, -1), k);
+    const int o3 = corner ? sel4(7, 8, 6, 5, c) : sel4(zdir(0, -1, -1), zdir(1, -1, -1), zdir(2, -1, -1), zdir(3, -1, -1), k);
+    Real out = (nb.template outgoing<Real>(G, x, y, o1) + nb.template outgoing<Real>(G, x, y, o2)) +
+               nb.template outgoing<Real>(G, x, y, o3);
+    if (corner) out += nb.template outgoing<Real>(G, x, y, sel4(6, 5, 7, 8, c)) + nb.template outgoing<Real>(G, x, y, sel4(8, 7, 5, 6, c));
+    const Real known_c = (f[0] + (dx > 0 ? f[3] : f[1])) + ((dy > 0 ? f[4] : f[2]) + sel4(f[7], f[8], f[6], f[5], c));
+    const Real dr = !imperm ? dr_zh : (corner ? known_c : K0 + Km) + out;   // rho_b - R0
     const Real rho = R0 + dr;
 
     if (!corner) {
@@ -454,7 +449,12 @@ __device__ __forceinline__ void wall_step_nb(const NB& nb, const Geo& G, const P
             f[8] = unk[8] ? f[6] - od : f[8];
         }
     }
-    if (imperm) f[0] = dr - ((((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]))));
+    // 5. impermeable: f_0 = rho_b - sum_{i>0} f_i.  On an edge Zou-He's unknowns sum to K_m - F_n/2
+    //    (u_n = 0), so this is f_0 + (out - K_m) + F_n/2; at a corner the sum is formed directly.
+    if (imperm) {
+        if (corner) f[0] = dr - ((((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]))));
+        else f[0] += (out - Km) + Real(0.5) * Fn;
+    }
 }
 
 template <typename S, typename Real, bool DEV>
