@@ -69,20 +69,38 @@ def cavity(L=256, Ra=1e5, Pr=0.71, Ma=0.1, seed=2, noise=1e-4, T_hot=0.5, T_cold
 
 
 def rayleigh_benard(nx=2048, ny=1024, Ra=1e6, Pr=0.71, Ma=0.3, seed=3, amp=1e-3,
-                    T_hot=0.5, T_cold=-0.5, T0=0.0):
+                    T_hot=0.5, T_cold=-0.5, T0=0.0, rolls=0.0):
     """Rayleigh-Benard cell, periodic in x, hot south wall and cold north wall (Dirichlet, no-slip),
     gravity along -y.  Initial state: rest, the conduction profile T = T_hot - (T_hot - T_cold) y/H
-    on nodes y = 0..H, plus U(-amp, amp) noise on the interior rows."""
+    on nodes y = 0..H, plus U(-amp, amp) noise on the interior rows.
+
+    rolls > 0 starts instead from convection rolls of that fraction of the convective velocity
+    u_c = Ma c_s, one pair per 2H of width (k = 2 pi m / nx with m = round(nx / 2H)): stream
+    function psi = (A / k) sin(kx) sin^2(pi y / H), so u_x = A (pi / (k H)) sin(kx) sin(2 pi y / H) and
+    u_y = -A cos(kx) sin^2(pi y / H) are divergence-free and vanish on the walls, with the warm
+    anomaly -0.1 dT cos(kx) sin(pi y / H) where the fluid rises."""
     rng = np.random.default_rng(seed)
     H = ny - 1
     y = np.arange(ny, dtype=np.float64)[:, None]
     T = np.broadcast_to(T_hot - (T_hot - T_cold) * y / H, (ny, nx)).copy()
     T[1:-1, :] += rng.uniform(-amp, amp, size=(ny - 2, nx))
-    return {"name": f"rayleigh_benard_{nx}x{ny}_Ra{Ra:.3g}", "nx": nx, "ny": ny, "T0": T0,
+    ux = uy = None
+    u_c = Ma / math.sqrt(3.0)
+    if rolls > 0:
+        A = rolls * u_c
+        m = max(1, round(nx / (2 * H)))
+        k = 2 * math.pi * m / nx
+        x = np.arange(nx, dtype=np.float64)[None, :]
+        s = np.sin(math.pi * y / H)
+        ux = A * (math.pi / (k * H)) * np.sin(k * x) * np.sin(2 * math.pi * y / H)
+        uy = -A * np.cos(k * x) * s * s
+        T = T - 0.1 * (T_hot - T_cold) * np.cos(k * x) * s
+    return {"name": f"rayleigh_benard_{nx}x{ny}_Ra{Ra:.3g}" + (f"_rolls{rolls:g}" if rolls > 0 else ""),
+            "nx": nx, "ny": ny, "T0": T0,
             "edges": _edges(south=("dirichlet", 0.0, 0.0, T_hot), north=("dirichlet", 0.0, 0.0, T_cold)),
             "physics": {"Ra": Ra, "Pr": Pr, "Ma": Ma, "H": H, "dT": T_hot - T_cold},
-            "u_scale": Ma / math.sqrt(3.0),
-            "fields": {"rho": None, "ux": None, "uy": None, "T": T}}
+            "u_scale": u_c,
+            "fields": {"rho": None, "ux": ux, "uy": uy, "T": T}}
 
 
 def rb_cell(Ra, L=60, H=30, Pr=0.71, Ma=0.3, T_hot=1.05, T_cold=0.95, amp=1e-3):

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_1710_10569_amd import workloads as W
-from tests.helpers import field_errors, oracle_from_workload
+from tests.helpers import field_errors, oracle_from_workload, worst
 
 pytestmark = pytest.mark.gpu
 
@@ -91,7 +91,7 @@ def test_batch_fp64_matches_oracle(gpu):
         o = oracle_from_workload(w)
         o.step(120)
         e = field_errors(b.moments(s), o.moments(), w["T0"], w["u_scale"])
-        assert max(e.values()) < 1e-12, (w["name"], e)
+        assert worst(e) < 1e-12, (w["name"], e)
 
 
 def test_admission_by_footprint_and_slot_reuse(gpu):
@@ -223,7 +223,7 @@ def test_served_result_same_alone_and_in_mix(gpu, in_place):
     assert a.status == m.status and a.steps == m.steps and a.nu_wall == m.nu_wall
     for x, y in zip(a.fields, m.fields):
         assert np.array_equal(x, y)
-    assert all(r.status in ("converged", "plateau", "capped") for r in out)
+    assert all(r.status in ("converged", "fp32_floor", "capped") for r in out)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp32_sr"])
@@ -263,7 +263,7 @@ def _serve_against_oracle(precision, cases, step_cap):
     from paper_1710_10569_amd import serving as S
     reqs = [S.Request(i, 0.0, L, Ra, seed) for i, (L, Ra, seed) in enumerate(cases)]
     srv = S.CavityServer(budget_bytes=64 << 20, capacity=8, precision=precision, chunk=1000, tol=1e-9,
-                         step_cap=step_cap, schedule="grouped", keep_fields=True, plateau_patience=10 ** 9)
+                         step_cap=step_cap, schedule="grouped", keep_fields=True, stall_patience=10 ** 9)
     out = srv.run(reqs)
     srv.close()
     errs = []
@@ -292,35 +292,42 @@ def test_served_fp32_matches_fp64_oracle(gpu):
         assert max(e["u"], e["T"]) * 10 < max(e0["u"], e0["T"]), (e, e0)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp32_sr"])
-def test_full_batch_sampled_against_oracle(gpu, precision):
+def test_full_batch_sampled_against_oracle(gpu):
     """The 512-cavity batch in the launch configuration the benchmark times (one grouped launch
-    per step over all cavities, autotuned tile mappings and store form), 200 steps: a sample of
-    cavities (three of side 64, three of 96, two of 128) compared node by node with the oracle
-    within 1e-5 in u and T, and every cavity finite."""
+    per step over all cavities, autotuned tile mappings and store form), 2000 steps, FP32 storage
+    with stochastic rounding and plain FP32: a sample of cavities of sides 64 to 256 compared node
+    by node with the oracle, u and T within 1e-5 (stochastic rounding) and 3e-5 (plain FP32,
+    round-to-nearest), errors relative to max |u_ref| and max |T_ref - T0|; every cavity finite."""
     clb = _clb()
     specs = W.batch_cavity_specs()
-    budget = sum(clb.footprint(L, L, precision) for L, _, _ in specs) + (64 << 20)
-    b = clb.Batch(len(specs), precision, budget_bytes=budget)
-    slots = [b.add_workload(W.cavity(L, Ra=Ra, seed=sd)) for L, Ra, sd in specs]
-    assert all(s is not None for s in slots)
-    b.autotune(2)          # leaves the state untouched
-    b.step(200, "grouped")
-    b.check()
-    res = b.residuals()
-    assert not any(v[2] for v in res.values())
     picked = []
-    for L, count in ((64, 3), (96, 3), (128, 2)):
+    for L, count in ((64, 2), (96, 2), (128, 2), (192, 1), (256, 1)):
         picked += [i for i, sp in enumerate(specs) if sp[0] == L][:count]
+    steps = 2000
+    ref = {}
     for i in picked:
         L, Ra, sd = specs[i]
-        w = W.cavity(L, Ra=Ra, seed=sd)
-        o = oracle_from_workload(w)
-        o.step(200)
-        e = field_errors(b.moments(slots[i]), o.moments(), w["T0"], w["u_scale"])
-        print(f"[batch] full batch {precision} cavity {i} L={L} Ra={Ra:.3g}: {e}", flush=True)
-        assert e["u"] < 1e-5 and e["T"] < 1e-5, (i, e)
-    b.close()
+        o = oracle_from_workload(W.cavity(L, Ra=Ra, seed=sd))
+        o.step(steps)
+        ref[i] = o.moments()
+        o.close()
+    for precision, tol in (("fp32_sr", 1e-5), ("fp32", 3e-5)):
+        budget = sum(clb.footprint(L, L, precision) for L, _, _ in specs) + (64 << 20)
+        b = clb.Batch(len(specs), precision, budget_bytes=budget)
+        slots = [b.add_workload(W.cavity(L, Ra=Ra, seed=sd)) for L, Ra, sd in specs]
+        assert all(s is not None for s in slots)
+        b.autotune(2)          # leaves the state untouched
+        b.step(steps, "grouped")
+        b.check()
+        res = b.residuals()
+        assert not any(v[2] for v in res.values())
+        for i in picked:
+            L, Ra, sd = specs[i]
+            w = W.cavity(L, Ra=Ra, seed=sd)
+            e = field_errors(b.moments(slots[i]), ref[i], w["T0"], w["u_scale"])
+            print(f"[batch] full batch {precision} cavity {i} L={L} Ra={Ra:.3g}: {e}", flush=True)
+            assert e["u"] < tol and e["T"] < tol, (precision, i, e)
+        b.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_sr"])
