@@ -5,8 +5,9 @@ request is admitted as soon as a batch slot and enough pool memory are free (adm
 footprint, first come first served); admitted lattices stay resident and are advanced together by
 the batched kernel in chunks of `chunk` steps; after every chunk each resident lattice's FP64
 max-norm change of u and T over that chunk is measured on the device, and a lattice whose change
-is below `tol` (or whose change has stopped falling, or that hits the step cap, or goes non-finite)
-is read out and its slot and memory are released for the next request.  A request therefore overlaps on the device with whatever else
+is below `tol` (converged), whose change has stopped falling (at the FP32 storage floor, or above
+it without converging), that hits the step cap, or that goes non-finite is read out and its slot
+and memory are released for the next request.  A request therefore overlaps on the device with whatever else
 is resident, and its result does not depend on the mix: every lattice takes the same per-node
 update and the same chunk-aligned stopping test alone or with others.
 
@@ -35,10 +36,10 @@ class Request:
     admitted: float = math.nan
     finished: float = math.nan
     steps: int = 0
-    status: str = "pending"   # converged | plateau | capped | diverged | rejected
+    status: str = "pending"   # converged | fp32_floor | stalled | capped | diverged | rejected
     du: float = math.nan
     dT: float = math.nan
-    best: float = math.inf    # smallest max(du, dT) seen: the plateau level of a "plateau" request
+    best: float = math.inf    # smallest max(du, dT) seen: the level a stopped request settled at
     nu_wall: float = math.nan
     fields: tuple = field(default=None, repr=False)
 
@@ -58,20 +59,24 @@ class CavityServer:
     steady; step_cap: give up after this many steps; schedule: 'grouped' or 'persistent';
     keep_fields: return (rho, ux, uy, T).
 
-    Plateau: a request whose change per chunk is below plateau_max and has not fallen below
-    0.9 times its best value for plateau_patience chunks has stopped approaching a fixed point and
-    is finished as "plateau", its best change recorded.  Closed buoyant cavities level off this way
-    even in FP64 (the corner closure lets mass drain slowly, so the discrete problem has no exact
-    steady state); FP32 storage adds its rounding noise to the level.  A slow but steady decay
-    (halving in fewer than about 6 * plateau_patience chunks) keeps running."""
+    Stopping without converging: the change per chunk is noisy once FP32 storage holds the state
+    (each store rounds at random, so the state jitters at the rounding level: about 1e-7 in T for
+    cavities with |T| up to 1/2, whose populations are stored to FP32's 3e-8 spacing).  A request
+    whose change has not fallen below 0.9 times its best value for stall_patience chunks has
+    stopped approaching a fixed point: "fp32_floor" if it runs with FP32 storage and its change is
+    below floor_max (converged to FP32's resolution), "stalled" otherwise while the change is below
+    stall_max (stopped without converging: an unsteady or under-resolved flow); its best change is
+    recorded.  FP64 runs converge to tol.  A slow but steady decay (halving in fewer than about
+    6 * stall_patience chunks) keeps running."""
 
     def __init__(self, budget_bytes=16 << 30, capacity=1024, precision="fp32_sr", chunk=1000, tol=1e-8,
                  step_cap=5_000_000, schedule="persistent", Pr=0.71, Ma=0.1, keep_fields=False,
-                 plateau_patience=20, plateau_max=1e-5, stream=None, in_place=False):
+                 stall_patience=20, floor_max=1e-6, stall_max=1e-5, stream=None, in_place=False):
         self.batch = clb.Batch(capacity, precision, budget_bytes=budget_bytes, stream=stream)
         self.precision, self.chunk, self.tol, self.step_cap = precision, int(chunk), float(tol), int(step_cap)
         self.schedule, self.Pr, self.Ma, self.keep_fields = schedule, Pr, Ma, keep_fields
-        self.plateau_patience, self.plateau_max = int(plateau_patience), float(plateau_max)
+        self.stall_patience, self.floor_max, self.stall_max = int(stall_patience), float(floor_max), float(stall_max)
+        self.fp32_storage = precision in ("fp32", "fp32_sr")
         self.in_place = bool(in_place)
         self.site_updates = 0
 
@@ -133,8 +138,10 @@ class CavityServer:
                         st[1], st[2] = res, 0
                     else:
                         st[2] += 1
-                    if st[2] >= self.plateau_patience and res < self.plateau_max:
-                        r.status = "plateau"    # stopped approaching a fixed point
+                    if st[2] >= self.stall_patience and res < self.floor_max and self.fp32_storage:
+                        r.status = "fp32_floor"    # converged to FP32 storage's resolution
+                    elif st[2] >= self.stall_patience and res < self.stall_max:
+                        r.status = "stalled"       # stopped approaching a fixed point
                     elif r.steps >= self.step_cap:
                         r.status = "capped"
                 if r.status != "pending":
@@ -155,20 +162,30 @@ class CavityServer:
         return reqs
 
 
+def _latency(rs, wall):
+    if not rs:
+        return {"count": 0, "p50_latency_s": None, "p99_latency_s": None, "solves_per_s": 0.0}
+    lat = np.array([r.latency for r in rs])
+    return {"count": len(rs), "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "solves_per_s": len(rs) / wall if wall > 0 else 0.0}
+
+
 def summarize(reqs, wall, site_updates):
-    """p50/p99 latency of finished requests (converged, plateau, capped), solves/s, aggregate MLUPS,
-    counts by status and the levels at which plateau requests stopped."""
-    fin = [r for r in reqs if r.status in ("converged", "plateau", "capped")]
-    lat = np.array([r.latency for r in fin]) if fin else np.array([math.nan])
+    """Counts by status (converged, fp32_floor, stalled, capped, diverged, rejected); p50/p99
+    latency and solves/s over the converged requests ("converged") and over those that reached a
+    steady state to the storage's resolution ("settled": converged or fp32_floor); the levels at
+    which fp32_floor and stalled requests stopped; aggregate MLUPS over the whole run."""
     counts = {}
     for r in reqs:
         counts[r.status] = counts.get(r.status, 0) + 1
-    plateau = [r.best for r in reqs if r.status == "plateau"]
-    out = {"requests": len(reqs), "p50_latency_s": float(np.percentile(lat, 50)),
-           "p99_latency_s": float(np.percentile(lat, 99)), "solves_per_s": len(fin) / wall if wall > 0 else 0.0,
-           "aggregate_MLUPS": site_updates / wall / 1e6 if wall > 0 else 0.0, "wall_s": wall, "status": counts}
-    if plateau:
-        out["plateau_level"] = {"p50": float(np.percentile(plateau, 50)), "max": float(max(plateau))}
+    out = {"requests": len(reqs), "status": counts,
+           "converged": _latency([r for r in reqs if r.status == "converged"], wall),
+           "settled": _latency([r for r in reqs if r.status in ("converged", "fp32_floor")], wall),
+           "aggregate_MLUPS": site_updates / wall / 1e6 if wall > 0 else 0.0, "wall_s": wall}
+    for st in ("fp32_floor", "stalled"):
+        lv = [r.best for r in reqs if r.status == st]
+        if lv:
+            out[st + "_level"] = {"p50": float(np.percentile(lv, 50)), "max": float(max(lv))}
     return out
 
 

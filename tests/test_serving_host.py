@@ -1,7 +1,8 @@
 """The serving loop's scheduling on the host, with a scripted stand-in for the batch (no GPU):
 admission by free slots and footprint, continuous admission as slots free up, and the stopping
-rules -- converged below the tolerance, stopped on a plateau, capped, diverged, and rejected when a
-request could never fit the pool."""
+rules -- converged below the tolerance, settled at the FP32 storage floor, stalled without
+converging, capped, diverged, and rejected when a request could never fit the pool -- and the
+summary's separate counts and latency sets."""
 import math
 
 import pytest
@@ -75,26 +76,42 @@ def server(monkeypatch):
 def test_stopping_rules(server):
     server.update({0: (1e-3, 500.0, 0.0),        # decays below tol: converged
                    1: (1e-3, 1e9, 0.0),          # never decays: capped at the step cap
-                   2: (1e-4, 300.0, 3e-7),       # levels off at 3e-7: plateau
+                   2: (1e-4, 300.0, 3e-7),       # levels off at 3e-7: the FP32 storage floor
                    3: (float("nan"), 1.0, 0.0),  # non-finite: diverged
-                   4: (1e-3, 1e9, 2e-5)})        # stalls above plateau_max: runs to the cap
-    reqs = [S.Request(i, 0.0, 32, 1e4, i) for i in range(5)]
-    srv = S.CavityServer(budget_bytes=1 << 30, capacity=8, chunk=1000, tol=1e-8, step_cap=40000, plateau_patience=5)
+                   4: (1e-3, 1e9, 2e-5),         # stalls above stall_max: runs to the cap
+                   5: (1e-4, 300.0, 4e-6)})      # levels off above floor_max: stalled without converging
+    reqs = [S.Request(i, 0.0, 32, 1e4, i) for i in range(6)]
+    srv = S.CavityServer(budget_bytes=1 << 30, capacity=8, chunk=1000, tol=1e-8, step_cap=40000, stall_patience=5)
     out = {r.id: r for r in srv.run(reqs)}
     assert out[0].status == "converged" and out[0].steps < 40000
     assert out[1].status == "capped" and out[1].steps == 40000
-    assert out[2].status == "plateau" and out[2].best == pytest.approx(3e-7, rel=1e-3)
+    assert out[2].status == "fp32_floor" and out[2].best == pytest.approx(3e-7, rel=1e-3)
     assert out[3].status == "diverged" and out[3].steps == 1000
     assert out[4].status == "capped" and out[4].steps == 40000
+    assert out[5].status == "stalled" and out[5].best == pytest.approx(4e-6, rel=1e-3)
     assert out[0].nu_wall == 1.5
     s = S.summarize(list(out.values()), srv.wall, srv.site_updates)
-    assert s["status"] == {"converged": 1, "capped": 2, "plateau": 1, "diverged": 1}
-    assert s["plateau_level"]["p50"] == pytest.approx(3e-7, rel=1e-3)
+    assert s["status"] == {"converged": 1, "capped": 2, "fp32_floor": 1, "diverged": 1, "stalled": 1}
+    assert s["converged"]["count"] == 1 and s["settled"]["count"] == 2
+    assert s["converged"]["p50_latency_s"] == pytest.approx(out[0].latency)
+    assert s["fp32_floor_level"]["p50"] == pytest.approx(3e-7, rel=1e-3)
+    assert s["stalled_level"]["max"] == pytest.approx(4e-6, rel=1e-3)
 
 
-def test_slow_decay_is_not_a_plateau(server):
+def test_fp64_storage_has_no_fp32_floor(server):
+    """With FP64 storage a request that levels off below floor_max has stalled, not converged."""
+    server.update({0: (1e-4, 300.0, 3e-7)})
+    srv = S.CavityServer(budget_bytes=1 << 30, capacity=2, chunk=1000, tol=1e-8, step_cap=40000, stall_patience=5,
+                         precision="fp64")
+    out = srv.run([S.Request(0, 0.0, 32, 1e4, 0)])
+    assert out[0].status == "stalled"
+    s = S.summarize(out, srv.wall, srv.site_updates)
+    assert s["converged"]["count"] == 0 and s["converged"]["p50_latency_s"] is None
+
+
+def test_slow_decay_is_not_a_stall(server):
     """A residual that halves only every 60 chunks (e-folding 87 chunks) keeps falling by 10 % within
-    the 20-chunk patience, so it runs on to convergence instead of stopping as a plateau."""
+    the 20-chunk patience, so it runs on to convergence instead of stopping as stalled."""
     server.update({0: (1e-6, 87_000.0, 0.0)})
     srv = S.CavityServer(budget_bytes=1 << 30, capacity=2, chunk=1000, tol=1e-8, step_cap=10 ** 6)
     out = srv.run([S.Request(0, 0.0, 32, 1e4, 0)])
