@@ -58,6 +58,7 @@ def _load(path=None):
     lib.orc_get_outgoing.argtypes = [vp, _dp]
     lib.orc_set_outgoing.argtypes = [vp, _dp]
     lib.orc_threads.restype = ctypes.c_int
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
     lib.orc_matrix_M.argtypes = [_dp]
     lib.orc_matrix_N.argtypes = [ctypes.c_double, ctypes.c_double, _dp]
     lib.orc_matrix_Ninv.argtypes = [ctypes.c_double, ctypes.c_double, _dp]
@@ -108,6 +109,11 @@ def _f64(a, shape=None):
 def threads() -> int:
     """OpenMP threads the oracle uses (OMP_NUM_THREADS, else all cores)."""
     return _load().orc_threads()
+
+
+def set_threads(n: int) -> None:
+    """Run the following oracle steps on n threads."""
+    _load().orc_set_threads(int(n))
 
 
 class Edge:

@@ -499,6 +499,16 @@ int orc_threads(void)
 #endif
 }
 
+/* Threads for the following steps (n >= 1); used to time the oracle on one core. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 orc_lattice* orc_create(int nx, int ny, const int* kind, const double* uw, const double* Tw, double T0)
 {
     if (nx < 3 || ny < 3) return NULL;
