@@ -91,41 +91,49 @@ def test_rb_cell_parity(gpu, Ra):
         assert worst(e) < tol and worst(eb) < tol, (e, eb)
 
 
-def test_table1_nusselt_batch_fp32(gpu):
+def test_table1_nusselt_batch_fp64(gpu):
     """All eight Table 1 cells (60 x 30, Pr = 0.71, Ma = 0.3, temperatures centred on 0) in one
-    FP32 batch, persistent schedule, run to a steady state.  Ra <= 20000 within 0.5% of the
-    analytic Nu (the paper's own errors reach 0.41%); all within 1.5%."""
+    FP64 batch, persistent schedule, run to a steady state (max-norm change below 1e-12 per 1000
+    steps): the Nu of Eq. 29 of every cell equals the oracle's steady value
+    (tests/golden/table1_oracle.json, written by make_table1_oracle.py) within 1e-8, and the
+    analytic column within 0.25 % for Ra <= 20000 and 1.5 % above, the bounds the oracle itself is
+    pinned to."""
     clb = _clb()
     gold = json.load(open(os.path.join(GOLD, "table1_nusselt.json")))
+    orc = {r["Ra"]: r for r in json.load(open(os.path.join(GOLD, "table1_oracle.json")))["rows"]}
     rows = gold["rows"]
-    b = clb.Batch(len(rows), "fp32", budget_bytes=64 << 20)
+    b = clb.Batch(len(rows), "fp64", budget_bytes=64 << 20)
     slots, alphas = [], []
     for r in rows:
         w = W.rb_cell(r["Ra"], T_hot=0.05, T_cold=-0.05)
         slots.append(b.add_workload(w))
         p = w["physics"]
         alphas.append((clb.params_from_physics(p["Ra"], p["Pr"], p["Ma"], p["H"], p["dT"])[1] - 0.5) / 4)
-    for _ in range(80):
+    for _ in range(120):
         b.step(1000, "persistent")
         b.check()
         res = b.residuals()
-        if max(max(v[0], v[1]) for v in res.values()) < 1e-9:
+        if max(max(v[0], v[1]) for v in res.values()) < 1e-12:
             break
     out = []
     for r, s, a in zip(rows, slots, alphas):
         d = b.diagnostics(s)
         nu = 1 + d["sum_w_uy_T"] / d["sum_w"] * 30 / (a * 0.1)
-        out.append((r["Ra"], nu, nu / r["Nu_analytic"] - 1))
-    print("[physics] Table 1 on GPU:", [(ra, round(nu, 4), f"{e:+.2%}") for ra, nu, e in out], flush=True)
-    for ra, nu, e in out:
-        assert abs(e) < (5e-3 if ra <= 20000 else 1.5e-2), (ra, nu, e)
+        out.append((r["Ra"], nu, nu / r["Nu_analytic"] - 1, nu / orc[r["Ra"]]["Nu_volume"] - 1))
+    b.close()
+    print("[physics] Table 1 on GPU (Ra, Nu, vs analytic, vs oracle):",
+          [(ra, round(nu, 5), f"{e:+.3%}", f"{eo:+.1e}") for ra, nu, e, eo in out], flush=True)
+    for ra, nu, e, eo in out:
+        assert abs(eo) < 1e-8, (ra, nu, eo)
+        assert abs(e) < (2.5e-3 if ra <= 20000 else 1.5e-2), (ra, nu, e)
 
 
 def test_critical_rayleigh_number_batch(gpu):
     """Sec. 3.3: Rayleigh-Benard cells (60 x 30, Pr = 0.71, Ma = 0.3) at Ra = 1702 ... 1710, all in
     one FP64 batch.  After the start-up transient the velocity maximum grows or decays exponentially
     at a rate linear in Ra; the least-squares zero of that rate is the critical Rayleigh number
-    (linear stability 1707.76; the paper measures 1706.82)."""
+    (linear stability 1707.76; the paper measures 1706.82; measured here 1709.89, +0.12 %, the
+    60 x 30 grid's own error)."""
     clb = _clb()
     Ras = [1702.0, 1704.0, 1706.0, 1708.0, 1710.0]
     b = clb.Batch(len(Ras), "fp64", budget_bytes=64 << 20)
@@ -141,7 +149,7 @@ def test_critical_rayleigh_number_batch(gpu):
     slope, icpt = np.polyfit(Ras, rates, 1)
     ra_c = -icpt / slope
     print(f"[physics] growth rates {['%.3e' % r for r in rates]} -> Ra_c = {ra_c:.2f}", flush=True)
-    assert abs(ra_c - 1707.76) < 0.005 * 1707.76
+    assert abs(ra_c - 1707.76) < 0.002 * 1707.76
 
 
 def test_steps_to_convergence_scale_with_inverse_Ma(gpu):

@@ -302,28 +302,71 @@ def test_unknowns_are_exactly_the_out_of_domain_sources():
             assert np.array_equal(np.isnan(g[i]), outside)
 
 
-def test_table1_nusselt_centred_temperatures():
-    """Sec. 3.3, Table 1: Rayleigh-Benard at L x H = 60 x 30 (60 periodic columns,
-    H + 1 = 31 rows), Pr = 0.71, Ma = 0.3.  The steady Nu of Eq. 29 is within 0.5% of the analytic
-    column (the paper's own errors reach 0.41%).  The wall temperatures are centred on T0 = 0
-    (+-0.05); with the printed 1.05 / 0.95 the weakly compressible flow's div u, multiplied by the
-    mean temperature in the conservative D2Q5 equation, lowers Nu by about 4% at Ra = 1e4."""
+def _table1_cell(Ra, Ma=0.3, T_hot=0.05, T_cold=-0.05):
+    """Steady Nu of the Table 1 cell (60 x 30 nodes + 1, periodic in x): Eq. 29's volume form and
+    the hot-wall gradient form, once Eq. 29 changes by less than 1e-9 of itself over 1000 steps."""
+    w = W.rb_cell(Ra, Ma=Ma, T_hot=T_hot, T_cold=T_cold)
+    lat = make(w)
+    p = w["physics"]
+    alpha = O.alpha_of_tau(O.params_from_physics(p["Ra"], p["Pr"], p["Ma"], p["H"], p["dT"])[1])
+    prev = None
+    for _ in range(300):
+        lat.step(1000)
+        _, ux, uy, T = lat.moments()
+        nu = O.nusselt_volume(uy.T, T.T, alpha, p["dT"], p["H"], along_periodic=True)
+        if prev is not None and abs(nu - prev) < 1e-9 * nu:
+            break
+        prev = nu
+    g = (3 * T[0, :] - 4 * T[1, :] + T[2, :]) / 2.0
+    return nu, float(g.mean() * p["H"] / p["dT"])
+
+
+def test_table1_nusselt_all_rows():
+    """Sec. 3.3, Table 1: Rayleigh-Benard at L x H = 60 x 30 (60 periodic columns, 31 rows),
+    Pr = 0.71, Ma = 0.3, wall temperatures centred on T0 = 0 (+-0.05; with the printed 1.05 / 0.95
+    see the next tests), all eight rows.  For Ra <= 20000 the steady Nu of Eq. 29 is within 0.25 %
+    of the analytic column (the paper's own errors reach 0.41 %).  Above, the 60 x 30 grid's own
+    error reaches the percent level: the hot-wall gradient Nu of the same fields differs from
+    Eq. 29's by 1.1 % and 1.4 % at Ra = 30000 and 50000 (0.3 % or less at Ra <= 5000), and halving
+    the spacing moves Eq. 29's value by 0.3 % and 0.5 %.  There the analytic value lies between the
+    two measures (within 0.1 %) and Eq. 29's value within 1.5 % of it."""
     gold = json.load(open(os.path.join(GOLD, "table1_nusselt.json")))
-    rows = {r["Ra"]: r for r in gold["rows"]}
-    for Ra in (2500, 5000, 10000):
-        w = W.rb_cell(Ra, T_hot=0.05, T_cold=-0.05)
-        lat = make(w)
-        p = w["physics"]
-        alpha = O.alpha_of_tau(O.params_from_physics(p["Ra"], p["Pr"], p["Ma"], p["H"], p["dT"])[1])
-        prev = None
-        for _ in range(60):
-            lat.step(1000)
-            _, ux, uy, T = lat.moments()
-            nu = O.nusselt_volume(uy.T, T.T, alpha, p["dT"], p["H"], along_periodic=True)
-            if prev is not None and abs(nu - prev) < 1e-8 * nu:
-                break
-            prev = nu
-        assert nu == pytest.approx(rows[Ra]["Nu_analytic"], rel=5e-3)
+    for row in gold["rows"]:
+        Ra, ref = row["Ra"], row["Nu_analytic"]
+        nu, nu_w = _table1_cell(Ra)
+        if Ra <= 20000:
+            assert nu == pytest.approx(ref, rel=2.5e-3), (Ra, nu, ref)
+        else:
+            assert nu == pytest.approx(ref, rel=1.5e-2), (Ra, nu, ref)
+            lo, hi = min(nu, nu_w), max(nu, nu_w)
+            assert lo * (1 - 1e-3) <= ref <= hi * (1 + 1e-3), (Ra, nu, nu_w, ref)
+
+
+def test_table1_high_ra_is_not_a_compressibility_error():
+    """The Rayleigh number 50000 row at Ma = 0.1 instead of 0.3 (one ninth of the density
+    variations, three times the steps): Eq. 29's Nu moves by less than 0.1 %, so the 1.2 % gap
+    to the analytic column is not set by Ma."""
+    nu3, _ = _table1_cell(50000, Ma=0.3)
+    nu1, _ = _table1_cell(50000, Ma=0.1)
+    assert abs(nu1 / nu3 - 1) < 1e-3, (nu1, nu3)
+
+
+def test_printed_temperature_offset_deficit_grows_with_ma():
+    """Reading R20: with the printed wall temperatures 1.05 / 0.95 (mean 1, not 0) the conservative
+    D2Q5 equation carries the term T div u of the weakly compressible flow, which is of order
+    Ma^2 T0/dT relative to the advection of the 0.1 temperature difference.  At Ra = 10000 Nu of
+    Eq. 29 falls below the centred run's by 0.32 % at Ma = 0.15 and 4.0 % at Ma = 0.3: about the
+    fourth power of Ma (the square of that ratio), vanishing as Ma -> 0, while the centred run
+    itself changes by less than 0.1 % over that range."""
+    d = {}
+    for Ma in (0.15, 0.3):
+        c, _ = _table1_cell(10000, Ma=Ma)
+        o, _ = _table1_cell(10000, Ma=Ma, T_hot=1.05, T_cold=0.95)
+        d[Ma] = (c, o / c - 1)
+    assert -0.006 < d[0.15][1] < -0.001 and -0.05 < d[0.3][1] < -0.03, d
+    k = math.log(d[0.3][1] / d[0.15][1]) / math.log(2.0)
+    assert 3.0 < k < 4.5, (k, d)
+    assert abs(d[0.3][0] / d[0.15][0] - 1) < 1e-3, d
 
 
 def _normal_plate_errors(L, Re=10.0):
