@@ -313,16 +313,18 @@ int clb_batch_check(clb_batch* b);
 int clb_batch_time_steps(clb_batch* b, int mode, long long n, double* ms);
 
 /* Tile width of one lattice: 64, 128 or 256 nodes per row segment (256 nodes per tile), or 0 for
- * wrapped rows: tiles of 256 consecutive nodes in row-major order, shifted by half a wavefront so
- * that the last node of a row and the first node of the next share one wavefront (on lattices with
- * walls in x this halves the wavefronts that take the wall branch). */
+ * wrapped rows: each row is cut into 32-node runs from x = 0 (the last may be short), the runs of
+ * all rows are taken in row-major order, shifted by one run, two per wavefront, so that the last
+ * run of a row and the first run of the next share one wavefront (on lattices with walls in x this
+ * halves the wavefronts that take the wall branch) and every access stays cache-line aligned.
+ * Results do not depend on it. */
 int clb_batch_set_tile_width(clb_batch* b, int slot, int tile_width);
 
 /* The lattice's current tile width (64, 128, 256, or 0 for wrapped rows), as set by
- * clb_batch_set_tile_width, clb_batch_autotune or the default: for two-buffer lattices 64 when x has
- * walls, else by width (64 up to 96 nodes, 128 up to 192, 256 beyond); for in-place lattices, which
- * the autotuner does not time, wrapped rows when x has walls and nx is a multiple of 32, else 64.  Errors: CLB_EINVAL for an
- * unused slot or a NULL output. */
+ * clb_batch_set_tile_width, clb_batch_autotune or the default: wrapped rows when x has walls; else
+ * for two-buffer lattices by width (64 up to 96 nodes, 128 up to 192, 256 beyond) and 64 for
+ * in-place lattices, which the autotuner does not time.  Errors: CLB_EINVAL for an unused slot or
+ * a NULL output. */
 int clb_batch_get_tile_width(clb_batch* b, int slot, int* tile_width);
 
 /* Store form of the batch's step kernels: 1 = non-temporal stores (populations written this step

@@ -8,8 +8,9 @@
 //
 // Device tables: one entry per slot (geometry, buffer offsets, current buffer, tile width, and the
 // lattice's parameters in the arithmetic type), and a tile list ordered by slot and, within a
-// lattice, row-major.  Every tile is 256 nodes: 64 x 4, 128 x 2 or 256 x 1, chosen per lattice
-// (the autotuner picks the width per size class).
+// lattice, row-major.  Every tile is 256 threads: row tiles of 64 x 4, 128 x 2 or 256 x 1 nodes, or
+// eight 32-node runs of wrapped rows, chosen per lattice (the autotuner picks the mapping per size
+// class).
 //
 // Step schedules, all running the same per-node update (node_update), so a lattice's result does
 // not depend on the schedule or on the other lattices:
@@ -47,7 +48,8 @@ struct BatchLat {
     uint32_t step;      // steps taken before the current call (low 32 bits): the rounding key base
     int tw_log2;        // tile width 1 << tw_log2 (6, 7 or 8), tile rows 256 >> tw_log2; 0: wrapped rows
     int tiles_x, ntiles;
-    double inv_nx;      // 1 / nx (wrapped rows)
+    int halves;         // 32-node runs per row, ceil(nx / 32) (wrapped rows)
+    double inv_halves;  // 1 / halves
     int aa;             // 1: in-place lattice (off[0] only, snapshot copies at sn[0], sn[1])
     long long sn[2];    // element offsets of the in-place snapshot copies
 };
@@ -63,21 +65,25 @@ struct TileRef { int lat, tile; };
 constexpr int BNT = 256;
 
 // Node of thread `lane` of work item `tile` of a lattice; false if none.  Row tiles: width
-// 1 << tw_log2, BNT >> tw_log2 rows.  Wrapped rows (tw_log2 = 0): tile t covers the row-major node
-// indices [t BNT - 32, (t + 1) BNT - 32), so that a wavefront starts half a chunk into a row: the
-// last node of a row and the first of the next share one wavefront, and only that wavefront takes
-// the wall branch of the two x-wall nodes (in row tiles each of them costs its own wavefront).
-// Wavefronts still read and write whole 32-node halves of storage chunks, i.e. whole cache lines.
+// 1 << tw_log2, BNT >> tw_log2 rows.  Wrapped rows (tw_log2 = 0): the rows are cut into runs of 32
+// nodes starting at x = 0, 32, 64, ... (the halves of the storage chunks; a row's last run may be
+// short), all runs of all rows are numbered in row-major order, and each half-wavefront takes one
+// run, the sequence shifted by one run: tile t takes runs 8t - 1 .. 8t + 6.  The last run of a row
+// and the first of the next thus share one wavefront, and only that wavefront takes the wall
+// branch of the two x-wall nodes (in row tiles each of them costs its own wavefront); every
+// half-wavefront reads and writes one aligned 32-node half of a chunk, i.e. whole cache lines, for
+// any nx.  Where nx is a multiple of 32 this is node k = 256 t + lane - 32 in row-major order.
 __device__ __forceinline__ bool batch_node(const BatchLat& L, int tile, int lane, int& x, int& y)
 {
     if (L.tw_log2 == 0) {
-        const int k = tile * BNT + lane - 32;
-        if (k < 0 || k >= L.G.nx * L.G.ny) return false;
-        y = int(double(k) * L.inv_nx);
-        x = k - y * L.G.nx;
-        if (x < 0) { --y; x += L.G.nx; }
-        else if (x >= L.G.nx) { ++y; x -= L.G.nx; }
-        return true;
+        const int q = tile * (BNT / 32) + (lane >> 5) - 1;   // run of this half-wavefront
+        if (q < 0 || q >= L.halves * L.G.ny) return false;
+        y = int(double(q) * L.inv_halves);
+        int h = q - y * L.halves;
+        if (h < 0) { --y; h += L.halves; }
+        else if (h >= L.halves) { ++y; h -= L.halves; }
+        x = (h << 5) + (lane & 31);
+        return x < L.G.nx;
     }
     const int tyi = tile / L.tiles_x, txi = tile - tyi * L.tiles_x;
     x = (txi << L.tw_log2) + (lane & ((1 << L.tw_log2) - 1));
@@ -287,30 +293,18 @@ size_t slot_bytes(const clb_desc& d, size_t* buf_bytes_out, size_t* band_bytes_o
     return d.in_place ? buf + 2 * band + snap : 2 * buf + snap;
 }
 
-// Tile mapping of a lattice whose size class has not been autotuned: row tiles about as wide as the
-// lattice.  (Wrapped rows are the autotuner's choice where they pay: they halve the wavefronts that
-// take the x-wall branch, but where nx is not a multiple of the 64-node chunk their wavefronts
-// straddle chunks and write partial cache lines -- 64 cavities of sides 128-512 ran at 31 GLUPS
-// with wrapped rows and 42 with row tiles.)
-// Default mapping of a two-buffer lattice until the autotuner or the caller sets one: with walls in
-// x, 64-wide rows (on 64 served-style cavities of sides 100-700, MI355X: 47.0 GLUPS FP32 and 42.4 SR
-// against 45.7 and 41.3 with the width-based choice below, which the autotuner matches or beats);
-// periodic in x, by width.
+// Default mapping of a lattice until the autotuner or the caller sets one.  With walls in x: wrapped
+// rows, which put the two x-wall ends of consecutive rows into one wavefront (half the wavefronts
+// that take the wall branch of row tiles) and keep every access line-aligned for any nx.  Measured
+// on the 32 cavities of the served mix (sides 34-864, MI355X): two-buffer SR 41.4 GLUPS wrapped
+// against 38.9 with 64-wide rows, FP32 46.2 against 46.5; in place SR 38.1 against 35.7, FP32
+// 49.4 against 47.2.  Periodic in x: row tiles about as wide as the lattice.  The autotuner
+// cannot time in-place lattices (its timing launches would advance them), so they keep this.
 int default_tw_log2(const clb_desc& d)
 {
-    if (d.west.kind != CLB_PERIODIC) return 6;
+    if (d.west.kind != CLB_PERIODIC) return 0;
+    if (d.in_place) return 6;
     return d.nx <= 96 ? 6 : (d.nx <= 192 ? 7 : 8);
-}
-
-// Default mapping of an in-place lattice, which the autotuner cannot time (its timing launches
-// would advance the lattice): wrapped rows when x has walls and nx is a multiple of 32 (every
-// wavefront then covers whole 32-node halves of chunks, and the two wall ends of a row share one
-// wavefront, halving the wavefronts that run the wall and snapshot branches), else 64-wide rows.
-// Measured on the 512-cavity batch (sides multiples of 32, MI355X): FP32 47.8 GLUPS wrapped, 47.5
-// with 64-wide rows, 46.3 with the two-buffer default widths; SR 44.2, 42.1 and 39.8.
-int default_tw_log2_in_place(const clb_desc& d)
-{
-    return (d.west.kind != CLB_PERIODIC && d.nx % 32 == 0) ? 0 : 6;
 }
 
 int size_class(const clb_desc& d)
@@ -415,10 +409,12 @@ BatchEntry<Real> make_entry(const BatchSlot& s, int tw_log2)
     E.L.cur = s.cur;
     E.L.step = uint32_t(s.steps);
     E.L.tw_log2 = tw_log2;
-    E.L.inv_nx = 1.0 / double(s.desc.nx);
+    E.L.halves = (s.desc.nx + 31) / 32;
+    E.L.inv_halves = 1.0 / double(E.L.halves);
     if (tw_log2 == 0) {
+        // runs -1 .. halves ny - 1, eight per tile
         E.L.tiles_x = 0;
-        E.L.ntiles = int(((long long)s.desc.nx * s.desc.ny + 32 + BNT - 1) / BNT);
+        E.L.ntiles = int(((long long)E.L.halves * s.desc.ny + 1 + BNT / 32 - 1) / (BNT / 32));
     } else {
         const int tw = 1 << tw_log2, th = BNT >> tw_log2;
         E.L.tiles_x = (s.desc.nx + tw - 1) / tw;
@@ -806,8 +802,7 @@ extern "C" int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, 
         s.snap_off = off + 2 * buf_bytes;
     }
     auto it = b->tw_by_class.find(size_class(*desc));
-    s.tw_log2 = desc->in_place ? default_tw_log2_in_place(*desc)
-              : it != b->tw_by_class.end() ? it->second : default_tw_log2(*desc);
+    s.tw_log2 = !desc->in_place && it != b->tw_by_class.end() ? it->second : default_tw_log2(*desc);
     b->slots[free_slot] = s;
     b->dirty = true;
     *slot = free_slot;

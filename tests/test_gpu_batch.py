@@ -58,18 +58,19 @@ def test_batch_equals_alone(gpu, precision, mode):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_sr"])
-@pytest.mark.parametrize("width", [0, 64, 256])
-def test_tile_width_keeps_results(gpu, precision, width):
-    """Every batch tile mapping -- row tiles of width 64 or 256 and wrapped rows (0: row-major
-    tiles shifted by half a wavefront) -- covers each node once with the same per-node update: the
-    lattices match the single-lattice path bitwise, and so do the residuals' snapshots."""
+@pytest.mark.parametrize("width,in_place", [(0, False), (64, False), (256, False), (0, True), (64, True)])
+def test_tile_width_keeps_results(gpu, precision, width, in_place):
+    """Every batch tile mapping -- row tiles of width 64 or 256 and wrapped rows (0: the rows' 32-node
+    runs in row-major order, shifted by one run, two per wavefront) -- covers each node once with the
+    same per-node update: the lattices (two-buffer or in place; sides 45-300, most not multiples of
+    32) match the single-lattice path bitwise, and so do the residuals' snapshots."""
     clb = _clb()
     ws = mixed_workloads()
     b = clb.Batch(16, precision, budget_bytes=256 << 20)
-    slots = [b.add_workload(w) for w in ws]
+    slots = [b.add_workload(w, in_place=in_place) for w in ws]
     for s in slots:
         b.set_tile_width(s, width)
-    print(f"[batch] {precision} width={width}", flush=True)
+    print(f"[batch] {precision} width={width} in_place={in_place}", flush=True)
     b.step(31)
     res = b.residuals()
     b.step(26)
@@ -361,24 +362,25 @@ def test_in_place_lattices_in_a_batch(gpu, precision, mode):
 
 def test_tile_width_and_store_form_read_back(gpu):
     """The per-slot tile width and the batch's store form read back as set, and as the defaults
-    (width by lattice width; ordinary stores for a small FP32 batch)."""
+    (wrapped rows with walls in x, else width by lattice width; ordinary stores for a small FP32
+    batch)."""
     clb = _clb()
     b = clb.Batch(8, "fp32", budget_bytes=64 << 20)
     s0 = b.add_workload(W.cavity(64, Ra=1e4))
     s1 = b.add_workload(W.cavity(150, Ra=1e4))
     s2 = b.add_workload(W.rayleigh_benard(300, 17, Ra=1e4))
-    # two-buffer: 64-wide rows with walls in x, else by width
-    assert [b.tile_width(s) for s in (s0, s1, s2)] == [64, 64, 256]
-    # in-place lattices: wrapped rows when x has walls and nx is a multiple of 32, else 64-wide rows
+    # two-buffer: wrapped rows with walls in x, else by width
+    assert [b.tile_width(s) for s in (s0, s1, s2)] == [0, 0, 256]
+    # in-place lattices: wrapped rows with walls in x, else 64-wide rows
     ip = [b.add_workload(w, in_place=True) for w in (W.cavity(96, Ra=1e4), W.cavity(50, Ra=1e4),
                                                      W.rayleigh_benard(320, 17, Ra=1e4))]
-    assert [b.tile_width(s) for s in ip] == [0, 64, 64]
+    assert [b.tile_width(s) for s in ip] == [0, 0, 64]
     for s in ip:
         b.remove(s)
     assert b.nontemporal is False
-    b.set_tile_width(s1, 0)
+    b.set_tile_width(s1, 128)
     b.set_nontemporal(True)
-    assert b.tile_width(s1) == 0 and b.nontemporal is True
+    assert b.tile_width(s1) == 128 and b.nontemporal is True
     with pytest.raises(clb.CLBError):
         b.tile_width(7)
     b.close()
