@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libclb.so")
 # debug variant for the tests: populations whose source lies beyond a wall are loaded as NaN
 LIB_POISON = os.path.join(HERE, "libclb_poison.so")
-SOURCES = ["clb.hip", "clb_batch.hip"]
+SOURCES = ["clb.hip", "clb_batch.hip", "clb3d.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -236,3 +236,92 @@ def prescribed_walled(nx, ny, seed, u=(0.03, -0.05), kinds=("dirichlet", "adiaba
             "taus": {"tau_nu": 0.8, "tau_alpha": tau_alpha, "g_beta": 0.0},
             "prescribed_u": tuple(u), "u_scale": 1.0,
             "fields": {"rho": np.ones((ny, nx)), "ux": np.full((ny, nx), u[0]), "uy": np.full((ny, nx), u[1]), "T": T}}
+
+
+# ---------------------------------------------------------------------------------------------
+# Three-dimensional workloads (D3Q27/D3Q7 path).  Same conventions, with fields of shape
+# (nz, ny, nx), "u" a triple (u_x, u_y, u_z), periodic x and y, and "z_walls" None (periodic z) or
+# two dicts {"kind": "dirichlet"|"adiabatic", "u": (ux, uy), "T": float} for z = 0 and z = nz - 1;
+# gravity acts along -z.  "taus" carries the relaxation times directly, or "physics" the
+# dimensionless groups, which each side maps with its own parameter routine (nu = (tau_nu - 1/2)/3,
+# alpha = (tau_alpha - 1/2)/4 in three dimensions too).
+
+
+def _wall3(kind, u=(0.0, 0.0), T=0.0):
+    return {"kind": kind, "u": (float(u[0]), float(u[1])), "T": float(T)}
+
+
+def rayleigh_benard_3d(nx=256, ny=256, nz=129, Ra=1e5, Pr=0.71, Ma=0.1, seed=3, amp=1e-3, T_hot=0.5, T_cold=-0.5,
+                       rolls=0.0):
+    """Rayleigh-Benard convection in a layer periodic in x and y: hot bottom wall z = 0 at T_hot,
+    cold top wall z = nz - 1 at T_cold (H = nz - 1), resting walls, T0 the mean.  Starts from the
+    conduction profile with a seeded perturbation: amp dT U(-1, 1) at every interior node.
+
+    rolls > 0 adds two crossed sets of convection rolls of that fraction of u_c = Ma c_s, one pair
+    per 2H along x and along y (k = 2 pi m / n, m = round(n / 2H)): stream functions
+    psi_x = (A / k_x) sin(k_x x) s^2 in the x-z plane and psi_y = (A / (2 k_y)) sin(k_y y) s^2 in the
+    y-z plane, s = sin(pi z / H), so u = (-d psi_x/dz, -d psi_y/dz, d psi_x/dx + d psi_y/dy) is
+    divergence-free and vanishes on the walls; the warm anomaly -0.1 dT cos(k_x x) s rides with
+    the rising fluid."""
+    rng = np.random.default_rng(seed)
+    H = nz - 1
+    dT = T_hot - T_cold
+    T0 = 0.5 * (T_hot + T_cold)
+    z = np.arange(nz, dtype=np.float64)[:, None, None]
+    T = T_hot - dT * z / H + np.zeros((nz, ny, nx))
+    T[1:-1] += amp * dT * rng.uniform(-1.0, 1.0, (nz - 2, ny, nx))
+    u = None
+    if rolls > 0:
+        A = rolls * Ma / math.sqrt(3.0)
+        kx = 2 * math.pi * max(1, round(nx / (2 * H))) / nx
+        ky = 2 * math.pi * max(1, round(ny / (2 * H))) / ny
+        x = np.arange(nx, dtype=np.float64)[None, None, :]
+        y = np.arange(ny, dtype=np.float64)[None, :, None]
+        s = np.sin(math.pi * z / H)
+        ds2 = (math.pi / H) * np.sin(2 * math.pi * z / H)       # d(s^2)/dz
+        ux = -(A / kx) * np.sin(kx * x) * ds2 + 0.0 * y
+        uy = -(0.5 * A / ky) * np.sin(ky * y) * ds2 + 0.0 * x
+        uz = A * np.cos(kx * x) * s * s + 0.5 * A * np.cos(ky * y) * s * s
+        u = (ux, uy, uz)
+        T = T - 0.1 * dT * np.cos(kx * x) * s
+    return {"name": f"rayleigh_benard_3d_{nx}x{ny}x{nz}_Ra{Ra:g}" + (f"_rolls{rolls:g}" if rolls > 0 else ""),
+            "nx": nx, "ny": ny, "nz": nz, "T0": T0,
+            "z_walls": (_wall3("dirichlet", T=T_hot), _wall3("dirichlet", T=T_cold)),
+            "physics": {"Ra": Ra, "Pr": Pr, "Ma": Ma, "H": H, "dT": dT},
+            "fields": {"rho": None, "u": u, "T": T}, "u_scale": Ma / math.sqrt(3.0)}
+
+
+def abc_flow_3d(n=64, A=0.01, tau_nu=0.8, tau_alpha=0.8, T0=0.0):
+    """Arnold-Beltrami-Childress flow (A = B = C) on a periodic n^3 box, k = 2 pi / n: a Beltrami
+    field whose Navier-Stokes solution decays as exp(-nu k^2 t); T = T0, no buoyancy."""
+    k = 2.0 * math.pi / n
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=np.float64),) * 3, indexing="ij")
+    u = (A * (np.sin(k * z) + np.cos(k * y)), A * (np.sin(k * x) + np.cos(k * z)), A * (np.sin(k * y) + np.cos(k * x)))
+    return {"name": f"abc_flow_{n}^3", "nx": n, "ny": n, "nz": n, "T0": T0, "z_walls": None,
+            "taus": {"tau_nu": tau_nu, "tau_alpha": tau_alpha, "g_beta": 0.0},
+            "fields": {"rho": None, "u": u, "T": None}, "k": k, "A": A, "u_scale": 2.0 * A}
+
+
+def random_3d(nx, ny, nz, seed, walls=None, amp_u=0.03, amp_T=0.1, T0=0.0, g_beta=1e-3, tau_nu=0.7,
+              tau_alpha=0.9, body_force=(1e-5, -2e-5, 1.5e-5), relaxation=None):
+    """Random (unsmoothed) fields for parity tests: rho = 1 + 0.01 N(0,1), u = amp_u N(0,1) per
+    component, T = T0 + amp_T N(0,1), from default_rng(seed).  walls: None (periodic z) or a pair of
+    (kind, (ux, uy), T) for the bottom and top walls; wall nodes then start at the wall data."""
+    rng = np.random.default_rng(seed)
+    shp = (nz, ny, nx)
+    rho = 1.0 + 0.01 * rng.standard_normal(shp)
+    u = [amp_u * rng.standard_normal(shp) for _ in range(3)]
+    T = T0 + amp_T * rng.standard_normal(shp)
+    zw = None
+    if walls is not None:
+        zw = tuple(_wall3(k, uw, Tw) for k, uw, Tw in walls)
+        for zi, w in ((0, zw[0]), (nz - 1, zw[1])):
+            u[0][zi], u[1][zi], u[2][zi] = w["u"][0], w["u"][1], 0.0
+            if w["kind"] == "dirichlet":
+                T[zi] = w["T"]
+    out = {"name": f"random_3d_{nx}x{ny}x{nz}_s{seed}" + ("_walls" if walls else ""), "nx": nx, "ny": ny, "nz": nz,
+           "T0": T0, "z_walls": zw, "taus": {"tau_nu": tau_nu, "tau_alpha": tau_alpha, "g_beta": g_beta},
+           "body_force": tuple(body_force), "fields": {"rho": rho, "u": tuple(u), "T": T}, "u_scale": amp_u}
+    if relaxation is not None:
+        out["relaxation"] = dict(relaxation)
+    return out

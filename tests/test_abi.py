@@ -1,5 +1,6 @@
-"""CPU-side checks of the C ABI: the library loads, exports every function include/clb.h declares,
-and rejects invalid descriptions on the host before touching a device.  No compute call is made."""
+"""CPU-side checks of the C ABI: the library loads, exports every function include/clb.h and
+include/clb3d.h declare, and rejects invalid descriptions on the host before touching a device.  No
+compute call is made."""
 import ctypes
 import math
 import os
@@ -10,10 +11,10 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    src = open(os.path.join(ROOT, "include", "clb.h")).read()
+def header_functions(header="clb.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(clb_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(clb3?d?_[a-z_]+)\s*\(", src)))
 
 
 def test_header_declares_the_core_calls():
@@ -25,8 +26,42 @@ def test_header_declares_the_core_calls():
 def test_library_exports_every_declared_symbol():
     from paper_1710_10569_amd import clb
     lib = ctypes.CDLL(clb.LIBPATH)
-    missing = [n for n in header_functions() if not hasattr(lib, n)]
+    names = header_functions("clb.h") + header_functions("clb3d.h")
+    assert "clb3d_create" in names and "clb3d_step" in names
+    missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0, ny=4, nz=4),
+    dict(nx=4, ny=4, nz=2, walls=True),                                   # walls need nz >= 3
+    dict(nx=4, ny=4, nz=4, precision=9),
+    dict(nx=4, ny=4, nz=4, bottom_only=True),                             # one wall, one periodic side
+    dict(nx=4, ny=4, nz=4, walls=True, T=float("nan")),
+    dict(nx=2000, ny=2000, nz=1000),                                      # more than 2e9 nodes
+])
+def test_3d_create_rejects_bad_descriptions_on_host(bad):
+    from paper_1710_10569_amd import clb, clb3d
+    w = ("dirichlet", (0.0, 0.0), bad.get("T", 0.0)) if bad.get("walls") else None
+    d = clb3d.make_desc(bad["nx"], bad["ny"], bad["nz"], bad.get("precision", "fp64"), w, w)
+    if bad.get("bottom_only"):
+        d.bottom.kind = clb3d.CLB3D_DIRICHLET
+    h = ctypes.c_void_p()
+    rc = clb._lib.clb3d_create(ctypes.byref(d), None, ctypes.byref(h))
+    assert rc == clb.CLB_EINVAL and not h.value and clb.last_error()
+    assert clb._lib.clb3d_footprint(ctypes.byref(d)) == 0
+
+
+def test_3d_null_arguments_and_footprint():
+    from paper_1710_10569_amd import clb, clb3d
+    assert clb._lib.clb3d_create(None, None, None) == clb.CLB_EINVAL
+    clb._lib.clb3d_destroy(None)
+    assert clb._lib.clb3d_step(None, 1) == clb.CLB_EINVAL
+    assert clb._lib.clb3d_moments(None, None, None, None) == clb.CLB_EINVAL
+    # two FP32 buffers of 34 populations per node in 64-node chunks, plus FP64 fields and partials
+    fp = clb3d.footprint(256, 256, 129, "fp32_sr", walls=True)
+    n = 256 * 256 * 129
+    assert fp == 2 * 4 * 34 * n + 5 * 8 * n + (n + 255) // 256 * 7 * 8 + 16 * 8
 
 
 def test_params_from_physics_matches_sec33_relations():
