@@ -275,6 +275,50 @@ def field_errors_vs_fp64(clb, W, stream, steps=ERROR_STEPS):
     return out
 
 
+BYTES_PER_SITE_3D = {"fp32": 272, "fp32_sr": 272, "fp64": 544}   # 34 populations read + written
+RB3D_SHAPE = (256, 256, 129)
+
+
+def run_3d(W, steps=200, warmup=10, error_steps=2000, precisions=("fp32", "fp32_sr", "fp64"), stream=None):
+    """The 3D path on a 256 x 256 x 129 Rayleigh-Benard layer (Ra = 1e5, started from convection
+    rolls): steps per precision timed with HIP events, and the FP32 / SR fields against FP64 after
+    error_steps steps."""
+    from paper_1710_10569_amd import clb, clb3d
+    w = W.rayleigh_benard_3d(*RB3D_SHAPE, Ra=1e5, Ma=0.1, seed=3, rolls=0.5)
+    p = w["physics"]
+    w = dict(w, taus=dict(zip(("tau_nu", "tau_alpha", "g_beta"), clb.params_from_physics(p["Ra"], p["Pr"], p["Ma"], p["H"], p["dT"]))))
+    n = RB3D_SHAPE[0] * RB3D_SHAPE[1] * RB3D_SHAPE[2]
+    out = {"workload": w["name"], "sites": n}
+    for prec in precisions:
+        L = clb3d.lattice_from_workload(w, prec, stream=stream)
+        L.step(warmup)
+        L.synchronize()
+        ms = L.time_steps(steps) / steps
+        L.close()
+        gbps = BYTES_PER_SITE_3D[prec] * n / (ms * 1e-3) / 1e9
+        out[prec] = {"MLUPS": n / (ms * 1e-3) / 1e6, "ms_per_step": ms, "steps_timed": steps, "achieved_GBps": gbps,
+                     "frac": gbps / HBM_PEAK_GBPS, "bytes_per_site": BYTES_PER_SITE_3D[prec],
+                     "footprint_GB": clb3d.footprint(*RB3D_SHAPE, prec, walls=True) / 1e9}
+        log(f"[bench] 3D {prec}: {out[prec]['MLUPS']:.0f} MLUPS, {gbps:.0f} GB/s")
+    if error_steps:
+        fields = {}
+        for prec in ("fp64", "fp32_sr", "fp32"):
+            L = clb3d.lattice_from_workload(w, prec, stream=stream)
+            L.step(error_steps)
+            fields[prec] = L.moments()
+            L.close()
+        ref = fields["fp64"]
+        umax = max(float(np.abs(c).max()) for c in ref[1])
+        Tdev = float(np.abs(ref[2] - w["T0"]).max())
+        out["field_error_vs_fp64"] = {"steps": error_steps}
+        for prec in ("fp32_sr", "fp32"):
+            r, u, T = fields[prec]
+            out["field_error_vs_fp64"][prec] = {
+                "u": max(float(np.abs(a - b).max()) for a, b in zip(u, ref[1])) / umax,
+                "T": float(np.abs(T - ref[2]).max()) / Tdev}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +336,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the single-lattice tile shape instead of the library default")
     ap.add_argument("--tile-shape", type=int, default=None, help="force a single-lattice FP32 tile shape")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D Rayleigh-Benard layer")
+    ap.add_argument("--3d-only", dest="only_3d", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS steps of the 3D layer in each precision (for profiling) and exit")
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference kernel for "
                          "scaling hardware byte counters) and exit")
@@ -318,6 +365,10 @@ def main():
         return
     from paper_1710_10569_amd import clb, workloads as W
     stream = torch.cuda.Stream()   # default priority
+    if args.only_3d:
+        print(json.dumps({"rayleigh_benard_3d": run_3d(W, steps=args.only_3d, warmup=2, error_steps=0,
+                                                       stream=stream.cuda_stream)}), flush=True)
+        return
 
     # headline: the 512-cavity batch, FP32 storage with stochastic rounding, grouped launches
     hb = run_batch(clb, W, args.steps, stream.cuda_stream, "fp32_sr", modes=("grouped",), warmup=args.warmup)
@@ -396,6 +447,9 @@ def main():
             result["in_place"][f"{prec}_{wl['nx']}x{wl['ny']}"] = {
                 "value": ri["mlups"], "unit": "MLUPS", "ms_per_step": ri["ms_per_step"], "achieved_GBps": ri["gbps"],
                 "frac": ri["gbps"] / HBM_PEAK_GBPS, "footprint_GB": BYTES_PER_SITE[prec] / 2 * wl["nx"] * wl["ny"] / 1e9}
+    if not args.no_3d:
+        result["rayleigh_benard_3d_256x256x129"] = run_3d(W, stream=stream.cuda_stream)
+        torch.cuda.empty_cache()
     if not args.no_serve:
         result["served_saturated"] = run_serving(clb, W, stream.cuda_stream, lam=math.inf)
         torch.cuda.empty_cache()

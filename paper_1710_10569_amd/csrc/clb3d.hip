@@ -9,9 +9,11 @@
 // step pulls from one and stores into the other; population i of node x is stored at x after
 // collision (f*_i(x)), and pulled by x + e_i.
 //
-// One thread per node, 256-thread workgroups of 64 x 4 nodes in one z plane (so the wall branch
-// is uniform over a workgroup), tiles handed to the eight XCDs in contiguous bands of the
-// (x, y, z) tile order.  Per node and step:
+// One thread per node, 256-thread workgroups of 64 x 4 nodes in one z plane, tiles handed to the
+// eight XCDs in contiguous bands of the (x, y, z) tile order.  The two wall planes and the planes
+// between them are separate launches of the same per-node code, so the interior kernel carries
+// none of the wall step's registers (FP32: 57 VGPRs and 8 waves per SIMD instead of 112 and 4).
+// Per node and step:
 //   pull the 34 populations (z walls: sources beyond the wall are replaced by the wall step);
 //   wall step on z = 0 and z = nz - 1: non-equilibrium extrapolation of all 34 populations from the
 //     inner neighbour, at the node's mass-balance density (known populations + the ones it sent
@@ -57,7 +59,6 @@ struct Geo3 {
     int walls;          // 1: walls on z = 0 and z = nz - 1
     int zk[2];          // bottom, top: CLB3D_DIRICHLET or CLB3D_ADIABATIC
     int nxt, nyt;       // tiles along x and y
-    long long ntiles;
 };
 
 template <typename Real>
@@ -370,19 +371,26 @@ __device__ __forceinline__ void store3(S* __restrict__ dst, long long o, const R
     }
 }
 
-// Tile t of the band-ordered grid -> node of this thread; y is uniform over the wavefront.
-__device__ __forceinline__ bool node_of(const Geo3& G, int& x, int& y, int& z)
+// The planes one launch covers: z0 .. z0 + count - 1, or (walls_only) the two wall planes z = 0
+// and z = nz - 1.
+struct Planes {
+    int z0, count, walls_only;
+    long long ntiles;   // tiles of the launch: nxt nyt count
+};
+
+// Tile t of the band-ordered grid -> node of this thread; y and z are uniform over the wavefront.
+__device__ __forceinline__ bool node_of(const Geo3& G, const Planes& Z, int& x, int& y, int& z)
 {
     const unsigned q = gridDim.x >> 3;
     const long long t = (long long)(blockIdx.x & 7u) * q + (blockIdx.x >> 3);
-    if (t >= G.ntiles) return false;
+    if (t >= Z.ntiles) return false;
     const long long txy = (long long)G.nxt * G.nyt;
-    z = int(t / txy);
-    const int r = int(t - (long long)z * txy);
+    const int p = int(t / txy);
+    const int r = int(t - (long long)p * txy);
     const int ty = r / G.nxt, tx = r - ty * G.nxt;
     x = tx * TX + int(threadIdx.x & (TX - 1));
     y = __builtin_amdgcn_readfirstlane(ty * TY + int(threadIdx.x >> 6));
-    z = __builtin_amdgcn_readfirstlane(z);
+    z = __builtin_amdgcn_readfirstlane(Z.walls_only ? (p == 0 ? 0 : G.nz - 1) : Z.z0 + p);
     return x < G.nx && y < G.ny;
 }
 
@@ -392,14 +400,18 @@ __host__ __device__ __forceinline__ int wall_of(const Geo3& G, int z)
 }
 
 // The whole update of node (x, y, z): pull, wall step (wall planes), macroscopic, both collisions;
-// the 34 post-collision populations are left in f, g.
-template <typename S, typename Real>
+// the 34 post-collision populations are left in f, g.  WALL: 1 the node lies on a wall plane,
+// 0 it does not, -1 test at run time.  (The step launches the wall planes and the others
+// separately, so that the interior kernel carries none of the wall step's registers.)
+template <int WALL, typename S, typename Real>
 __host__ __device__ __forceinline__ void update_node3(const S* __restrict__ src, const Geo3& G, const Par3<Real>& P, int x, int y,
                                                       int z, Real f[NQ], Real g[NTQ])
 {
     pull3(src, G, x, y, z, f, g);
-    const int w = wall_of(G, z);
-    if (w >= 0) wall_step3(src, G, P, x, y, z, w, f, g);
+    if (WALL != 0) {
+        const int w = wall_of(G, z);
+        if (WALL == 1 || w >= 0) wall_step3(src, G, P, x, y, z, w, f, g);
+    }
     const Macro3<Real> m = macro3(f, g, P);
     collide27(f, m, P);
     collide7(g, m, P);
@@ -423,22 +435,24 @@ __host__ __device__ __forceinline__ void moments_node3(const S* __restrict__ src
     out[4 * n + k] = double(P.TR) + double(m.dT);
 }
 
-template <typename S, typename Real>
+// One step over the planes of Z; WALL: Z is the two wall planes (1) or planes without walls (0).
+template <typename S, typename Real, int WALL>
 __global__ __launch_bounds__(BNT3) void step3_kernel(const S* __restrict__ src, S* __restrict__ dst, Geo3 G, Par3<Real> P,
-                                                    uint32_t key)
+                                                    Planes Z, uint32_t key)
 {
     int x, y, z;
-    if (!node_of(G, x, y, z)) return;
+    if (!node_of(G, Z, x, y, z)) return;
     Real f[NQ], g[NTQ];
-    update_node3(src, G, P, x, y, z, f, g);
+    update_node3<WALL>(src, G, P, x, y, z, f, g);
     store3<S, Real>(dst, row_base(G, y, z) + col_of(x), f, g, key, uint32_t(((long long)z * G.ny + y) * G.nx + x));
 }
 
 template <typename S, typename Real>
-__global__ __launch_bounds__(BNT3) void moments3_kernel(const S* __restrict__ src, Geo3 G, Par3<Real> P, double* __restrict__ out)
+__global__ __launch_bounds__(BNT3) void moments3_kernel(const S* __restrict__ src, Geo3 G, Par3<Real> P, Planes Z,
+                                                       double* __restrict__ out)
 {
     int x, y, z;
-    if (!node_of(G, x, y, z)) return;
+    if (!node_of(G, Z, x, y, z)) return;
     moments_node3(src, G, P, x, y, z, out);
 }
 
@@ -492,10 +506,10 @@ __host__ __device__ __forceinline__ void init_node3(S* __restrict__ dst, const G
 }
 
 template <typename S, typename Real>
-__global__ __launch_bounds__(BNT3) void init3_kernel(S* __restrict__ dst, Geo3 G, Par3<Real> P, const double* __restrict__ fl)
+__global__ __launch_bounds__(BNT3) void init3_kernel(S* __restrict__ dst, Geo3 G, Par3<Real> P, Planes Z, const double* __restrict__ fl)
 {
     int x, y, z;
-    if (!node_of(G, x, y, z)) return;
+    if (!node_of(G, Z, x, y, z)) return;
     init_node3(dst, G, P, fl, x, y, z);
 }
 
@@ -611,7 +625,6 @@ Geo3 make_geo3(const clb3d_desc& d)
     G.zk[0] = d.bottom.kind; G.zk[1] = d.top.kind;
     G.nxt = (d.nx + TX - 1) / TX;
     G.nyt = (d.ny + TY - 1) / TY;
-    G.ntiles = (long long)G.nxt * G.nyt * d.nz;
     return G;
 }
 
@@ -634,7 +647,18 @@ Par3<Real> make_par3(const clb3d_lattice* h)
     return P;
 }
 
-unsigned grid_of(const Geo3& G) { return unsigned((G.ntiles + 7) / 8 * 8); }
+unsigned grid_of(const Planes& Z) { return unsigned((Z.ntiles + 7) / 8 * 8); }
+
+Planes planes(const Geo3& G, int z0, int count, int walls_only)
+{
+    Planes Z;
+    Z.z0 = z0;
+    Z.count = count;
+    Z.walls_only = walls_only;
+    Z.ntiles = (long long)G.nxt * G.nyt * count;
+    return Z;
+}
+Planes all_planes(const Geo3& G) { return planes(G, 0, G.nz, 0); }
 
 size_t buffer_bytes3(const clb3d_desc& d)
 {
@@ -650,12 +674,22 @@ int launch_step(clb3d_lattice* h, long long n)
 {
     const Geo3 G = make_geo3(h->desc);
     const Par3<Real> P = make_par3<Real>(h);
+    // with walls: the two wall planes, then the planes between them (independent nodes of the same
+    // step); periodic z: every plane in one launch
+    const Planes Zw = planes(G, 0, 2, 1);
+    const Planes Zi = G.walls ? planes(G, 1, G.nz - 2, 0) : all_planes(G);
     for (long long s = 0; s < n; ++s) {
         const S* src = static_cast<const S*>(h->buf[h->cur]);
         S* dst = static_cast<S*>(h->buf[h->cur ^ 1]);
-        hipLaunchKernelGGL((step3_kernel<S, Real>), dim3(grid_of(G)), dim3(BNT3), 0, h->stream, src, dst, G, P,
-                           step_key(uint32_t(h->steps)));
-        CLB_HIP(hipGetLastError());
+        const uint32_t key = step_key(uint32_t(h->steps));
+        if (G.walls) {
+            hipLaunchKernelGGL((step3_kernel<S, Real, 1>), dim3(grid_of(Zw)), dim3(BNT3), 0, h->stream, src, dst, G, P, Zw, key);
+            CLB_HIP(hipGetLastError());
+        }
+        if (Zi.count > 0) {
+            hipLaunchKernelGGL((step3_kernel<S, Real, 0>), dim3(grid_of(Zi)), dim3(BNT3), 0, h->stream, src, dst, G, P, Zi, key);
+            CLB_HIP(hipGetLastError());
+        }
         h->cur ^= 1;
         ++h->steps;
     }
@@ -675,8 +709,9 @@ template <typename S, typename Real>
 int launch_moments(clb3d_lattice* h)
 {
     const Geo3 G = make_geo3(h->desc);
-    hipLaunchKernelGGL((moments3_kernel<S, Real>), dim3(grid_of(G)), dim3(BNT3), 0, h->stream,
-                       static_cast<const S*>(h->buf[h->cur]), G, make_par3<Real>(h), h->d_fields);
+    const Planes Z = all_planes(G);
+    hipLaunchKernelGGL((moments3_kernel<S, Real>), dim3(grid_of(Z)), dim3(BNT3), 0, h->stream,
+                       static_cast<const S*>(h->buf[h->cur]), G, make_par3<Real>(h), Z, h->d_fields);
     CLB_HIP(hipGetLastError());
     return CLB_OK;
 }
@@ -694,8 +729,9 @@ template <typename S, typename Real>
 int launch_init(clb3d_lattice* h)
 {
     const Geo3 G = make_geo3(h->desc);
-    hipLaunchKernelGGL((init3_kernel<S, Real>), dim3(grid_of(G)), dim3(BNT3), 0, h->stream,
-                       static_cast<S*>(h->buf[h->cur]), G, make_par3<Real>(h), h->d_fields);
+    const Planes Z = all_planes(G);
+    hipLaunchKernelGGL((init3_kernel<S, Real>), dim3(grid_of(Z)), dim3(BNT3), 0, h->stream,
+                       static_cast<S*>(h->buf[h->cur]), G, make_par3<Real>(h), Z, h->d_fields);
     CLB_HIP(hipGetLastError());
     return CLB_OK;
 }
