@@ -277,6 +277,31 @@ def field_errors_vs_fp64(clb, W, stream, steps=ERROR_STEPS):
 
 BYTES_PER_SITE_3D = {"fp32": 272, "fp32_sr": 272, "fp64": 544}   # 34 populations read + written
 RB3D_SHAPE = (256, 256, 129)
+TRAFFIC_FILE_3D = os.path.join(ROOT, "profiles", "traffic_step3_kernel_rb3d_256x256x129.json")
+
+
+def kernel_source_hash_3d():
+    """Hash of the sources that define the 3D step kernels and of the build flags."""
+    h = hashlib.sha256()
+    for rel in ("paper_1710_10569_amd/csrc/clb3d.hip", "paper_1710_10569_amd/csrc/clb_device.h",
+                "paper_1710_10569_amd/build.py"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(rel.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic_3d(precision, sites):
+    """HBM bytes per 3D step (wall-plane and interior launches) from the committed counter summary,
+    if it was taken on the current kernel sources and the same layer; else None."""
+    try:
+        with open(TRAFFIC_FILE_3D) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash_3d() or t.get("sites") != sites:
+        return None
+    return t.get("precisions", {}).get(precision, {}).get("bytes_per_step")
 
 
 def run_3d(W, steps=200, warmup=10, error_steps=2000, precisions=("fp32", "fp32_sr", "fp64"), stream=None):
@@ -298,6 +323,7 @@ def run_3d(W, steps=200, warmup=10, error_steps=2000, precisions=("fp32", "fp32_
         gbps = BYTES_PER_SITE_3D[prec] * n / (ms * 1e-3) / 1e9
         out[prec] = {"MLUPS": n / (ms * 1e-3) / 1e6, "ms_per_step": ms, "steps_timed": steps, "achieved_GBps": gbps,
                      "frac": gbps / HBM_PEAK_GBPS, "bytes_per_site": BYTES_PER_SITE_3D[prec],
+                     "traffic": measured_traffic_3d(prec, n),
                      "footprint_GB": clb3d.footprint(*RB3D_SHAPE, prec, walls=True) / 1e9}
         log(f"[bench] 3D {prec}: {out[prec]['MLUPS']:.0f} MLUPS, {gbps:.0f} GB/s")
     if error_steps:
