@@ -190,6 +190,21 @@ int clb_diagnostics_noalloc(clb_lattice* h, clb_diag* out);
  * may be NULL.  Synchronises the stream. */
 int clb_get_populations(clb_lattice* h, double* f, double* g);
 
+/* Checkpoint / resume (for callers that must stop and continue a run, possibly in another process on
+ * the same library build).  clb_checkpoint_size writes the bytes a checkpoint of this lattice takes;
+ * clb_checkpoint_save copies into the caller's host buffer `host` (at least that many bytes) a
+ * header -- description, parameters, step count, whether a residual snapshot exists -- followed by
+ * the raw device state: the current population buffer (in place: the buffer and its two
+ * wall-band snapshot copies) and the FP64 residual snapshot of clb_diagnostics.  Synchronises.
+ * clb_checkpoint_load restores such a blob into a lattice created with the same description (every
+ * field of clb_desc equal), replacing its state, parameters and step count; stepping on then gives
+ * bitwise the results of the run that was not interrupted (the stochastic rounding is keyed by the
+ * step count).  Errors: CLB_EINVAL for NULL arguments, a buffer that is too small, or a blob of
+ * another library version or lattice description; CLB_EDEVICE for a failed copy. */
+int clb_checkpoint_size(clb_lattice* h, size_t* bytes);
+int clb_checkpoint_save(clb_lattice* h, void* host, size_t bytes);
+int clb_checkpoint_load(clb_lattice* h, const void* host, size_t bytes);
+
 /* Physical parameters -> relaxation times (Sec. 3.3): nu = Ma c_s H sqrt(Pr/Ra), alpha = nu/Pr,
  * g*beta = Ra nu alpha / (dT H^3), tau_nu = 3 nu + 1/2, tau_alpha = 4 alpha + 1/2.
  * Host-only.  Errors: CLB_EINVAL for non-positive or non-finite inputs or NULL outputs. */

@@ -86,7 +86,8 @@ int clb3d_set_body_force(clb3d_lattice* h, double Fx, double Fy, double Fz);
  * step count. */
 int clb3d_init(clb3d_lattice* h, const double* rho, const double* u, const double* T);
 
-/* Advance n >= 0 steps (one kernel launch per step); does not block. */
+/* Advance n >= 0 steps (per step one launch, or two with walls: the wall planes and the rest); does
+ * not block. */
 int clb3d_step(clb3d_lattice* h, long long n);
 
 /* rho, u (three planes), T of the current time into host arrays of n = nx ny nz values (any may be
@@ -105,6 +106,15 @@ int clb3d_synchronize(clb3d_lattice* h);
 /* Bytes of device memory a lattice of this description holds (two population buffers and the
  * FP64 field and reduction buffers); 0 for an invalid description. */
 size_t clb3d_footprint(const clb3d_desc* desc);
+
+/* Checkpoint / resume, as clb_checkpoint_* of clb.h: the size of the blob; a copy of the header
+ * (description, parameters, step count) and the current population buffer into the caller's host
+ * buffer (synchronises); and its restore into a lattice of the same description, after which
+ * stepping on gives bitwise the uninterrupted run.  Errors: CLB_EINVAL (NULL, too small, another
+ * version or description), CLB_EDEVICE. */
+int clb3d_checkpoint_size(clb3d_lattice* h, size_t* bytes);
+int clb3d_checkpoint_save(clb3d_lattice* h, void* host, size_t bytes);
+int clb3d_checkpoint_load(clb3d_lattice* h, const void* host, size_t bytes);
 
 /* Destroy the lattice and free its memory (NULL-safe). */
 void clb3d_destroy(clb3d_lattice* h);

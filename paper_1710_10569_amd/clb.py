@@ -83,6 +83,9 @@ _sig("clb_set_prescribed_velocity", ctypes.c_int, [_H, ctypes.c_double, ctypes.c
 _sig("clb_diagnostics", ctypes.c_int, [_H, ctypes.c_int, ctypes.POINTER(clb_diag)])
 _sig("clb_diagnostics_noalloc", ctypes.c_int, [_H, ctypes.POINTER(clb_diag)])
 _sig("clb_get_populations", ctypes.c_int, [_H, _dp, _dp])
+_sig("clb_checkpoint_size", ctypes.c_int, [_H, ctypes.POINTER(ctypes.c_size_t)])
+_sig("clb_checkpoint_save", ctypes.c_int, [_H, _vp, ctypes.c_size_t])
+_sig("clb_checkpoint_load", ctypes.c_int, [_H, _vp, ctypes.c_size_t])
 _sig("clb_params_from_physics", ctypes.c_int, [ctypes.c_double] * 5 + [_dp, _dp, _dp])
 _sig("clb_time_steps", ctypes.c_int, [_H, ctypes.c_longlong, _dp])
 _sig("clb_synchronize", ctypes.c_int, [_H])
@@ -275,6 +278,28 @@ class Lattice:
         if rc != CLB_OK and (rc != CLB_EDIVERGED or raise_on_diverged):
             raise CLBError(rc, last_error())
         return d.as_dict()
+
+    def checkpoint(self):
+        """clb_checkpoint_save: the lattice's state, parameters and step count as bytes."""
+        return checkpoint_blob(_lib.clb_checkpoint_size, _lib.clb_checkpoint_save, self._h)
+
+    def restore(self, blob):
+        """clb_checkpoint_load: continue from a checkpoint of a lattice of the same description."""
+        restore_blob(_lib.clb_checkpoint_load, self._h, blob)
+
+
+def checkpoint_blob(size_fn, save_fn, h):
+    n = ctypes.c_size_t()
+    _check(size_fn(h, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(save_fn(h, ctypes.cast(buf, _vp), n.value))
+    return buf.raw
+
+
+def restore_blob(load_fn, h, blob):
+    b = bytes(blob)
+    buf = ctypes.create_string_buffer(b, len(b))
+    _check(load_fn(h, ctypes.cast(buf, _vp), len(b)))
 
 
 def lattice_from_workload(w, precision="fp64", stream=None, in_place=False):

@@ -59,6 +59,9 @@ _sig("clb3d_time_steps", ctypes.c_int, [_H, ctypes.c_longlong, _dp])
 _sig("clb3d_synchronize", ctypes.c_int, [_H])
 _sig("clb3d_footprint", ctypes.c_size_t, [ctypes.POINTER(clb3d_desc)])
 _sig("clb3d_destroy", None, [_H])
+_sig("clb3d_checkpoint_size", ctypes.c_int, [_H, ctypes.POINTER(ctypes.c_size_t)])
+_sig("clb3d_checkpoint_save", ctypes.c_int, [_H, _vp, ctypes.c_size_t])
+_sig("clb3d_checkpoint_load", ctypes.c_int, [_H, _vp, ctypes.c_size_t])
 
 
 def make_desc(nx, ny, nz, precision="fp32_sr", bottom=None, top=None, T0=0.0):
@@ -148,6 +151,14 @@ class Lattice3D:
 
     def synchronize(self):
         _check(_lib.clb3d_synchronize(self._h))
+
+    def checkpoint(self):
+        """clb3d_checkpoint_save: the lattice's state, parameters and step count as bytes."""
+        return _clb.checkpoint_blob(_lib.clb3d_checkpoint_size, _lib.clb3d_checkpoint_save, self._h)
+
+    def restore(self, blob):
+        """clb3d_checkpoint_load: continue from a checkpoint of a lattice of the same description."""
+        _clb.restore_blob(_lib.clb3d_checkpoint_load, self._h, blob)
 
 
 def lattice_from_workload(w, precision="fp32_sr", stream=None):

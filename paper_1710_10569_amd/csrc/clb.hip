@@ -708,3 +708,118 @@ extern "C" int clb_diagnostics_noalloc(clb_lattice* h, clb_diag* out)
     }
     return CLB_OK;
 }
+
+// ---------------------------------------------------------------------------------------------
+// Checkpoint / resume: a host blob holding a header (description, parameters, step count, which
+// buffer is current, whether a residual snapshot exists) followed by the raw device state -- the
+// current population buffer (in place: the single buffer and its two snapshot copies) and the FP64
+// residual snapshot.  Restoring it into a lattice of the same description and stepping on gives
+// bitwise the run that was not interrupted (the stochastic rounding is keyed by the step count,
+// which the blob carries).
+
+namespace {
+
+constexpr char kCkptMagic[8] = {'C', 'L', 'B', '2', 'D', 'C', 'K', 'P'};
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    clb_desc desc;
+    clb::Params par;
+    long long steps;
+    int cur, has_snap;
+    uint64_t pop_bytes, band_bytes, rsnap_bytes;
+};
+
+bool same_edge(const clb_edge& a, const clb_edge& b) { return a.kind == b.kind && a.ux == b.ux && a.uy == b.uy && a.T == b.T; }
+bool same_desc(const clb_desc& a, const clb_desc& b)
+{
+    return a.nx == b.nx && a.ny == b.ny && a.precision == b.precision && a.T0 == b.T0 && a.prescribed_u == b.prescribed_u &&
+           a.in_place == b.in_place && same_edge(a.west, b.west) && same_edge(a.east, b.east) && same_edge(a.south, b.south) &&
+           same_edge(a.north, b.north);
+}
+
+CkptHeader ckpt_header(const clb_lattice* h)
+{
+    CkptHeader H;
+    std::memset(&H, 0, sizeof H);
+    std::memcpy(H.magic, kCkptMagic, sizeof H.magic);
+    H.version = kCkptVersion;
+    H.header_bytes = uint32_t(sizeof(CkptHeader));
+    H.desc = h->desc;
+    H.par = h->par;
+    H.steps = h->steps;
+    H.cur = h->cur;
+    H.has_snap = h->has_snap ? 1 : 0;
+    H.pop_bytes = h->buf_bytes;
+    H.band_bytes = h->desc.in_place ? 2 * uint64_t(snap_elems(h->desc.nx, h->desc.ny)) * elem_bytes(h->desc.precision) : 0;
+    H.rsnap_bytes = h->has_snap ? 3 * uint64_t(h->desc.nx) * h->desc.ny * sizeof(double) : 0;
+    return H;
+}
+
+}  // namespace
+
+extern "C" int clb_checkpoint_size(clb_lattice* h, size_t* bytes)
+{
+    clear_error();
+    if (!h || !bytes) { set_error("NULL argument"); return CLB_EINVAL; }
+    const CkptHeader H = ckpt_header(h);
+    *bytes = sizeof(CkptHeader) + H.pop_bytes + H.band_bytes + H.rsnap_bytes;
+    return CLB_OK;
+}
+
+extern "C" int clb_checkpoint_save(clb_lattice* h, void* host, size_t bytes)
+{
+    clear_error();
+    if (!h || !host) { set_error("NULL argument"); return CLB_EINVAL; }
+    const CkptHeader H = ckpt_header(h);
+    const size_t need = sizeof(CkptHeader) + H.pop_bytes + H.band_bytes + H.rsnap_bytes;
+    if (bytes < need) { set_error("checkpoint buffer holds %zu bytes, %zu needed", bytes, need); return CLB_EINVAL; }
+    char* p = static_cast<char*>(host);
+    std::memcpy(p, &H, sizeof H);
+    p += sizeof H;
+    CLB_HIP(hipMemcpyAsync(p, h->desc.in_place ? h->buf[0] : h->buf[h->cur], H.pop_bytes, hipMemcpyDeviceToHost, h->stream));
+    p += H.pop_bytes;
+    if (H.band_bytes) CLB_HIP(hipMemcpyAsync(p, h->snap, H.band_bytes, hipMemcpyDeviceToHost, h->stream));
+    p += H.band_bytes;
+    if (H.rsnap_bytes) CLB_HIP(hipMemcpyAsync(p, h->d_snap, H.rsnap_bytes, hipMemcpyDeviceToHost, h->stream));
+    CLB_HIP(hipStreamSynchronize(h->stream));
+    return CLB_OK;
+}
+
+extern "C" int clb_checkpoint_load(clb_lattice* h, const void* host, size_t bytes)
+{
+    clear_error();
+    if (!h || !host) { set_error("NULL argument"); return CLB_EINVAL; }
+    CkptHeader H;
+    if (bytes < sizeof H) { set_error("checkpoint too short"); return CLB_EINVAL; }
+    std::memcpy(&H, host, sizeof H);
+    if (std::memcmp(H.magic, kCkptMagic, sizeof H.magic) != 0 || H.version != kCkptVersion ||
+        H.header_bytes != sizeof(CkptHeader)) {
+        set_error("not a checkpoint of this library's 2D lattices (magic, version or header size differ)");
+        return CLB_EINVAL;
+    }
+    if (!same_desc(H.desc, h->desc)) { set_error("checkpoint was taken on a lattice of another description"); return CLB_EINVAL; }
+    const CkptHeader mine = ckpt_header(h);
+    if (H.pop_bytes != mine.pop_bytes || H.band_bytes != mine.band_bytes ||
+        (H.has_snap && H.rsnap_bytes != 3 * uint64_t(h->desc.nx) * h->desc.ny * sizeof(double)) || (!H.has_snap && H.rsnap_bytes)) {
+        set_error("checkpoint sizes do not match the lattice");
+        return CLB_EINVAL;
+    }
+    if (bytes < sizeof H + H.pop_bytes + H.band_bytes + H.rsnap_bytes) { set_error("checkpoint truncated"); return CLB_EINVAL; }
+    const size_t n = size_t(h->desc.nx) * h->desc.ny;
+    if (H.has_snap && !h->d_snap) CLB_HIP(hipMalloc((void**)&h->d_snap, 3 * n * sizeof(double)));
+    const char* p = static_cast<const char*>(host) + sizeof H;
+    CLB_HIP(hipMemcpyAsync(h->buf[0], p, H.pop_bytes, hipMemcpyHostToDevice, h->stream));
+    p += H.pop_bytes;
+    if (H.band_bytes) CLB_HIP(hipMemcpyAsync(h->snap, p, H.band_bytes, hipMemcpyHostToDevice, h->stream));
+    p += H.band_bytes;
+    if (H.rsnap_bytes) CLB_HIP(hipMemcpyAsync(h->d_snap, p, H.rsnap_bytes, hipMemcpyHostToDevice, h->stream));
+    CLB_HIP(hipStreamSynchronize(h->stream));
+    h->par = H.par;
+    h->steps = H.steps;
+    h->cur = 0;                // the saved current buffer now sits in buf[0]
+    h->has_snap = H.has_snap != 0;
+    return CLB_OK;
+}

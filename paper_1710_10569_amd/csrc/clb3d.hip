@@ -29,6 +29,7 @@
 #include "clb_internal.h"
 #include "../../include/clb3d.h"
 
+#include <cstring>
 #include <new>
 #include <vector>
 
@@ -976,5 +977,97 @@ extern "C" int clb3d_synchronize(clb3d_lattice* h)
     CLB_HIP(hipSetDevice(h->device));
     CLB_HIP(hipStreamSynchronize(h->stream));
     CLB_HIP(hipGetLastError());
+    return CLB_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Checkpoint / resume of a 3D lattice: header (description, parameters, step count) and the
+// current population buffer.  Restoring it into a lattice of the same description and stepping on
+// gives bitwise the uninterrupted run.
+
+namespace {
+
+constexpr char kCkpt3Magic[8] = {'C', 'L', 'B', '3', 'D', 'C', 'K', 'P'};
+constexpr uint32_t kCkpt3Version = 1;
+
+struct Ckpt3Header {
+    char magic[8];
+    uint32_t version, header_bytes;
+    clb3d_desc desc;
+    double tau_nu, tau_alpha, g_beta, s_b, s3, s4, s5, s6, lam2, Fv[3];
+    long long steps;
+    uint64_t pop_bytes;
+};
+
+bool same_wall3(const clb3d_wall& a, const clb3d_wall& b) { return a.kind == b.kind && a.ux == b.ux && a.uy == b.uy && a.T == b.T; }
+bool same_desc3(const clb3d_desc& a, const clb3d_desc& b)
+{
+    return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.precision == b.precision && a.T0 == b.T0 &&
+           same_wall3(a.bottom, b.bottom) && same_wall3(a.top, b.top);
+}
+
+Ckpt3Header ckpt3_header(const clb3d_lattice* h)
+{
+    Ckpt3Header H;
+    std::memset(&H, 0, sizeof H);
+    std::memcpy(H.magic, kCkpt3Magic, sizeof H.magic);
+    H.version = kCkpt3Version;
+    H.header_bytes = uint32_t(sizeof(Ckpt3Header));
+    H.desc = h->desc;
+    H.tau_nu = h->tau_nu; H.tau_alpha = h->tau_alpha; H.g_beta = h->g_beta;
+    H.s_b = h->s_b; H.s3 = h->s3; H.s4 = h->s4; H.s5 = h->s5; H.s6 = h->s6; H.lam2 = h->lam2;
+    for (int i = 0; i < 3; ++i) H.Fv[i] = h->Fv[i];
+    H.steps = h->steps;
+    H.pop_bytes = h->buf_bytes;
+    return H;
+}
+
+}  // namespace
+
+extern "C" int clb3d_checkpoint_size(clb3d_lattice* h, size_t* bytes)
+{
+    clear_error();
+    if (!h || !bytes) { set_error("NULL argument"); return CLB_EINVAL; }
+    *bytes = sizeof(Ckpt3Header) + h->buf_bytes;
+    return CLB_OK;
+}
+
+extern "C" int clb3d_checkpoint_save(clb3d_lattice* h, void* host, size_t bytes)
+{
+    clear_error();
+    if (!h || !host) { set_error("NULL argument"); return CLB_EINVAL; }
+    const Ckpt3Header H = ckpt3_header(h);
+    const size_t need = sizeof H + H.pop_bytes;
+    if (bytes < need) { set_error("checkpoint buffer holds %zu bytes, %zu needed", bytes, need); return CLB_EINVAL; }
+    CLB_HIP(hipSetDevice(h->device));
+    std::memcpy(host, &H, sizeof H);
+    CLB_HIP(hipMemcpyAsync(static_cast<char*>(host) + sizeof H, h->buf[h->cur], H.pop_bytes, hipMemcpyDeviceToHost, h->stream));
+    CLB_HIP(hipStreamSynchronize(h->stream));
+    return CLB_OK;
+}
+
+extern "C" int clb3d_checkpoint_load(clb3d_lattice* h, const void* host, size_t bytes)
+{
+    clear_error();
+    if (!h || !host) { set_error("NULL argument"); return CLB_EINVAL; }
+    Ckpt3Header H;
+    if (bytes < sizeof H) { set_error("checkpoint too short"); return CLB_EINVAL; }
+    std::memcpy(&H, host, sizeof H);
+    if (std::memcmp(H.magic, kCkpt3Magic, sizeof H.magic) != 0 || H.version != kCkpt3Version ||
+        H.header_bytes != sizeof(Ckpt3Header)) {
+        set_error("not a checkpoint of this library's 3D lattices (magic, version or header size differ)");
+        return CLB_EINVAL;
+    }
+    if (!same_desc3(H.desc, h->desc)) { set_error("checkpoint was taken on a lattice of another description"); return CLB_EINVAL; }
+    if (H.pop_bytes != h->buf_bytes) { set_error("checkpoint sizes do not match the lattice"); return CLB_EINVAL; }
+    if (bytes < sizeof H + H.pop_bytes) { set_error("checkpoint truncated"); return CLB_EINVAL; }
+    CLB_HIP(hipSetDevice(h->device));
+    CLB_HIP(hipMemcpyAsync(h->buf[0], static_cast<const char*>(host) + sizeof H, H.pop_bytes, hipMemcpyHostToDevice, h->stream));
+    CLB_HIP(hipStreamSynchronize(h->stream));
+    h->tau_nu = H.tau_nu; h->tau_alpha = H.tau_alpha; h->g_beta = H.g_beta;
+    h->s_b = H.s_b; h->s3 = H.s3; h->s4 = H.s4; h->s5 = H.s5; h->s6 = H.s6; h->lam2 = H.lam2;
+    for (int i = 0; i < 3; ++i) h->Fv[i] = H.Fv[i];
+    h->steps = H.steps;
+    h->cur = 0;
     return CLB_OK;
 }

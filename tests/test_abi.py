@@ -52,6 +52,16 @@ def test_3d_create_rejects_bad_descriptions_on_host(bad):
     assert clb._lib.clb3d_footprint(ctypes.byref(d)) == 0
 
 
+def test_checkpoint_calls_reject_null_arguments():
+    from paper_1710_10569_amd import clb
+    n = ctypes.c_size_t()
+    for fn in (clb._lib.clb_checkpoint_size, clb._lib.clb3d_checkpoint_size):
+        assert fn(None, ctypes.byref(n)) == clb.CLB_EINVAL
+    for fn in (clb._lib.clb_checkpoint_save, clb._lib.clb_checkpoint_load, clb._lib.clb3d_checkpoint_save,
+               clb._lib.clb3d_checkpoint_load):
+        assert fn(None, None, 0) == clb.CLB_EINVAL
+
+
 def test_3d_null_arguments_and_footprint():
     from paper_1710_10569_amd import clb, clb3d
     assert clb._lib.clb3d_create(None, None, None) == clb.CLB_EINVAL
