@@ -92,8 +92,9 @@ __device__ __forceinline__ bool batch_node(const BatchLat& L, int tile, int lane
 }
 
 // AA: the batch holds in-place lattices (a separate instantiation, so that batches without them keep
-// the register budget of the two-buffer update alone).
-template <typename S, typename Real, bool DEV, bool NT, bool AA>
+// the register budget of the two-buffer update alone).  UNIT: every lattice has s_b = s3 = s4 =
+// lambda2 = 1 (the collision skips the moments those rates send to equilibrium; two-buffer batches).
+template <typename S, typename Real, bool DEV, bool NT, bool AA, bool UNIT = false>
 __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntry<Real>& E, int tile, int s)
 {
     int x, y;
@@ -114,10 +115,10 @@ __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntr
     const bool c = (E.L.cur ^ (s & 1)) != 0;
     const long long o_src = c ? E.L.off[1] : E.L.off[0];
     const long long o_dst = c ? E.L.off[0] : E.L.off[1];
-    node_update<S, Real, DEV, NT>(pool + o_src, pool + o_dst, E.L.G, E.P, x, y, step_key(E.L.step + uint32_t(s)));
+    node_update<S, Real, DEV, NT, UNIT>(pool + o_src, pool + o_dst, E.L.G, E.P, x, y, step_key(E.L.step + uint32_t(s)));
 }
 
-template <typename S, typename Real, bool DEV, bool NT, bool AA>
+template <typename S, typename Real, bool DEV, bool NT, bool AA, bool UNIT = false>
 __global__ __launch_bounds__(BNT) void batch_step_kernel(S* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
                                                        const TileRef* __restrict__ tiles, int tile_base, int ntiles,
                                                        int s)
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(BNT) void batch_step_kernel(S* __restrict__ pool, c
     if (t >= ntiles) return;
     const TileRef r = tiles[tile_base + t];
     const BatchEntry<Real> E = lats[r.lat];
-    batch_tile<S, Real, DEV, NT, AA>(pool, E, r.tile, s);
+    batch_tile<S, Real, DEV, NT, AA, UNIT>(pool, E, r.tile, s);
 }
 
 // After a call of nsteps steps: flip the current-buffer index of every listed slot if nsteps is
@@ -355,6 +356,7 @@ struct clb_batch {
     bool nontemporal = false;
     bool nt_chosen = false;               // store form set by the caller or the autotuner
     bool has_aa = false;                  // some resident lattice streams in place
+    bool unit_rates = false;              // every resident lattice has s_b = s3 = s4 = lambda2 = 1
 };
 
 namespace {
@@ -435,12 +437,14 @@ int upload_tables(clb_batch* b)
     std::vector<int> active;
     size_t resident = 0;
     b->has_aa = false;
+    bool all_unit = true;
     for (int i = 0; i < cap; ++i) {
         BatchSlot& s = b->slots[i];
         if (!s.used) continue;
         active.push_back(i);
         resident += s.alloc_bytes;
         b->has_aa = b->has_aa || s.desc.in_place;
+        all_unit = all_unit && s.par.s_b == 1.0 && s.par.s3 == 1.0 && s.par.s4 == 1.0 && s.par.lam2 == 1.0;
         int nt;
         if (b->precision == CLB_FP32_DEV) {
             BatchEntry<float> E = make_entry<float>(s, s.tw_log2);
@@ -473,6 +477,7 @@ int upload_tables(clb_batch* b)
     if (!active.empty())
         CLB_HIP(hipMemcpyAsync(b->d_active, active.data(), active.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
     b->n_active = int(active.size());
+    b->unit_rates = all_unit;
     // split for the persistent schedule: small lattices are workgroup-resident, the rest grouped
     b->small_slots.clear();
     b->tiles_big.clear();
@@ -517,6 +522,9 @@ hipError_t grouped_launch(clb_batch* b, const TileRef* tiles, int tile_base, int
     if (b->has_aa) {
         if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, true><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
         else batch_step_kernel<S, Real, DEV, false, true><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+    } else if (b->unit_rates) {
+        if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, false, true><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+        else batch_step_kernel<S, Real, DEV, false, false, true><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
     } else {
         if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, false><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
         else batch_step_kernel<S, Real, DEV, false, false><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);

@@ -511,7 +511,10 @@ __device__ __forceinline__ void wall_step_T(const S* __restrict__ src, const Geo
 // the pair (k~20, k~02) as s_b on their sum and s_nu on their difference, and as s_nu, s3, s3,
 // s4 on k~11, k~21, k~12, k~22; the first central moments go from -F/2 to +F/2.  The raw
 // post-collision moments are N(-u) Gamma~* (N(u)^-1 = N(-u)), and f* = M^-1 Gamma*.
-template <typename Real, bool DEV>
+// UNIT: s_b = s3 = s4 = 1 (the paper's default rates), so the bulk, third- and fourth-order
+// non-equilibrium parts relax to zero in one step and need not be formed; the result is the general
+// form's (up to the sign of an exact zero).
+template <typename Real, bool DEV, bool UNIT = false>
 __device__ __forceinline__ void collide_f(Real f[9], const Macro<Real, DEV>& m, const Par<Real>& P)
 {
     const Real R0 = DEV ? Real(1) : Real(0);
@@ -530,17 +533,29 @@ __device__ __forceinline__ void collide_f(Real f[9], const Macro<Real, DEV>& m, 
     const Real c20 = (m20 - dr * third) - Real(2) * ux * jx + ux2 * rho;
     const Real c02 = (m02 - dr * third) - Real(2) * uy * jy + uy2 * rho;
     const Real c11 = m11 - ux * jy - uy * jx + uxy * rho;
-    const Real c21 = m21 - Real(2) * ux * m11 - uy * k20 + Real(2) * uxy * jx + ux2 * jy - ux2 * uy * rho;
-    const Real c12 = m12 - Real(2) * uy * m11 - ux * k02 + Real(2) * uxy * jy + uy2 * jx - ux * uy2 * rho;
-    const Real c22 = (m22 - dr * ninth) - Real(2) * ux * m12 - Real(2) * uy * m21 + Real(4) * uxy * m11
-                   + uy2 * k20 + ux2 * k02 - Real(2) * ux * uy2 * jx - Real(2) * uy * ux2 * jy + ux2 * uy2 * rho;
     // relaxation (Eq. 8)
-    const Real sum_s = P.om_b * (c20 + c02), dif_s = P.om_nu * (c20 - c02);
-    const Real c20s = Real(0.5) * (sum_s + dif_s), c02s = Real(0.5) * (sum_s - dif_s);
+    Real c20s, c02s, c21s, c12s, c22s;
     const Real c11s = P.om_nu * c11;
-    const Real c21s = P.om_3 * c21 + P.c3 * m.Fy;
-    const Real c12s = P.om_3 * c12 + P.c3 * m.Fx;
-    const Real c22s = P.om_4 * c22;
+    if constexpr (UNIT) {
+        const Real dif_s = P.om_nu * (c20 - c02);
+        c20s = Real(0.5) * dif_s;
+        c02s = Real(0.5) * -dif_s;
+        c21s = P.c3 * m.Fy;
+        c12s = P.c3 * m.Fx;
+        c22s = Real(0);
+        (void)m21; (void)m12; (void)m22; (void)k20; (void)k02;
+    } else {
+        const Real c21 = m21 - Real(2) * ux * m11 - uy * k20 + Real(2) * uxy * jx + ux2 * jy - ux2 * uy * rho;
+        const Real c12 = m12 - Real(2) * uy * m11 - ux * k02 + Real(2) * uxy * jy + uy2 * jx - ux * uy2 * rho;
+        const Real c22 = (m22 - dr * ninth) - Real(2) * ux * m12 - Real(2) * uy * m21 + Real(4) * uxy * m11
+                       + uy2 * k20 + ux2 * k02 - Real(2) * ux * uy2 * jx - Real(2) * uy * ux2 * jy + ux2 * uy2 * rho;
+        const Real sum_s = P.om_b * (c20 + c02), dif_s = P.om_nu * (c20 - c02);
+        c20s = Real(0.5) * (sum_s + dif_s);
+        c02s = Real(0.5) * (sum_s - dif_s);
+        c21s = P.om_3 * c21 + P.c3 * m.Fy;
+        c12s = P.om_3 * c12 + P.c3 * m.Fx;
+        c22s = P.om_4 * c22;
+    }
     const Real hx = Real(0.5) * m.Fx, hy = Real(0.5) * m.Fy;   // k~10*, k~01*
     // back to raw moments, N(-u) Gamma~* (Gamma~*_20 = rho/3 + c20s, ..., Gamma~*_22 = rho/9 + c22s)
     const Real t20 = rho * third + c20s, t02 = rho * third + c02s;
@@ -566,7 +581,8 @@ __device__ __forceinline__ void collide_f(Real f[9], const Macro<Real, DEV>& m, 
 
 // D2Q5, Eq. 19: the first central moments relax with lambda1, the second with lambda2, towards
 // Eq. 20's [T, 0, 0, T/4, T/4]; back-transform with N_T(-u) and M_T^-1 (Eq. 21).
-template <typename Real, bool DEV>
+// UNIT: lambda2 = 1, the second-order non-equilibrium parts relax to zero and need not be formed.
+template <typename Real, bool DEV, bool UNIT = false>
 __device__ __forceinline__ void collide_g(Real g[5], const Macro<Real, DEV>& m, const Par<Real>& P)
 {
     const Real ux = m.ux, uy = m.uy, dT = m.dT;
@@ -574,10 +590,17 @@ __device__ __forceinline__ void collide_g(Real g[5], const Macro<Real, DEV>& m, 
     const Real kx = g[1] - g[3], ky = g[2] - g[4];
     const Real m20 = g[1] + g[3], m02 = g[2] + g[4];
     const Real cx = kx - ux * T, cy = ky - uy * T;
-    const Real c20 = (m20 - Real(0.25) * dT) - Real(2) * ux * kx + ux * ux * T;
-    const Real c02 = (m02 - Real(0.25) * dT) - Real(2) * uy * ky + uy * uy * T;
     const Real cxs = P.om_l1 * cx, cys = P.om_l1 * cy;
-    const Real c20s = P.om_l2 * c20, c02s = P.om_l2 * c02;
+    Real c20s, c02s;
+    if constexpr (UNIT) {
+        c20s = c02s = Real(0);
+        (void)m20; (void)m02;
+    } else {
+        const Real c20 = (m20 - Real(0.25) * dT) - Real(2) * ux * kx + ux * ux * T;
+        const Real c02 = (m02 - Real(0.25) * dT) - Real(2) * uy * ky + uy * uy * T;
+        c20s = P.om_l2 * c20;
+        c02s = P.om_l2 * c02;
+    }
     const Real Kx = cxs + ux * T, Ky = cys + uy * T;
     const Real D20 = Real(0.25) * dT + c20s + Real(2) * ux * cxs + ux * ux * T;
     const Real D02 = Real(0.25) * dT + c02s + Real(2) * uy * cys + uy * uy * T;
@@ -673,7 +696,7 @@ __device__ __forceinline__ void store_node(S* __restrict__ dst, long long o, con
 //
 // The whole update of node (x, y) of one step; key = step_key(step) (used by FP32 storage of
 // FP64 arithmetic only).
-template <typename S, typename Real, bool DEV, bool NT>
+template <typename S, typename Real, bool DEV, bool NT, bool UNIT = false>
 __device__ __forceinline__ void node_update(const S* __restrict__ src, S* __restrict__ dst, const Geo& G,
                                             const Par<Real>& P, int x, int y, uint32_t key)
 {
@@ -681,8 +704,8 @@ __device__ __forceinline__ void node_update(const S* __restrict__ src, S* __rest
     pull(src, G, x, y, f, g);
     if (on_wall(G, x, y)) wall_step<S, Real, DEV>(src, G, P, x, y, f, g);
     const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
-    collide_f<Real, DEV>(f, m, P);
-    collide_g<Real, DEV>(g, m, P);
+    collide_f<Real, DEV, UNIT>(f, m, P);
+    collide_g<Real, DEV, UNIT>(g, m, P);
     store_node<S, Real, NT>(dst, pop_at(G, x, y), f, g, key, uint32_t(y) * uint32_t(G.nx) + uint32_t(x));
 }
 
