@@ -97,9 +97,20 @@ __device__ __forceinline__ bool batch_node(const BatchLat& L, int tile, int lane
 template <typename S, typename Real, bool DEV, bool NT, bool AA, bool UNIT = false>
 __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntry<Real>& E, int tile, int s)
 {
-    int x, y;
-    if (!batch_node(E.L, tile, int(threadIdx.x), x, y)) return;
-    if (AA && E.L.aa) {
+    int x = 0, y = 0;
+    const bool valid = batch_node(E.L, tile, int(threadIdx.x), x, y);
+    if (!AA || !E.L.aa) {
+        // select the buffers without indexing off[] by a runtime value (which would put the entry
+        // in private memory); every lane of the wavefront takes part (node_update_wave)
+        const bool c = (E.L.cur ^ (s & 1)) != 0;
+        const long long o_src = c ? E.L.off[1] : E.L.off[0];
+        const long long o_dst = c ? E.L.off[0] : E.L.off[1];
+        node_update_wave<S, Real, DEV, NT, UNIT>(pool + o_src, pool + o_dst, E.L.G, E.P, x, y, valid,
+                                                 step_key(E.L.step + uint32_t(s)));
+        return;
+    }
+    if (!valid) return;
+    {
         // the lattice's own step count sets the in-place form and the snapshot copies
         const uint32_t t = E.L.step + uint32_t(s);
         const bool odd = (t & 1u) != 0;
@@ -108,14 +119,7 @@ __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntr
         S* snext = pool + (odd ? E.L.sn[0] : E.L.sn[1]);
         if (odd) node_update_aa<S, Real, DEV, true, NT>(A, snow, snext, E.L.G, E.P, x, y, step_key(t));
         else node_update_aa<S, Real, DEV, false, NT>(A, snow, snext, E.L.G, E.P, x, y, step_key(t));
-        return;
     }
-    // select the buffers without indexing off[] by a runtime value (which would put the entry
-    // in private memory)
-    const bool c = (E.L.cur ^ (s & 1)) != 0;
-    const long long o_src = c ? E.L.off[1] : E.L.off[0];
-    const long long o_dst = c ? E.L.off[0] : E.L.off[1];
-    node_update<S, Real, DEV, NT, UNIT>(pool + o_src, pool + o_dst, E.L.G, E.P, x, y, step_key(E.L.step + uint32_t(s)));
 }
 
 template <typename S, typename Real, bool DEV, bool NT, bool AA, bool UNIT = false>

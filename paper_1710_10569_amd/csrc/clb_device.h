@@ -71,12 +71,15 @@ template <typename Real> __device__ __forceinline__ Real R0v();
 template <> __device__ __forceinline__ float R0v<float>() { return 1.0f; }
 template <> __device__ __forceinline__ double R0v<double>() { return 1.0; }
 
-// Select one of four values by a runtime index without indexing a kernel-argument array (which
-// would make the compiler copy the argument block to private memory).
+// Select one of four values by a runtime index i in 0..3 without indexing a kernel-argument array
+// (which would make the compiler copy the argument block to private memory).  Selecting on the two
+// bits of i, rather than comparing i with 0, 1, 2, keeps the compiler from turning the chain into
+// a switch, i.e. branches.
 template <typename T>
 __device__ __forceinline__ T sel4(T v0, T v1, T v2, T v3, int i)
 {
-    return i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : v3));
+    const T lo = (i & 1) ? v1 : v0, hi = (i & 1) ? v3 : v2;
+    return (i & 2) ? hi : lo;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -248,7 +251,7 @@ __host__ __device__ constexpr int za(int k, int i) { return ex_of(i) * zny(k) - 
 template <typename Real, bool DEV>
 __device__ __forceinline__ void zou_he(Real f[9], int nx, int ny, Real uwx, Real uwy, Real Fx, Real Fy, Real rho)
 {
-    const int k = nx == 1 ? 0 : (nx == -1 ? 1 : (ny == 1 ? 2 : 3));
+    const int k = nx != 0 ? int(nx < 0) : 2 + int(ny < 0);
     const Real tx = Real(ny), ty = Real(-nx);
     const Real un = uwx * Real(nx) + uwy * Real(ny);
     const Real ut = uwx * tx + uwy * ty;
@@ -331,6 +334,55 @@ __device__ __forceinline__ void nee_g(Real g[5], const Real gf[5], Real dTbf, Re
 // Corner data: velocity of the west/east wall; temperature of a Dirichlet wall if one meets
 // there, the west/east wall's otherwise.
 //
+// Geometry of a wall node: the walls it lies on, its inner neighbour x_f = x + (dx, dy), the wall
+// whose velocity (vw) and temperature (tw, tkind) it takes, the normal k of an edge node or the
+// corner c, and the directions o[] of the populations it sent out of the domain the step before
+// (o[0..2]; at corners also o[3..4]).
+struct WallGeom {
+    bool onW, onE, onS, onN, corner, second;   // second: x_ff is read (adiabatic temperature)
+    int xw, yw, dx, dy, vw, kx, ky, tw, tkind, k, c;
+    int o[5];
+};
+
+// Entry i (0..3) of four 4-bit constants: a shift and a mask (a select chain over constants is
+// turned into branches by the compiler).
+__host__ __device__ constexpr unsigned nib4(int v0, int v1, int v2, int v3)
+{
+    return unsigned(v0) | (unsigned(v1) << 4) | (unsigned(v2) << 8) | (unsigned(v3) << 12);
+}
+__device__ __forceinline__ int nib(unsigned table, int i) { return int((table >> (4 * i)) & 15u); }
+
+__device__ __forceinline__ WallGeom wall_geom(const Geo& G, int x, int y)
+{
+    WallGeom W;
+    W.onW = !G.perx && x == 0;
+    W.onE = !G.perx && x == G.nx - 1;
+    W.onS = !G.pery && y == 0;
+    W.onN = !G.pery && y == G.ny - 1;
+    W.xw = W.onW ? WEST : (W.onE ? EAST : -1);
+    W.yw = W.onS ? SOUTH : (W.onN ? NORTH : -1);
+    W.dx = W.onW ? 1 : (W.onE ? -1 : 0);
+    W.dy = W.onS ? 1 : (W.onN ? -1 : 0);
+    W.corner = W.xw >= 0 && W.yw >= 0;
+    W.vw = W.xw >= 0 ? W.xw : W.yw;
+    W.kx = W.xw >= 0 ? sel4(G.kind[0], G.kind[1], G.kind[2], G.kind[3], W.xw) : K_PERIODIC;
+    W.ky = W.yw >= 0 ? sel4(G.kind[0], G.kind[1], G.kind[2], G.kind[3], W.yw) : K_PERIODIC;
+    W.tw = (W.corner && W.kx != K_DIRICHLET && W.ky == K_DIRICHLET) ? W.yw : W.vw;
+    W.tkind = W.tw == W.xw ? W.kx : W.ky;
+    W.second = W.tkind != K_DIRICHLET;
+    W.k = W.dx != 0 ? int(W.dx < 0) : 2 + int(W.dy < 0);   // 0: dx = 1, 1: dx = -1, 2: dy = 1, 3: dy = -1
+    W.c = (W.dx > 0 ? 0 : 1) + (W.dy > 0 ? 0 : 2);   // corner: 0 SW, 1 SE, 2 NW, 3 NE
+    // edge (inward normal k): the outgoing populations have e.n = -1; corner (inward (dx, dy)): the
+    // five with e_x = -dx or e_y = -dy
+    const int k = W.k, c = W.c;
+    W.o[0] = W.corner ? (W.dx > 0 ? 3 : 1) : nib(nib4(zdir(0, 0, -1), zdir(1, 0, -1), zdir(2, 0, -1), zdir(3, 0, -1)), k);
+    W.o[1] = W.corner ? (W.dy > 0 ? 4 : 2) : nib(nib4(zdir(0, 1, -1), zdir(1, 1, -1), zdir(2, 1, -1), zdir(3, 1, -1)), k);
+    W.o[2] = nib(W.corner ? nib4(7, 8, 6, 5) : nib4(zdir(0, -1, -1), zdir(1, -1, -1), zdir(2, -1, -1), zdir(3, -1, -1)), W.corner ? c : k);
+    W.o[3] = nib(nib4(6, 5, 7, 8), c);
+    W.o[4] = nib(nib4(8, 7, 5, 6), c);
+    return W;
+}
+
 // Sources of the wall step's other inputs.  PullSource: two-buffer streaming; the inner
 // neighbours' post-streaming populations by pull from the previous step's buffer, and the node's
 // own outgoing populations from its own slots of that buffer (f*_k(x) is stored at x, slot k).
@@ -341,11 +393,11 @@ struct PullSource {
     __device__ __forceinline__ void all(const Geo& G, int x, int y, Real f[9], Real g[5]) const { pull(src, G, x, y, f, g); }
     template <typename Real>
     __device__ __forceinline__ void temp(const Geo& G, int x, int y, Real g[5]) const { pull_g(src, G, x, y, g); }
-    // f*_k(x) of the previous step for a direction k (runtime) that leaves the domain
+    // f*_k(x) of the previous step for the outgoing direction k = W.o[j]
     template <typename Real>
-    __device__ __forceinline__ Real outgoing(const Geo& G, int x, int y, int k) const
+    __device__ __forceinline__ Real outgoing(const Geo& G, int x, int y, const WallGeom& W, int j) const
     {
-        return Real(src[pop_at(G, x, y) + k * CW]);
+        return Real(src[pop_at(G, x, y) + W.o[j] * CW]);
     }
 };
 
@@ -353,18 +405,9 @@ template <typename Real, bool DEV, typename NB>
 __device__ __forceinline__ void wall_step_nb(const NB& nb, const Geo& G, const Par<Real>& P,
                                              int x, int y, Real f[9], Real g[5])
 {
-    const bool onW = !G.perx && x == 0, onE = !G.perx && x == G.nx - 1;
-    const bool onS = !G.pery && y == 0, onN = !G.pery && y == G.ny - 1;
-    const int xw = onW ? WEST : (onE ? EAST : -1);
-    const int yw = onS ? SOUTH : (onN ? NORTH : -1);
-    const int dx = onW ? 1 : (onE ? -1 : 0);
-    const int dy = onS ? 1 : (onN ? -1 : 0);
-    const bool corner = xw >= 0 && yw >= 0;
-    const int vw = xw >= 0 ? xw : yw;
-    const int kx = xw >= 0 ? sel4(G.kind[0], G.kind[1], G.kind[2], G.kind[3], xw) : K_PERIODIC;
-    const int ky = yw >= 0 ? sel4(G.kind[0], G.kind[1], G.kind[2], G.kind[3], yw) : K_PERIODIC;
-    const int tw = (corner && kx != K_DIRICHLET && ky == K_DIRICHLET) ? yw : vw;
-    const int tkind = tw == xw ? kx : ky;
+    const WallGeom W = wall_geom(G, x, y);
+    const bool onW = W.onW, onE = W.onE, onS = W.onS, onN = W.onN, corner = W.corner;
+    const int dx = W.dx, dy = W.dy, vw = W.vw, tw = W.tw, tkind = W.tkind;
     const Real uwx = sel4(P.uw[0][0], P.uw[1][0], P.uw[2][0], P.uw[3][0], vw);
     const Real uwy = sel4(P.uw[0][1], P.uw[1][1], P.uw[2][1], P.uw[3][1], vw);
 
@@ -396,19 +439,15 @@ __device__ __forceinline__ void wall_step_nb(const NB& nb, const Geo& G, const P
     // have e.n = -1; corner (inward (dx, dy)): known f_0 and the three populations from inside,
     // (-dx, 0), (0, -dy), (-dx, -dy), and the five with e_x = -dx or e_y = -dy left the domain.
     // Both are formed with selects, without branches, and the node's kind picks one.
-    const int k = dx == 1 ? 0 : (dx == -1 ? 1 : (dy == 1 ? 2 : 3));
-    const int c = (dx > 0 ? 0 : 1) + (dy > 0 ? 0 : 2);   // corner: 0 SW, 1 SE, 2 NW, 3 NE
+    const int k = W.k, c = W.c;
     const Real K0 = (f[0] + at<1, 0>(f, k)) + at<-1, 0>(f, k);
     const Real Km = (at<0, -1>(f, k) + at<1, -1>(f, k)) + at<-1, -1>(f, k);
     const Real un = uwx * Real(dx) + uwy * Real(dy);
     const Real Fn = Fxb * Real(dx) + Fyb * Real(dy);
     const Real dr_zh = (R0 + K0 + Real(2) * Km - Real(0.5) * Fn) / (Real(1) - un) - R0;
-    const int o1 = corner ? (dx > 0 ? 3 : 1) : sel4(zdir(0, 0, -1), zdir(1, 0, -1), zdir(2, 0, -1), zdir(3, 0, -1), k);
-    const int o2 = corner ? (dy > 0 ? 4 : 2) : sel4(zdir(0, 1, -1), zdir(1, 1, -1), zdir(2, 1, -1), zdir(3, 1, -1), k);
-    const int o3 = corner ? sel4(7, 8, 6, 5, c) : sel4(zdir(0, -1, -1), zdir(1, -1, -1), zdir(2, -1, -1), zdir(3, -1, -1), k);
-    Real out = (nb.template outgoing<Real>(G, x, y, o1) + nb.template outgoing<Real>(G, x, y, o2)) +
-               nb.template outgoing<Real>(G, x, y, o3);
-    if (corner) out += nb.template outgoing<Real>(G, x, y, sel4(6, 5, 7, 8, c)) + nb.template outgoing<Real>(G, x, y, sel4(8, 7, 5, 6, c));
+    Real out = (nb.template outgoing<Real>(G, x, y, W, 0) + nb.template outgoing<Real>(G, x, y, W, 1)) +
+               nb.template outgoing<Real>(G, x, y, W, 2);
+    if (corner) out += nb.template outgoing<Real>(G, x, y, W, 3) + nb.template outgoing<Real>(G, x, y, W, 4);
     const Real known_c = (f[0] + (dx > 0 ? f[3] : f[1])) + ((dy > 0 ? f[4] : f[2]) + sel4(f[7], f[8], f[6], f[5], c));
     const Real dr = !imperm ? dr_zh : (corner ? known_c : K0 + Km) + out;   // rho_b - R0
     const Real rho = R0 + dr;
@@ -703,6 +742,74 @@ __device__ __forceinline__ void node_update(const S* __restrict__ src, S* __rest
     Real f[9], g[5];
     pull(src, G, x, y, f, g);
     if (on_wall(G, x, y)) wall_step<S, Real, DEV>(src, G, P, x, y, f, g);
+    const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
+    collide_f<Real, DEV, UNIT>(f, m, P);
+    collide_g<Real, DEV, UNIT>(g, m, P);
+    store_node<S, Real, NT>(dst, pop_at(G, x, y), f, g, key, uint32_t(y) * uint32_t(G.nx) + uint32_t(x));
+}
+
+// ExchangeSource: two-buffer streaming where the wall node's inner neighbour x_f = x + (dx, 0) of a
+// wall in x may be held by the next or previous lane of the wavefront: its 14 post-streaming
+// populations (in the storage type, exactly the values that lane pulled) come from that lane
+// through a cross-lane move (`got`), else from memory as in PullSource.
+template <typename S>
+struct ExchangeSource {
+    const S* src;
+    bool got;
+    const S* nf;   // 14 values: f then g
+    template <typename Real>
+    __device__ __forceinline__ void all(const Geo& G, int x, int y, Real f[9], Real g[5]) const
+    {
+        if (got) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[i] = Real(nf[i]);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) g[i] = Real(nf[9 + i]);
+        } else {
+            pull(src, G, x, y, f, g);
+        }
+    }
+    template <typename Real>
+    __device__ __forceinline__ void temp(const Geo& G, int x, int y, Real g[5]) const { pull_g(src, G, x, y, g); }
+    template <typename Real>
+    __device__ __forceinline__ Real outgoing(const Geo& G, int x, int y, const WallGeom& W, int j) const
+    {
+        return Real(src[pop_at(G, x, y) + W.o[j] * CW]);
+    }
+};
+
+// node_update for a whole wavefront, every lane taking part (valid: the lane holds node (x, y)).
+// Same arithmetic and result as node_update; a node on a wall in x whose inner neighbour is
+// held by the adjacent lane takes that lane's pulled populations instead of loading them again
+// (one cross-lane move per population instead of 14 loads issued for one or two lanes of the
+// wavefront).  The adjacent lane's node is checked, so any node-to-lane mapping is correct.
+template <typename S, typename Real, bool DEV, bool NT, bool UNIT = false>
+__device__ __forceinline__ void node_update_wave(const S* __restrict__ src, S* __restrict__ dst, const Geo& G,
+                                                 const Par<Real>& P, int x, int y, bool valid, uint32_t key)
+{
+    S raw[14];
+    if (valid) pull(src, G, x, y, raw, raw + 9);
+    const bool xwall = valid && !G.perx && (x == 0 || x == G.nx - 1) && G.nx > 1;
+    const bool ywall = !G.pery && (y == 0 || y == G.ny - 1);
+    const bool want = xwall && !ywall;   // edge nodes of the x walls (corners use the diagonal)
+    const int dx = x == 0 ? 1 : -1;
+    bool got = false;
+    S nb[14];
+    if (__ballot(want) != 0) {   // wavefront-uniform
+        const int lane = int(__lane_id());
+        const int from = want ? lane + dx : lane;
+        const int sx = __shfl(valid ? x : -1, from, 64), sy = __shfl(y, from, 64);
+        got = want && sx == x + dx && sy == y;
+#pragma unroll
+        for (int i = 0; i < 14; ++i) nb[i] = __shfl(raw[i], from, 64);
+    }
+    if (!valid) return;
+    Real f[9], g[5];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = Real(raw[i]);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) g[i] = Real(raw[9 + i]);
+    if (on_wall(G, x, y)) wall_step_nb<Real, DEV>(ExchangeSource<S>{src, got, nb}, G, P, x, y, f, g);
     const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
     collide_f<Real, DEV, UNIT>(f, m, P);
     collide_g<Real, DEV, UNIT>(g, m, P);

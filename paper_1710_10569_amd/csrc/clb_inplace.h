@@ -79,8 +79,9 @@ struct SnapSource {
     const S* snap;
     const S* A;
     template <typename Real>
-    __device__ __forceinline__ Real outgoing(const Geo& G, int x, int y, int k) const
+    __device__ __forceinline__ Real outgoing(const Geo& G, int x, int y, const WallGeom& W, int j) const
     {
+        const int k = W.o[j];
         return Real(A[pop_at(G, x, y) + (k == 1 ? 3 : k == 2 ? 4 : k == 3 ? 1 : k == 4 ? 2 : k == 5 ? 7 : k == 6 ? 8 : k == 7 ? 5 : 6) * CW]);
     }
     template <typename Real>
