@@ -199,9 +199,7 @@ static int launch_moments(clb_lattice* h)
 {
     const Geo G = make_geo(h->desc);
     if (h->desc.in_place) {
-        const size_t sb = size_t(snap_elems(h->desc.nx, h->desc.ny)) * elem_bytes(h->desc.precision);
-        CLB_HIP(enqueue_moments_aa(h->desc, h->par, (h->steps & 1) != 0, h->buf[0], (const char*)h->snap + (h->steps & 1) * sb,
-                                   G, h->d_fields, h->stream));
+        CLB_HIP(enqueue_moments_aa(h->desc, h->par, (h->steps & 1) != 0, h->buf[0], G, h->d_fields, h->stream));
         return CLB_OK;
     }
     CLB_HIP(enqueue_moments(h->desc, h->par, h->buf[h->cur], G, h->d_fields, h->stream));

@@ -148,15 +148,15 @@ __global__ void init_aa_kernel(S* __restrict__ A, S* __restrict__ snap0, Geo G, 
 }
 
 template <typename S, typename Real, bool DEV, bool ODD>
-__global__ __launch_bounds__(TX * TY) void moments_aa_kernel(const S* __restrict__ A, const S* __restrict__ snow, Geo G,
-                                                           Par<Real> P, double* __restrict__ fields)
+__global__ __launch_bounds__(TX * TY) void moments_aa_kernel(const S* __restrict__ A, Geo G, Par<Real> P,
+                                                           double* __restrict__ fields)
 {
     const int x = blockIdx.x * TX + threadIdx.x;
     const int y = blockIdx.y * TY + threadIdx.y;
     if (x >= G.nx || y >= G.ny) return;
     Real f[9], g[5];
     load_aa<S, Real, ODD>(A, G, x, y, f, g);
-    if (on_wall(G, x, y)) wall_step_nb<Real, DEV>(SnapSource<S>{snow, A}, G, P, x, y, f, g);
+    if (on_wall(G, x, y)) wall_step_nb<Real, DEV>(DirectSource<S, ODD>{A}, G, P, x, y, f, g);
     const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
     const long long n = (long long)G.nx * G.ny;
     const long long k = (long long)y * G.nx + x;
@@ -345,22 +345,23 @@ inline hipError_t enqueue_init_aa(const clb_desc& d, const Params& p, void* A, v
 }
 
 template <typename S, typename Real, bool DEV>
-inline void moments_aa_launch(bool odd, const void* A, const void* snow, const Geo& G, const Par<Real>& P, double* d_fields,
-                              hipStream_t st)
+inline void moments_aa_launch(bool odd, const void* A, const Geo& G, const Par<Real>& P, double* d_fields, hipStream_t st)
 {
     const dim3 grid = node_grid(G), block(TX, TY);
-    if (odd) moments_aa_kernel<S, Real, DEV, true><<<grid, block, 0, st>>>((const S*)A, (const S*)snow, G, P, d_fields);
-    else moments_aa_kernel<S, Real, DEV, false><<<grid, block, 0, st>>>((const S*)A, (const S*)snow, G, P, d_fields);
+    if (odd) moments_aa_kernel<S, Real, DEV, true><<<grid, block, 0, st>>>((const S*)A, G, P, d_fields);
+    else moments_aa_kernel<S, Real, DEV, false><<<grid, block, 0, st>>>((const S*)A, G, P, d_fields);
 }
 
-inline hipError_t enqueue_moments_aa(const clb_desc& d, const Params& p, bool odd, const void* A, const void* snow,
-                                     const Geo& G, double* d_fields, hipStream_t st)
+// Moments of an in-place lattice; reads only the population buffer (the wall step's neighbours
+// directly, DirectSource), not the snapshot.
+inline hipError_t enqueue_moments_aa(const clb_desc& d, const Params& p, bool odd, const void* A, const Geo& G,
+                                     double* d_fields, hipStream_t st)
 {
     switch (d.precision) {
-    case CLB_FP64: moments_aa_launch<double, double, false>(odd, A, snow, G, make_par<double>(d, p), d_fields, st); break;
-    case CLB_FP64_DEV: moments_aa_launch<double, double, true>(odd, A, snow, G, make_par<double>(d, p), d_fields, st); break;
-    case CLB_FP32_SR: moments_aa_launch<float, double, true>(odd, A, snow, G, make_par<double>(d, p), d_fields, st); break;
-    default: moments_aa_launch<float, float, true>(odd, A, snow, G, make_par<float>(d, p), d_fields, st); break;
+    case CLB_FP64: moments_aa_launch<double, double, false>(odd, A, G, make_par<double>(d, p), d_fields, st); break;
+    case CLB_FP64_DEV: moments_aa_launch<double, double, true>(odd, A, G, make_par<double>(d, p), d_fields, st); break;
+    case CLB_FP32_SR: moments_aa_launch<float, double, true>(odd, A, G, make_par<double>(d, p), d_fields, st); break;
+    default: moments_aa_launch<float, float, true>(odd, A, G, make_par<float>(d, p), d_fields, st); break;
     }
     return hipGetLastError();
 }

@@ -51,6 +51,7 @@ struct BatchLat {
     int halves;         // 32-node runs per row, ceil(nx / 32) (wrapped rows)
     double inv_halves;  // 1 / halves
     int aa;             // 1: in-place lattice (off[0] only, snapshot copies at sn[0], sn[1])
+    int xbands;         // in place: the snapshot keeps the column bands (aa_column_bands)
     long long sn[2];    // element offsets of the in-place snapshot copies
 };
 
@@ -109,17 +110,15 @@ __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntr
                                                  step_key(E.L.step + uint32_t(s)));
         return;
     }
-    if (!valid) return;
-    {
-        // the lattice's own step count sets the in-place form and the snapshot copies
-        const uint32_t t = E.L.step + uint32_t(s);
-        const bool odd = (t & 1u) != 0;
-        S* A = pool + E.L.off[0];
-        const S* snow = pool + (odd ? E.L.sn[1] : E.L.sn[0]);
-        S* snext = pool + (odd ? E.L.sn[0] : E.L.sn[1]);
-        if (odd) node_update_aa<S, Real, DEV, true, NT>(A, snow, snext, E.L.G, E.P, x, y, step_key(t));
-        else node_update_aa<S, Real, DEV, false, NT>(A, snow, snext, E.L.G, E.P, x, y, step_key(t));
-    }
+    // the lattice's own step count sets the in-place form and the snapshot copies
+    const uint32_t t = E.L.step + uint32_t(s);
+    const bool odd = (t & 1u) != 0;
+    S* A = pool + E.L.off[0];
+    const S* snow = pool + (odd ? E.L.sn[1] : E.L.sn[0]);
+    S* snext = pool + (odd ? E.L.sn[0] : E.L.sn[1]);
+    const bool xb = E.L.xbands != 0;
+    if (odd) node_update_aa_wave<S, Real, DEV, true, NT>(A, snow, snext, E.L.G, E.P, x, y, valid, xb, step_key(t));
+    else node_update_aa_wave<S, Real, DEV, false, NT>(A, snow, snext, E.L.G, E.P, x, y, valid, xb, step_key(t));
 }
 
 template <typename S, typename Real, bool DEV, bool NT, bool AA, bool UNIT = false>
@@ -218,8 +217,10 @@ __global__ __launch_bounds__(BNT) void batch_residual_kernel(S* __restrict__ poo
             const S* A = pool + E.L.off[0];
             if (odd) load_aa<S, Real, true>(A, E.L.G, x, y, f, g);
             else load_aa<S, Real, false>(A, E.L.G, x, y, f, g);
-            if (on_wall(E.L.G, x, y))
-                wall_step_nb<Real, DEV>(SnapSource<S>{pool + (odd ? E.L.sn[1] : E.L.sn[0]), A}, E.L.G, E.P, x, y, f, g);
+            if (on_wall(E.L.G, x, y)) {
+                if (odd) wall_step_nb<Real, DEV>(DirectSource<S, true>{A}, E.L.G, E.P, x, y, f, g);
+                else wall_step_nb<Real, DEV>(DirectSource<S, false>{A}, E.L.G, E.P, x, y, f, g);
+            }
         } else {
             const S* src = pool + (E.L.cur ? E.L.off[1] : E.L.off[0]);
             pull(src, E.L.G, x, y, f, g);
@@ -310,6 +311,20 @@ int default_tw_log2(const clb_desc& d)
     if (d.west.kind != CLB_PERIODIC) return 0;
     if (d.in_place) return 6;
     return d.nx <= 96 ? 6 : (d.nx <= 192 ? 7 : 8);
+}
+
+// Whether an in-place lattice keeps the column bands of its snapshot.  Not needed when every x-wall
+// edge node finds its inner neighbours x + dx and x + 2 dx in its own wavefront in the grouped step:
+// under wrapped rows (runs of 32 from x = 0) and row tiles (64-node rows per wavefront) the west
+// wall sits at a run's first node, and the east wall at position (nx - 1) mod 32 (resp. 64) >= 2
+// unless nx mod 32 is 1 or 2; lattices small enough for the workgroup-resident step (whose
+// node-to-lane mapping gives no such guarantee) keep them.  Fixed at admission, so the choice holds
+// whatever mapping or schedule steps the lattice later.
+bool aa_column_bands(const clb_desc& d)
+{
+    if (!d.in_place || d.west.kind == CLB_PERIODIC) return false;
+    const int r = d.nx % 32;
+    return d.nx < 4 || r == 1 || r == 2 || (long long)d.nx * d.ny <= kResidentMaxNodes;
 }
 
 int size_class(const clb_desc& d)
@@ -410,6 +425,7 @@ BatchEntry<Real> make_entry(const BatchSlot& s, int tw_log2)
     E.L.off[1] = s.off[1];
     E.L.snap = (long long)s.snap_off;
     E.L.aa = s.desc.in_place ? 1 : 0;
+    E.L.xbands = aa_column_bands(s.desc) ? 1 : 0;
     E.L.sn[0] = s.sn[0];
     E.L.sn[1] = s.sn[1];
     E.L.cur = s.cur;
@@ -864,8 +880,7 @@ static hipError_t slot_moments(clb_batch* b, const BatchSlot& s)
     const Geo G = make_geo(d);
     if (d.in_place) {
         const bool odd = (s.steps & 1) != 0;
-        return enqueue_moments_aa(d, s.par, odd, b->pool + s.off[0] * eb, b->pool + (odd ? s.sn[1] : s.sn[0]) * eb, G,
-                                  b->d_fields, b->stream);
+        return enqueue_moments_aa(d, s.par, odd, b->pool + s.off[0] * eb, G, b->d_fields, b->stream);
     }
     return enqueue_moments(d, s.par, b->pool + s.off[s.cur] * eb, G, b->d_fields, b->stream);
 }

@@ -331,6 +331,38 @@ def test_full_batch_sampled_against_oracle(gpu):
         b.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_sr"])
+@pytest.mark.parametrize("width", [0, 64, 256])
+def test_in_place_without_column_bands(gpu, precision, width):
+    """In-place lattices of more than 64^2 nodes whose width is not 1 or 2 modulo 32 keep no column
+    bands in their snapshot: their x-wall edge nodes take the inner neighbours x_f and x_ff from the
+    adjacent lanes of the wavefront.  Adiabatic and moving x walls (x_ff is read), an x-walled
+    lattice periodic in y, widths 99, 127, 128 and the band-keeping 97 and 130 (1 and 2 modulo 32),
+    wrapped rows and row tiles: every lattice matches the same lattice alone with two-buffer
+    streaming bitwise after odd and even step counts, and the residuals match the two-buffer
+    lattices' in the same batch."""
+    clb = _clb()
+    ws = [W.random_walled(nx, 45, seed=20 + nx, kinds=("adiabatic", "adiabatic", "dirichlet", "adiabatic"),
+                          wall_u=0.02, g_beta=2e-3) for nx in (99, 127, 130)]
+    ws.append(W.random_walled(97, 50, seed=7, kinds=("adiabatic", "dirichlet", "adiabatic", "dirichlet"), wall_u=0.01))
+    ws.append(W.random_walled(128, 40, seed=8, kinds=("dirichlet", "adiabatic", "periodic", "periodic"), wall_u=0.02))
+    b = clb.Batch(16, precision, budget_bytes=256 << 20)
+    ip = [b.add_workload(w, in_place=True) for w in ws]
+    tb = [b.add_workload(w) for w in ws]
+    for s in ip + tb:
+        b.set_tile_width(s, width)
+    print(f"[batch] no column bands {precision} width={width}", flush=True)
+    b.step(31)
+    res = b.residuals()
+    for s, t in zip(ip, tb):
+        assert res[s] == res[t], (s, res[s], res[t])
+    b.step(26)
+    for w, s in zip(ws, ip):
+        for a, r in zip(b.moments(s), alone(w, precision, 57)):
+            assert np.array_equal(a, r), (w["name"], width)
+    b.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_sr"])
 @pytest.mark.parametrize("mode", ["grouped", "each", "persistent"])
 def test_in_place_lattices_in_a_batch(gpu, precision, mode):
