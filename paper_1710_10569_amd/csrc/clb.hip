@@ -1,12 +1,16 @@
-// clb.hip -- single-lattice kernels and the C ABI of libclb (include/clb.h).
+// clb.hip -- single-lattice entry points of libclb (include/clb.h); the kernels they launch live in
+// the headers below.
 //
 // Kernels (all one thread per node):
-//   step_kernel      the fused time step: pull, wall step, macroscopic, D2Q9 + D2Q5 collision,
-//                    store (Sec. 2.1 Eq. 8, Sec. 2.2 Eq. 19, Eq. 3, Eq. 13, Eq. 23, Sec. 3 walls).
-//   init_kernel      equilibrium populations from FP64 fields, scattered to where the next pull
-//                    reads them (Eqs. 9 and 20 through the generalised equilibria).
-//   moments_kernel   pull + wall step + macroscopic quantities -> FP64 rho, u, T.
-//   populations_kernel  pull -> FP64 post-streaming populations, NaN where unknown.
+//   step_tile_kernel the fused time step (clb_step.h): pull, wall step, macroscopic, D2Q9 + D2Q5
+//                    collision, store (Sec. 2.1 Eq. 8, Sec. 2.2 Eq. 19, Eq. 3, Eq. 13, Eq. 23,
+//                    Sec. 3 walls), in row tiles of several shapes.
+//   step_T_kernel    the temperature-only step with a prescribed velocity (clb_step.h, Sec. 3.1).
+//   step_aa_kernel   the in-place step (clb_inplace.h), even and odd forms.
+//   init_kernel / init_aa_kernel  equilibrium populations from FP64 fields, scattered to where
+//                    the next step reads them (Eqs. 9 and 20 through the generalised equilibria).
+//   moments_kernel / moments_aa_kernel  pull + wall step + macroscopic quantities -> FP64 rho, u, T.
+//   populations_kernel / populations_aa_kernel  post-streaming populations in FP64, NaN where unknown.
 //   diag_reduce_kernel / diag_final_kernel  FP64 sums and maxima of the moment fields, with a
 //                    fixed reduction order (64-lane wavefront shuffles, then block, then a single
 //                    block over the per-block partials), so repeated runs agree bitwise.
