@@ -282,9 +282,11 @@ int clb_batch_create(int capacity, int precision, size_t hbm_budget_bytes, void*
 /* Admit a lattice (desc->precision must equal the batch's) with the parameters of
  * clb_set_params; it starts at rest (rho = 1, u = 0, T = T0) with step count 0.  *slot receives its
  * index.  Two-buffer and in-place lattices may share a batch; temperature-only lattices
- * (prescribed_u = 1) are single-lattice only.  Errors: CLB_EINVAL (bad description, precision
- * other than the batch's, prescribed_u = 1); CLB_ENOMEM if the batch is full or the pool lacks
- * space. */
+ * (prescribed_u = 1) are single-lattice only.  A batch lattice's population buffer must be under
+ * 4 GiB (the grouped step addresses it with 32-bit byte offsets: up to about 76 M nodes in FP32
+ * storage, 38 M in FP64); larger lattices run as single lattices.  Errors: CLB_EINVAL (bad
+ * description, precision other than the batch's, prescribed_u = 1, a buffer of 4 GiB or more);
+ * CLB_ENOMEM if the batch is full or the pool lacks space. */
 int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, double tau_alpha, double g_beta, double Ma,
                   int* slot);
 

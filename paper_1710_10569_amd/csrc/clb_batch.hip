@@ -106,8 +106,8 @@ __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntr
         const bool c = (E.L.cur ^ (s & 1)) != 0;
         const long long o_src = c ? E.L.off[1] : E.L.off[0];
         const long long o_dst = c ? E.L.off[0] : E.L.off[1];
-        node_update_wave<S, Real, DEV, NT, UNIT>(pool + o_src, pool + o_dst, E.L.G, E.P, x, y, valid,
-                                                 step_key(E.L.step + uint32_t(s)));
+        node_update_wave<S, Real, DEV, NT, UNIT, true>(pool + o_src, pool + o_dst, E.L.G, E.P, x, y, valid,
+                                                       step_key(E.L.step + uint32_t(s)));
         return;
     }
     // the lattice's own step count sets the in-place form and the snapshot copies
@@ -802,6 +802,12 @@ extern "C" int clb_batch_add(clb_batch* b, const clb_desc* desc, double tau_nu, 
     BatchSlot s;
     size_t buf_bytes = 0, band_bytes = 0;
     const size_t bytes = slot_bytes(*desc, &buf_bytes, &band_bytes);
+    if (buf_bytes >= (size_t(1) << 32)) {
+        // the grouped step addresses a lattice's buffers with 32-bit byte offsets
+        set_error("a batch lattice's population buffer must be under 4 GiB (this one needs %zu bytes); "
+                  "use a single lattice (clb_create)", buf_bytes);
+        return CLB_EINVAL;
+    }
     size_t off = 0;
     if (alloc_range(b, bytes, &off) != CLB_OK) {
         set_error("lattice needs %zu bytes; %zu of %zu bytes in use", bytes, b->used_bytes, b->budget);

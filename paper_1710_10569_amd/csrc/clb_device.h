@@ -53,6 +53,40 @@ __host__ __device__ __forceinline__ long long pop_at(const Geo& G, int x, int y)
     return (long long)y * G.row + chunk_col(x);
 }
 
+// Addressing of a buffer.  B32 = false: element offsets in 64 bits.  B32 = true (buffers of less than
+// 4 GiB, as batch lattices are): byte offsets in 32 bits, so that a load or store takes the buffer's
+// (workgroup-uniform) base from scalar registers and a 32-bit offset per lane, with no 64-bit address
+// arithmetic per access.  Off<S, B32> is the offset type; node_off the offset of population 0 of node
+// (x, y); slot(p, k, o) the element of population slot k at offset o.
+template <bool B32> struct OffT { using type = long long; };
+template <> struct OffT<true> { using type = uint32_t; };
+template <typename S, bool B32> using Off = typename OffT<B32>::type;
+
+template <typename S, bool B32>
+__device__ __forceinline__ Off<S, B32> scale_off(long long elems)
+{
+    if constexpr (B32) return uint32_t(elems) * uint32_t(sizeof(S));
+    else return elems;
+}
+template <typename S, bool B32>
+__device__ __forceinline__ Off<S, B32> node_off(const Geo& G, int x, int y)
+{
+    if constexpr (B32) return (uint32_t(y) * uint32_t(G.row) + uint32_t(chunk_col(x))) * uint32_t(sizeof(S));
+    else return pop_at(G, x, y);
+}
+template <bool B32, typename S, typename O>
+__device__ __forceinline__ S& slot(S* p, int k, O o)
+{
+    if constexpr (B32) return *reinterpret_cast<S*>(reinterpret_cast<char*>(p) + k * CW * int(sizeof(S)) + o);
+    else return p[o + k * CW];
+}
+template <bool B32, typename S, typename O>
+__device__ __forceinline__ const S& slot(const S* p, int k, O o)
+{
+    if constexpr (B32) return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(p) + k * CW * int(sizeof(S)) + o);
+    else return p[o + k * CW];
+}
+
 // Per-lattice physical parameters in the arithmetic type.
 template <typename Real>
 struct Par {
@@ -109,7 +143,7 @@ __device__ __forceinline__ void poison_unknown(const Geo& G, int x, int y, Real 
 // Pull: the 14 post-streaming populations of node (x, y).  Periodic directions wrap; in a
 // walled direction a source outside the domain is clamped to the edge -- the value read is then
 // meaningless and is replaced by the wall step.
-template <typename S, typename Real>
+template <typename S, typename Real, bool B32 = false>
 __device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, int x, int y,
                                      Real f[9], Real g[5])
 {
@@ -117,39 +151,43 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, in
     const int xp = x < G.nx - 1 ? x + 1 : (G.perx ? 0 : G.nx - 1);
     const int ym = y > 0 ? y - 1 : (G.pery ? G.ny - 1 : 0);
     const int yp = y < G.ny - 1 ? y + 1 : (G.pery ? 0 : G.ny - 1);
-    const long long rc = (long long)y * G.row, rm = (long long)ym * G.row, rp = (long long)yp * G.row;
-    const int cc = chunk_col(x), cm = chunk_col(xm), cp = chunk_col(xp);
-    f[0] = Real(src[rc + cc + 0 * CW]);
-    f[1] = Real(src[rc + cm + 1 * CW]);
-    f[2] = Real(src[rm + cc + 2 * CW]);
-    f[3] = Real(src[rc + cp + 3 * CW]);
-    f[4] = Real(src[rp + cc + 4 * CW]);
-    f[5] = Real(src[rm + cm + 5 * CW]);
-    f[6] = Real(src[rm + cp + 6 * CW]);
-    f[7] = Real(src[rp + cp + 7 * CW]);
-    f[8] = Real(src[rp + cm + 8 * CW]);
-    g[0] = Real(src[rc + cc + 9 * CW]);
-    g[1] = Real(src[rc + cm + 10 * CW]);
-    g[2] = Real(src[rm + cc + 11 * CW]);
-    g[3] = Real(src[rc + cp + 12 * CW]);
-    g[4] = Real(src[rp + cc + 13 * CW]);
+    using O = Off<S, B32>;
+    const O rc = scale_off<S, B32>((long long)y * G.row), rm = scale_off<S, B32>((long long)ym * G.row),
+            rp = scale_off<S, B32>((long long)yp * G.row);
+    const O cc = scale_off<S, B32>(chunk_col(x)), cm = scale_off<S, B32>(chunk_col(xm)), cp = scale_off<S, B32>(chunk_col(xp));
+    f[0] = Real(slot<B32>(src, 0, rc + cc));
+    f[1] = Real(slot<B32>(src, 1, rc + cm));
+    f[2] = Real(slot<B32>(src, 2, rm + cc));
+    f[3] = Real(slot<B32>(src, 3, rc + cp));
+    f[4] = Real(slot<B32>(src, 4, rp + cc));
+    f[5] = Real(slot<B32>(src, 5, rm + cm));
+    f[6] = Real(slot<B32>(src, 6, rm + cp));
+    f[7] = Real(slot<B32>(src, 7, rp + cp));
+    f[8] = Real(slot<B32>(src, 8, rp + cm));
+    g[0] = Real(slot<B32>(src, 9, rc + cc));
+    g[1] = Real(slot<B32>(src, 10, rc + cm));
+    g[2] = Real(slot<B32>(src, 11, rm + cc));
+    g[3] = Real(slot<B32>(src, 12, rc + cp));
+    g[4] = Real(slot<B32>(src, 13, rp + cc));
     poison_unknown<Real>(G, x, y, f, g);
 }
 
-template <typename S, typename Real>
+template <typename S, typename Real, bool B32 = false>
 __device__ __forceinline__ void pull_g(const S* __restrict__ src, const Geo& G, int x, int y, Real g[5])
 {
     const int xm = x > 0 ? x - 1 : (G.perx ? G.nx - 1 : 0);
     const int xp = x < G.nx - 1 ? x + 1 : (G.perx ? 0 : G.nx - 1);
     const int ym = y > 0 ? y - 1 : (G.pery ? G.ny - 1 : 0);
     const int yp = y < G.ny - 1 ? y + 1 : (G.pery ? 0 : G.ny - 1);
-    const long long rc = (long long)y * G.row, rm = (long long)ym * G.row, rp = (long long)yp * G.row;
-    const int cc = chunk_col(x), cm = chunk_col(xm), cp = chunk_col(xp);
-    g[0] = Real(src[rc + cc + 9 * CW]);
-    g[1] = Real(src[rc + cm + 10 * CW]);
-    g[2] = Real(src[rm + cc + 11 * CW]);
-    g[3] = Real(src[rc + cp + 12 * CW]);
-    g[4] = Real(src[rp + cc + 13 * CW]);
+    using O = Off<S, B32>;
+    const O rc = scale_off<S, B32>((long long)y * G.row), rm = scale_off<S, B32>((long long)ym * G.row),
+            rp = scale_off<S, B32>((long long)yp * G.row);
+    const O cc = scale_off<S, B32>(chunk_col(x)), cm = scale_off<S, B32>(chunk_col(xm)), cp = scale_off<S, B32>(chunk_col(xp));
+    g[0] = Real(slot<B32>(src, 9, rc + cc));
+    g[1] = Real(slot<B32>(src, 10, rc + cm));
+    g[2] = Real(slot<B32>(src, 11, rm + cc));
+    g[3] = Real(slot<B32>(src, 12, rc + cp));
+    g[4] = Real(slot<B32>(src, 13, rp + cc));
     poison_unknown<Real>(G, x, y, nullptr, g);
 }
 
@@ -716,16 +754,16 @@ __device__ __forceinline__ void round_node(const Real f[9], const Real g[5], uin
 }
 
 // Round and store them with population 0 at offset o (population i at o + i CW).
-template <typename S, typename Real, bool NT>
-__device__ __forceinline__ void store_node(S* __restrict__ dst, long long o, const Real f[9], const Real g[5],
+template <typename S, typename Real, bool NT, bool B32 = false>
+__device__ __forceinline__ void store_node(S* __restrict__ dst, Off<S, B32> o, const Real f[9], const Real g[5],
                                            uint32_t key, uint32_t node)
 {
     S v[14];
     round_node<S, Real>(f, g, key, node, v);
 #pragma unroll
     for (int i = 0; i < 14; ++i) {
-        if (NT) __builtin_nontemporal_store(v[i], dst + o + i * CW);
-        else dst[o + i * CW] = v[i];
+        if (NT) __builtin_nontemporal_store(v[i], &slot<B32>(dst, i, o));
+        else slot<B32>(dst, i, o) = v[i];
     }
 }
 
@@ -752,7 +790,7 @@ __device__ __forceinline__ void node_update(const S* __restrict__ src, S* __rest
 // wall in x may be held by the next or previous lane of the wavefront: its 14 post-streaming
 // populations (in the storage type, exactly the values that lane pulled) come from that lane
 // through a cross-lane move (`got`), else from memory as in PullSource.
-template <typename S>
+template <typename S, bool B32>
 struct ExchangeSource {
     const S* src;
     bool got;
@@ -766,15 +804,18 @@ struct ExchangeSource {
 #pragma unroll
             for (int i = 0; i < 5; ++i) g[i] = Real(nf[9 + i]);
         } else {
-            pull(src, G, x, y, f, g);
+            pull<S, Real, B32>(src, G, x, y, f, g);
         }
     }
     template <typename Real>
-    __device__ __forceinline__ void temp(const Geo& G, int x, int y, Real g[5]) const { pull_g(src, G, x, y, g); }
+    __device__ __forceinline__ void temp(const Geo& G, int x, int y, Real g[5]) const
+    {
+        pull_g<S, Real, B32>(src, G, x, y, g);
+    }
     template <typename Real>
     __device__ __forceinline__ Real outgoing(const Geo& G, int x, int y, const WallGeom& W, int j) const
     {
-        return Real(src[pop_at(G, x, y) + W.o[j] * CW]);
+        return Real(slot<B32>(src, W.o[j], node_off<S, B32>(G, x, y)));
     }
 };
 
@@ -783,12 +824,12 @@ struct ExchangeSource {
 // held by the adjacent lane takes that lane's pulled populations instead of loading them again
 // (one cross-lane move per population instead of 14 loads issued for one or two lanes of the
 // wavefront).  The adjacent lane's node is checked, so any node-to-lane mapping is correct.
-template <typename S, typename Real, bool DEV, bool NT, bool UNIT = false>
+template <typename S, typename Real, bool DEV, bool NT, bool UNIT = false, bool B32 = false>
 __device__ __forceinline__ void node_update_wave(const S* __restrict__ src, S* __restrict__ dst, const Geo& G,
                                                  const Par<Real>& P, int x, int y, bool valid, uint32_t key)
 {
     S raw[14];
-    if (valid) pull(src, G, x, y, raw, raw + 9);
+    if (valid) pull<S, S, B32>(src, G, x, y, raw, raw + 9);
     const bool xwall = valid && !G.perx && (x == 0 || x == G.nx - 1) && G.nx > 1;
     const bool ywall = !G.pery && (y == 0 || y == G.ny - 1);
     const bool want = xwall && !ywall;   // edge nodes of the x walls (corners use the diagonal)
@@ -809,11 +850,11 @@ __device__ __forceinline__ void node_update_wave(const S* __restrict__ src, S* _
     for (int i = 0; i < 9; ++i) f[i] = Real(raw[i]);
 #pragma unroll
     for (int i = 0; i < 5; ++i) g[i] = Real(raw[9 + i]);
-    if (on_wall(G, x, y)) wall_step_nb<Real, DEV>(ExchangeSource<S>{src, got, nb}, G, P, x, y, f, g);
+    if (on_wall(G, x, y)) wall_step_nb<Real, DEV>(ExchangeSource<S, B32>{src, got, nb}, G, P, x, y, f, g);
     const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
     collide_f<Real, DEV, UNIT>(f, m, P);
     collide_g<Real, DEV, UNIT>(g, m, P);
-    store_node<S, Real, NT>(dst, pop_at(G, x, y), f, g, key, uint32_t(y) * uint32_t(G.nx) + uint32_t(x));
+    store_node<S, Real, NT, B32>(dst, node_off<S, B32>(G, x, y), f, g, key, uint32_t(y) * uint32_t(G.nx) + uint32_t(x));
 }
 
 // Two nodes of one column, (x, y0) and (x, y1): both pulls are issued before either update is

@@ -120,6 +120,21 @@ def test_admission_by_footprint_and_slot_reuse(gpu):
     b.close()
 
 
+def test_admission_refuses_buffers_of_4_gib(gpu):
+    """The grouped step addresses a batch lattice's buffers with 32-bit byte offsets: a lattice whose
+    population buffer needs 4 GiB or more (16384 x 16384 in FP32: 15 GB) is refused with CLB_EINVAL
+    before any pool space is taken; the largest admissible shapes stay admissible by this rule."""
+    clb = _clb()
+    b = clb.Batch(4, "fp32", budget_bytes=64 << 20)
+    with pytest.raises(clb.CLBError) as e:
+        b.add(16384, 16384)
+    assert e.value.code == clb.CLB_EINVAL and "4 GiB" in str(e.value)
+    assert b.info()["used_bytes"] == 0
+    s = b.add(64, 64)
+    assert s is not None
+    b.close()
+
+
 def test_external_torch_pool(gpu):
     import torch
     clb = _clb()
