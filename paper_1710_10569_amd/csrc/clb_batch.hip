@@ -117,8 +117,8 @@ __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntr
     const S* snow = pool + (odd ? E.L.sn[1] : E.L.sn[0]);
     S* snext = pool + (odd ? E.L.sn[0] : E.L.sn[1]);
     const bool xb = E.L.xbands != 0;
-    if (odd) node_update_aa_wave<S, Real, DEV, true, NT>(A, snow, snext, E.L.G, E.P, x, y, valid, xb, step_key(t));
-    else node_update_aa_wave<S, Real, DEV, false, NT>(A, snow, snext, E.L.G, E.P, x, y, valid, xb, step_key(t));
+    if (odd) node_update_aa_wave<S, Real, DEV, true, NT, true>(A, snow, snext, E.L.G, E.P, x, y, valid, xb, step_key(t));
+    else node_update_aa_wave<S, Real, DEV, false, NT, true>(A, snow, snext, E.L.G, E.P, x, y, valid, xb, step_key(t));
 }
 
 template <typename S, typename Real, bool DEV, bool NT, bool AA, bool UNIT = false>

@@ -132,63 +132,67 @@ __device__ __forceinline__ bool step_to(const Geo& G, int x, int y, int ex, int 
 }
 
 // Row bases and column offsets of a node and its neighbours (neighbours beyond a wall are clamped
-// onto the edge, as in pull).
+// onto the edge, as in pull), in the addressing of clb_device.h (B32: 32-bit byte offsets).
+template <typename S, bool B32>
 struct AANbr {
-    long long rm, rc, rp;
-    int cm, cc, cp;
+    Off<S, B32> rm, rc, rp, cm, cc, cp;
 };
-__device__ __forceinline__ AANbr aa_nbr(const Geo& G, int x, int y)
+template <typename S, bool B32>
+__device__ __forceinline__ AANbr<S, B32> aa_nbr(const Geo& G, int x, int y)
 {
     const int xm = x > 0 ? x - 1 : (G.perx ? G.nx - 1 : 0);
     const int xp = x < G.nx - 1 ? x + 1 : (G.perx ? 0 : G.nx - 1);
     const int ym = y > 0 ? y - 1 : (G.pery ? G.ny - 1 : 0);
     const int yp = y < G.ny - 1 ? y + 1 : (G.pery ? 0 : G.ny - 1);
-    return {(long long)ym * G.row, (long long)y * G.row, (long long)yp * G.row, chunk_col(xm), chunk_col(x), chunk_col(xp)};
+    return {scale_off<S, B32>((long long)ym * G.row), scale_off<S, B32>((long long)y * G.row),
+            scale_off<S, B32>((long long)yp * G.row), scale_off<S, B32>(chunk_col(xm)),
+            scale_off<S, B32>(chunk_col(x)), scale_off<S, B32>(chunk_col(xp))};
 }
 // offset of the node one step along (dx, dy) (each -1, 0 or +1, known at compile time after unrolling)
-__device__ __forceinline__ long long aa_at(const AANbr& n, int dx, int dy)
+template <typename S, bool B32>
+__device__ __forceinline__ Off<S, B32> aa_at(const AANbr<S, B32>& n, int dx, int dy)
 {
     return (dy < 0 ? n.rm : (dy > 0 ? n.rp : n.rc)) + (dx < 0 ? n.cm : (dx > 0 ? n.cp : n.cc));
 }
 
 // Post-streaming populations of node (x, y) at a time of parity ODD.  At a wall node the unknown
 // ones are read from a clamped neighbour and are meaningless: the wall step replaces them.
-template <typename S, typename Real, bool ODD>
+template <typename S, typename Real, bool ODD, bool B32 = false>
 __device__ __forceinline__ void load_aa(const S* __restrict__ A, const Geo& G, int x, int y, Real f[9], Real g[5])
 {
     if (!ODD) {
-        const long long o = pop_at(G, x, y);
+        const Off<S, B32> o = node_off<S, B32>(G, x, y);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = Real(A[o + i * CW]);
+        for (int i = 0; i < 9; ++i) f[i] = Real(slot<B32>(A, i, o));
 #pragma unroll
-        for (int i = 0; i < 5; ++i) g[i] = Real(A[o + (9 + i) * CW]);
+        for (int i = 0; i < 5; ++i) g[i] = Real(slot<B32>(A, 9 + i, o));
         poison_unknown<Real>(G, x, y, f, g);
         return;
     }
-    const AANbr n = aa_nbr(G, x, y);
+    const AANbr<S, B32> n = aa_nbr<S, B32>(G, x, y);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = Real(A[aa_at(n, -ex_of(i), -ey_of(i)) + opp_of(i) * CW]);
+    for (int i = 0; i < 9; ++i) f[i] = Real(slot<B32>(A, opp_of(i), aa_at(n, -ex_of(i), -ey_of(i))));
 #pragma unroll
-    for (int i = 0; i < 5; ++i) g[i] = Real(A[aa_at(n, -ex_of(i), -ey_of(i)) + (9 + opp_of(i)) * CW]);
+    for (int i = 0; i < 5; ++i) g[i] = Real(slot<B32>(A, 9 + opp_of(i), aa_at(n, -ex_of(i), -ey_of(i))));
     poison_unknown<Real>(G, x, y, f, g);
 }
 
 // Store the node's rounded post-collision values v (f* then g*) for the next time step, and copy
 // those that stream into a snapshot band node into the next snapshot.
-template <typename S, bool ODD, bool NT>
+template <typename S, bool ODD, bool NT, bool B32 = false>
 __device__ __forceinline__ void store_aa(S* __restrict__ A, S* __restrict__ snext, const Geo& G, int x, int y,
                                          const S v[14], bool xb = true)
 {
     if (!ODD) {
-        const long long o = pop_at(G, x, y);
+        const Off<S, B32> o = node_off<S, B32>(G, x, y);
 #pragma unroll
         for (int q = 0; q < 14; ++q) {
-            const int slot = q < 9 ? opp_of(q) : 9 + opp_of(q - 9);
-            if (NT) __builtin_nontemporal_store(v[q], A + o + slot * CW);
-            else A[o + slot * CW] = v[q];
+            const int k = q < 9 ? opp_of(q) : 9 + opp_of(q - 9);
+            if (NT) __builtin_nontemporal_store(v[q], &slot<B32>(A, k, o));
+            else slot<B32>(A, k, o) = v[q];
         }
     } else {
-        const AANbr n = aa_nbr(G, x, y);
+        const AANbr<S, B32> n = aa_nbr<S, B32>(G, x, y);
         // targets beyond a wall (wall nodes only): the population is kept in slot opp(q) of the node
         // itself, one address select instead of a branch per population.  For a flow population
         // the wall step's mass balance reads it there; a temperature one lands in the slot of the
@@ -201,9 +205,10 @@ __device__ __forceinline__ void store_aa(S* __restrict__ A, S* __restrict__ snex
             const int dx = ex_of(i), dy = ey_of(i);
             const bool ok = (dx < 0 ? okxm : (dx > 0 ? okxp : true)) && (dy < 0 ? okym : (dy > 0 ? okyp : true));
             const int keep = q < 9 ? opp_of(q) : 9 + opp_of(q - 9);
-            const long long a = ok ? aa_at(n, dx, dy) + q * CW : aa_at(n, 0, 0) + keep * CW;
-            if (NT) __builtin_nontemporal_store(v[q], A + a);
-            else A[a] = v[q];
+            const Off<S, B32> a = ok ? aa_at(n, dx, dy) + scale_off<S, B32>(q * CW)
+                                     : aa_at(n, 0, 0) + scale_off<S, B32>(keep * CW);
+            if (NT) __builtin_nontemporal_store(v[q], &slot<B32>(A, 0, a));
+            else slot<B32>(A, 0, a) = v[q];
         }
     }
     // only nodes within one step of a band can stream into it
@@ -341,13 +346,13 @@ struct XchgSource {
 // the lanes next to it takes their loaded populations through cross-lane moves instead of the
 // snapshot.  xb = false: the lattice keeps no column bands, which is correct when every x-wall edge
 // node finds both neighbours in its wavefront (the caller's node-to-lane mapping guarantees it).
-template <typename S, typename Real, bool DEV, bool ODD, bool NT>
+template <typename S, typename Real, bool DEV, bool ODD, bool NT, bool B32 = false>
 __device__ __forceinline__ void node_update_aa_wave(S* __restrict__ A, const S* __restrict__ snow, S* __restrict__ snext,
                                                     const Geo& G, const Par<Real>& P, int x, int y, bool valid,
                                                     bool xb, uint32_t key)
 {
     S raw[14];
-    if (valid) load_aa<S, S, ODD>(A, G, x, y, raw, raw + 9);
+    if (valid) load_aa<S, S, ODD, B32>(A, G, x, y, raw, raw + 9);
     const bool xwall = valid && !G.perx && (x == 0 || x == G.nx - 1) && G.nx > 1;
     const bool ywall = !G.pery && (y == 0 || y == G.ny - 1);
     const bool want = xwall && !ywall;   // corners use the diagonal neighbour (row bands)
@@ -384,7 +389,7 @@ __device__ __forceinline__ void node_update_aa_wave(S* __restrict__ A, const S* 
     collide_g<Real, DEV>(g, m, P);
     S v[14];
     round_node<S, Real>(f, g, key, uint32_t(y) * uint32_t(G.nx) + uint32_t(x), v);
-    store_aa<S, ODD, NT>(A, snext, G, x, y, v, xb);
+    store_aa<S, ODD, NT, B32>(A, snext, G, x, y, v, xb);
 }
 
 // One in-place step: TXW x 1 tiles (TXW = 64: one wavefront per workgroup, or 256) handed out XCD
