@@ -532,22 +532,35 @@ int upload_tables(clb_batch* b)
     return CLB_OK;
 }
 
+// Occupancy of the grouped step.  FP32 storage with FP32 arithmetic needs 47-51 VGPRs, so 8 wavefronts
+// per SIMD would fit; at most 6 are faster (512-cavity batch, one MI355X: two buffers 1.040 -> 1.005 ms
+// per step, in place 1.109 -> 1.090; 5 or 4 are no better), as fewer streams are in flight per CU.  The
+// cap is dynamic LDS the kernel does not use: a CU's 160 KiB hold 6 such allocations, i.e. 6
+// workgroups of BNT threads (one wavefront per SIMD each).  The FP64-arithmetic forms are held to 5
+// wavefronts by their registers already, and an extra cap makes them slower.
+template <typename S, typename Real>
+constexpr size_t occupancy_lds()
+{
+    return sizeof(S) == 4 && sizeof(Real) == 4 ? size_t(160 * 1024 / 6) / 512 * 512 : 0;
+}
+
 template <typename S, typename Real, bool DEV>
 hipError_t grouped_launch(clb_batch* b, const TileRef* tiles, int tile_base, int ntiles, int s)
 {
     const int q = (ntiles + 7) / 8;
     const dim3 grid(8 * q), block(BNT);
     S* pool = (S*)b->pool;
+    constexpr size_t lds = occupancy_lds<S, Real>();
     const BatchEntry<Real>* lats = (const BatchEntry<Real>*)b->d_lats;
     if (b->has_aa) {
-        if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, true><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
-        else batch_step_kernel<S, Real, DEV, false, true><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+        if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+        else batch_step_kernel<S, Real, DEV, false, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
     } else if (b->unit_rates) {
-        if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, false, true><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
-        else batch_step_kernel<S, Real, DEV, false, false, true><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+        if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, false, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+        else batch_step_kernel<S, Real, DEV, false, false, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
     } else {
-        if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, false><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
-        else batch_step_kernel<S, Real, DEV, false, false><<<grid, block, 0, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+        if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, false><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+        else batch_step_kernel<S, Real, DEV, false, false><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
     }
     return hipGetLastError();
 }
