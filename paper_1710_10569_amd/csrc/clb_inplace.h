@@ -248,14 +248,27 @@ __device__ __forceinline__ void store_aa(S* __restrict__ A, S* __restrict__ snex
         }
     }
     if (!G.pery) {
+        // Depth 1 of a row band (rows 2 and ny - 3) serves only the second inner neighbour x_ff, of
+        // which only the temperature populations are read; with ny >= 5 no lookup of an inner
+        // neighbour x_f lands there (rows 1 and ny - 2 are depth 0), so its flow populations are
+        // not written.
+        const bool g_only_rows = G.ny >= 5;
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
             if (rbase[e] < 0) continue;
+            const int ty = y + e - 1;
+            if (!(g_only_rows && (ty == 2 || ty == G.ny - 3))) {
 #pragma unroll
-            for (int q = 0; q < 14; ++q) {
-                const int i = q < 9 ? q : q - 9;
-                if (ey_of(i) + 1 != e) continue;
-                const int dx = ex_of(i) + 1;
+                for (int q = 0; q < 9; ++q) {
+                    if (ey_of(q) + 1 != e) continue;
+                    const int dx = ex_of(q) + 1;
+                    snext[xpos[dx] >= 0 ? rbase[e] + q * len + xpos[dx] : spare] = v[q];
+                }
+            }
+#pragma unroll
+            for (int q = 9; q < 14; ++q) {
+                if (ey_of(q - 9) + 1 != e) continue;
+                const int dx = ex_of(q - 9) + 1;
                 snext[xpos[dx] >= 0 ? rbase[e] + q * len + xpos[dx] : spare] = v[q];
             }
         }
