@@ -28,11 +28,17 @@ def cases():
         W.random_walled(4, 9, seed=6, kinds=("dirichlet", "adiabatic", "dirichlet", "adiabatic"), wall_u=0.01),
         W.cavity(64, Ra=1e5),
         W.rayleigh_benard(300, 41, Ra=1e4, seed=5),
+        # four and five rows between adiabatic y walls: the snapshot's depth-1 rows (2 and ny - 3)
+        # coincide with a depth-0 row at ny = 4 and with each other at ny = 5
+        W.random_walled(37, 4, seed=7, kinds=("dirichlet", "adiabatic", "adiabatic", "adiabatic"), wall_u=0.02,
+                        g_beta=2e-3),
+        W.random_walled(29, 5, seed=8, kinds=("adiabatic", "dirichlet", "adiabatic", "adiabatic"), wall_u=0.01,
+                        g_beta=2e-3),
     ]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_sr"])
-@pytest.mark.parametrize("case", range(9))
+@pytest.mark.parametrize("case", range(11))
 def test_in_place_equals_two_buffer(gpu, precision, case):
     clb = _clb()
     w = cases()[case]
