@@ -670,6 +670,17 @@ size_t buffer_bytes3(const clb3d_desc& d)
 long long nodes3(const clb3d_desc& d) { return (long long)d.nx * d.ny * d.nz; }
 long long diag_blocks(const clb3d_desc& d) { return (nodes3(d) + 255) / 256; }
 
+// Occupancy of the interior launch.  FP32 storage with FP32 arithmetic needs 57 VGPRs, so 8 wavefronts
+// per SIMD fit, but fewer are faster (256 x 256 x 129 layer, one MI355X: 413.7 us per step at 8, 406.4
+// at 6, 404.7 at 5, against a 402 us ceiling of the access pattern): dynamic LDS the kernel does not
+// use holds a CU to 5 workgroups of 256 threads.  The FP64-arithmetic forms run at 4 wavefronts by
+// their registers.
+template <typename S, typename Real>
+constexpr size_t occupancy_lds3()
+{
+    return sizeof(S) == 4 && sizeof(Real) == 4 ? size_t(160 * 1024 / 5) : 0;
+}
+
 template <typename S, typename Real>
 int launch_step(clb3d_lattice* h, long long n)
 {
@@ -688,7 +699,8 @@ int launch_step(clb3d_lattice* h, long long n)
             CLB_HIP(hipGetLastError());
         }
         if (Zi.count > 0) {
-            hipLaunchKernelGGL((step3_kernel<S, Real, 0>), dim3(grid_of(Zi)), dim3(BNT3), 0, h->stream, src, dst, G, P, Zi, key);
+            constexpr size_t lds = occupancy_lds3<S, Real>();
+            hipLaunchKernelGGL((step3_kernel<S, Real, 0>), dim3(grid_of(Zi)), dim3(BNT3), lds, h->stream, src, dst, G, P, Zi, key);
             CLB_HIP(hipGetLastError());
         }
         h->cur ^= 1;
