@@ -421,7 +421,7 @@ def main():
     traffic = measured_traffic(hb["sites"])
     result["roofline"] = {"bound": "hbm", "achieved": g["achieved_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                           "frac": g["achieved_GBps"] / HBM_PEAK_GBPS, "traffic": traffic,
-                          "kernel": "batch_step_kernel<float, double, DEV=true, NT, unit rates>",
+                          "kernel": "batch_step_kernel<float, double, DEV=true, NT, unit rates, walls at rest>",
                           "algorithmic_bytes_per_launch": BYTES_PER_SITE["fp32_sr"] * hb["sites"],
                           "avg_launch_us": g["ms_per_step"] * 1e3,
                           "footprint_GB": hb["pool_GB"]}

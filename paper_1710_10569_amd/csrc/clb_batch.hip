@@ -95,7 +95,9 @@ __device__ __forceinline__ bool batch_node(const BatchLat& L, int tile, int lane
 // AA: the batch holds in-place lattices (a separate instantiation, so that batches without them keep
 // the register budget of the two-buffer update alone).  UNIT: every lattice has s_b = s3 = s4 =
 // lambda2 = 1 (the collision skips the moments those rates send to equilibrium; two-buffer batches).
-template <typename S, typename Real, bool DEV, bool NT, bool AA, bool UNIT = false>
+// REST (with UNIT): every wall of every lattice is at rest, so the wall step takes u_w = 0 at compile
+// time.
+template <typename S, typename Real, bool DEV, bool NT, bool AA, bool UNIT = false, bool REST = false>
 __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntry<Real>& E, int tile, int s)
 {
     int x = 0, y = 0;
@@ -106,8 +108,8 @@ __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntr
         const bool c = (E.L.cur ^ (s & 1)) != 0;
         const long long o_src = c ? E.L.off[1] : E.L.off[0];
         const long long o_dst = c ? E.L.off[0] : E.L.off[1];
-        node_update_wave<S, Real, DEV, NT, UNIT, true>(pool + o_src, pool + o_dst, E.L.G, E.P, x, y, valid,
-                                                       step_key(E.L.step + uint32_t(s)));
+        node_update_wave<S, Real, DEV, NT, UNIT, true, REST>(pool + o_src, pool + o_dst, E.L.G, E.P, x, y, valid,
+                                                             step_key(E.L.step + uint32_t(s)));
         return;
     }
     // the lattice's own step count sets the in-place form and the snapshot copies
@@ -121,7 +123,7 @@ __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntr
     else node_update_aa_wave<S, Real, DEV, false, NT, true>(A, snow, snext, E.L.G, E.P, x, y, valid, xb, step_key(t));
 }
 
-template <typename S, typename Real, bool DEV, bool NT, bool AA, bool UNIT = false>
+template <typename S, typename Real, bool DEV, bool NT, bool AA, bool UNIT = false, bool REST = false>
 __global__ __launch_bounds__(BNT) void batch_step_kernel(S* __restrict__ pool, const BatchEntry<Real>* __restrict__ lats,
                                                        const TileRef* __restrict__ tiles, int tile_base, int ntiles,
                                                        int s)
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(BNT) void batch_step_kernel(S* __restrict__ pool, c
     if (t >= ntiles) return;
     const TileRef r = tiles[tile_base + t];
     const BatchEntry<Real> E = lats[r.lat];
-    batch_tile<S, Real, DEV, NT, AA, UNIT>(pool, E, r.tile, s);
+    batch_tile<S, Real, DEV, NT, AA, UNIT, REST>(pool, E, r.tile, s);
 }
 
 // After a call of nsteps steps: flip the current-buffer index of every listed slot if nsteps is
@@ -376,6 +378,7 @@ struct clb_batch {
     bool nt_chosen = false;               // store form set by the caller or the autotuner
     bool has_aa = false;                  // some resident lattice streams in place
     bool unit_rates = false;              // every resident lattice has s_b = s3 = s4 = lambda2 = 1
+    bool rest_walls = false;              // every wall of every resident lattice is at rest
 };
 
 namespace {
@@ -457,7 +460,7 @@ int upload_tables(clb_batch* b)
     std::vector<int> active;
     size_t resident = 0;
     b->has_aa = false;
-    bool all_unit = true;
+    bool all_unit = true, all_rest = true;
     for (int i = 0; i < cap; ++i) {
         BatchSlot& s = b->slots[i];
         if (!s.used) continue;
@@ -465,6 +468,8 @@ int upload_tables(clb_batch* b)
         resident += s.alloc_bytes;
         b->has_aa = b->has_aa || s.desc.in_place;
         all_unit = all_unit && s.par.s_b == 1.0 && s.par.s3 == 1.0 && s.par.s4 == 1.0 && s.par.lam2 == 1.0;
+        for (const clb_edge* e : {&s.desc.west, &s.desc.east, &s.desc.south, &s.desc.north})
+            all_rest = all_rest && (e->kind == CLB_PERIODIC || (e->ux == 0.0 && e->uy == 0.0));
         int nt;
         if (b->precision == CLB_FP32_DEV) {
             BatchEntry<float> E = make_entry<float>(s, s.tw_log2);
@@ -498,6 +503,7 @@ int upload_tables(clb_batch* b)
         CLB_HIP(hipMemcpyAsync(b->d_active, active.data(), active.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
     b->n_active = int(active.size());
     b->unit_rates = all_unit;
+    b->rest_walls = all_rest;
     // split for the persistent schedule: small lattices are workgroup-resident, the rest grouped
     b->small_slots.clear();
     b->tiles_big.clear();
@@ -555,6 +561,9 @@ hipError_t grouped_launch(clb_batch* b, const TileRef* tiles, int tile_base, int
     if (b->has_aa) {
         if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
         else batch_step_kernel<S, Real, DEV, false, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+    } else if (b->unit_rates && b->rest_walls) {
+        if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, false, true, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+        else batch_step_kernel<S, Real, DEV, false, false, true, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
     } else if (b->unit_rates) {
         if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, false, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
         else batch_step_kernel<S, Real, DEV, false, false, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);

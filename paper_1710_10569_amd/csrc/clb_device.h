@@ -439,15 +439,18 @@ struct PullSource {
     }
 };
 
-template <typename Real, bool DEV, typename NB>
+// REST: every wall of the lattice is at rest (u_w = 0, hence impermeable); the wall velocity is then a
+// compile-time zero and the terms it multiplies are not formed (the result is the general form's up
+// to the sign of an exact zero).
+template <typename Real, bool DEV, bool REST = false, typename NB>
 __device__ __forceinline__ void wall_step_nb(const NB& nb, const Geo& G, const Par<Real>& P,
                                              int x, int y, Real f[9], Real g[5])
 {
     const WallGeom W = wall_geom(G, x, y);
     const bool onW = W.onW, onE = W.onE, onS = W.onS, onN = W.onN, corner = W.corner;
     const int dx = W.dx, dy = W.dy, vw = W.vw, tw = W.tw, tkind = W.tkind;
-    const Real uwx = sel4(P.uw[0][0], P.uw[1][0], P.uw[2][0], P.uw[3][0], vw);
-    const Real uwy = sel4(P.uw[0][1], P.uw[1][1], P.uw[2][1], P.uw[3][1], vw);
+    const Real uwx = REST ? Real(0) : sel4(P.uw[0][0], P.uw[1][0], P.uw[2][0], P.uw[3][0], vw);
+    const Real uwy = REST ? Real(0) : sel4(P.uw[0][1], P.uw[1][1], P.uw[2][1], P.uw[3][1], vw);
 
     Real ff[9], gf[5];
     nb.all(G, x + dx, y + dy, ff, gf);
@@ -472,7 +475,7 @@ __device__ __forceinline__ void wall_step_nb(const NB& nb, const Geo& G, const P
     for (int i = 0; i < 9; ++i)
         unk[i] = (ex_of(i) > 0 && onW) || (ex_of(i) < 0 && onE) || (ey_of(i) > 0 && onS) || (ey_of(i) < 0 && onN);
     const Real R0 = DEV ? Real(1) : Real(0);
-    const bool imperm = corner || ((G.perm >> vw) & 1) == 0;
+    const bool imperm = REST || corner || ((G.perm >> vw) & 1) == 0;
     // edge (inward normal k): the known populations are those with e.n <= 0, the outgoing ones
     // have e.n = -1; corner (inward (dx, dy)): known f_0 and the three populations from inside,
     // (-dx, 0), (0, -dy), (-dx, -dy), and the five with e_x = -dx or e_y = -dy left the domain.
@@ -824,7 +827,7 @@ struct ExchangeSource {
 // held by the adjacent lane takes that lane's pulled populations instead of loading them again
 // (one cross-lane move per population instead of 14 loads issued for one or two lanes of the
 // wavefront).  The adjacent lane's node is checked, so any node-to-lane mapping is correct.
-template <typename S, typename Real, bool DEV, bool NT, bool UNIT = false, bool B32 = false>
+template <typename S, typename Real, bool DEV, bool NT, bool UNIT = false, bool B32 = false, bool REST = false>
 __device__ __forceinline__ void node_update_wave(const S* __restrict__ src, S* __restrict__ dst, const Geo& G,
                                                  const Par<Real>& P, int x, int y, bool valid, uint32_t key)
 {
@@ -850,7 +853,7 @@ __device__ __forceinline__ void node_update_wave(const S* __restrict__ src, S* _
     for (int i = 0; i < 9; ++i) f[i] = Real(raw[i]);
 #pragma unroll
     for (int i = 0; i < 5; ++i) g[i] = Real(raw[9 + i]);
-    if (on_wall(G, x, y)) wall_step_nb<Real, DEV>(ExchangeSource<S, B32>{src, got, nb}, G, P, x, y, f, g);
+    if (on_wall(G, x, y)) wall_step_nb<Real, DEV, REST>(ExchangeSource<S, B32>{src, got, nb}, G, P, x, y, f, g);
     const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
     collide_f<Real, DEV, UNIT>(f, m, P);
     collide_g<Real, DEV, UNIT>(g, m, P);

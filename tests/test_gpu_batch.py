@@ -120,6 +120,26 @@ def test_admission_by_footprint_and_slot_reuse(gpu):
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_sr"])
+def test_walls_at_rest_form_equals_general_form(gpu, precision):
+    """A batch whose lattices all have unit rates and walls at rest takes the step with u_w = 0 at
+    compile time; adding one lattice with a moving wall switches the batch to the general form.  Both
+    match every lattice's run alone (the general single-lattice step) bitwise."""
+    clb = _clb()
+    ws = [W.cavity(64, Ra=1e5, seed=4), W.cavity(97, Ra=3e4, seed=5),
+          W.random_walled(70, 45, seed=6, kinds=("adiabatic", "dirichlet", "adiabatic", "dirichlet"), g_beta=2e-3),
+          W.random_walled(40, 33, seed=7, kinds=("periodic", "periodic", "dirichlet", "adiabatic"))]
+    for extra in (None, W.random_walled(50, 30, seed=8, wall_u=0.02)):
+        b = clb.Batch(8, precision, budget_bytes=256 << 20)
+        slots = [b.add_workload(w) for w in ws + ([extra] if extra else [])]
+        print(f"[batch] rest walls {precision} extra={extra is not None}", flush=True)
+        b.step(37)
+        for w, s in zip(ws, slots):
+            for a, r in zip(b.moments(s), alone(w, precision, 37)):
+                assert np.array_equal(a, r), (w["name"], precision, extra is not None)
+        b.close()
+
+
 def test_admission_refuses_buffers_of_4_gib(gpu):
     """The grouped step addresses a batch lattice's buffers with 32-bit byte offsets: a lattice whose
     population buffer needs 4 GiB or more (16384 x 16384 in FP32: 15 GB) is refused with CLB_EINVAL
