@@ -94,9 +94,8 @@ __device__ __forceinline__ bool batch_node(const BatchLat& L, int tile, int lane
 
 // AA: the batch holds in-place lattices (a separate instantiation, so that batches without them keep
 // the register budget of the two-buffer update alone).  UNIT: every lattice has s_b = s3 = s4 =
-// lambda2 = 1 (the collision skips the moments those rates send to equilibrium; two-buffer batches).
-// REST (with UNIT): every wall of every lattice is at rest, so the wall step takes u_w = 0 at compile
-// time.
+// lambda2 = 1 (the collision skips the moments those rates send to equilibrium).  REST (with UNIT):
+// every wall of every lattice is at rest, so the wall step takes u_w = 0 at compile time.
 template <typename S, typename Real, bool DEV, bool NT, bool AA, bool UNIT = false, bool REST = false>
 __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntry<Real>& E, int tile, int s)
 {
@@ -119,8 +118,8 @@ __device__ __forceinline__ void batch_tile(S* __restrict__ pool, const BatchEntr
     const S* snow = pool + (odd ? E.L.sn[1] : E.L.sn[0]);
     S* snext = pool + (odd ? E.L.sn[0] : E.L.sn[1]);
     const bool xb = E.L.xbands != 0;
-    if (odd) node_update_aa_wave<S, Real, DEV, true, NT, true>(A, snow, snext, E.L.G, E.P, x, y, valid, xb, step_key(t));
-    else node_update_aa_wave<S, Real, DEV, false, NT, true>(A, snow, snext, E.L.G, E.P, x, y, valid, xb, step_key(t));
+    if (odd) node_update_aa_wave<S, Real, DEV, true, NT, true, UNIT, REST>(A, snow, snext, E.L.G, E.P, x, y, valid, xb, step_key(t));
+    else node_update_aa_wave<S, Real, DEV, false, NT, true, UNIT, REST>(A, snow, snext, E.L.G, E.P, x, y, valid, xb, step_key(t));
 }
 
 template <typename S, typename Real, bool DEV, bool NT, bool AA, bool UNIT = false, bool REST = false>
@@ -558,7 +557,13 @@ hipError_t grouped_launch(clb_batch* b, const TileRef* tiles, int tile_base, int
     S* pool = (S*)b->pool;
     constexpr size_t lds = occupancy_lds<S, Real>();
     const BatchEntry<Real>* lats = (const BatchEntry<Real>*)b->d_lats;
-    if (b->has_aa) {
+    if (b->has_aa && b->unit_rates && b->rest_walls) {
+        if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, true, true, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+        else batch_step_kernel<S, Real, DEV, false, true, true, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+    } else if (b->has_aa && b->unit_rates) {
+        if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, true, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+        else batch_step_kernel<S, Real, DEV, false, true, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
+    } else if (b->has_aa) {
         if (b->nontemporal) batch_step_kernel<S, Real, DEV, true, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
         else batch_step_kernel<S, Real, DEV, false, true><<<grid, block, lds, b->stream>>>(pool, lats, tiles, tile_base, ntiles, s);
     } else if (b->unit_rates && b->rest_walls) {

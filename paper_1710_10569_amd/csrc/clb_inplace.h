@@ -359,7 +359,7 @@ struct XchgSource {
 // the lanes next to it takes their loaded populations through cross-lane moves instead of the
 // snapshot.  xb = false: the lattice keeps no column bands, which is correct when every x-wall edge
 // node finds both neighbours in its wavefront (the caller's node-to-lane mapping guarantees it).
-template <typename S, typename Real, bool DEV, bool ODD, bool NT, bool B32 = false>
+template <typename S, typename Real, bool DEV, bool ODD, bool NT, bool B32 = false, bool UNIT = false, bool REST = false>
 __device__ __forceinline__ void node_update_aa_wave(S* __restrict__ A, const S* __restrict__ snow, S* __restrict__ snext,
                                                     const Geo& G, const Par<Real>& P, int x, int y, bool valid,
                                                     bool xb, uint32_t key)
@@ -396,10 +396,10 @@ __device__ __forceinline__ void node_update_aa_wave(S* __restrict__ A, const S* 
 #pragma unroll
     for (int i = 0; i < 5; ++i) g[i] = Real(raw[9 + i]);
     if (on_wall(G, x, y))
-        wall_step_nb<Real, DEV>(XchgSource<S>{SnapSource<S>{snow, A, xb}, got, got2, nb, nb2}, G, P, x, y, f, g);
+        wall_step_nb<Real, DEV, REST>(XchgSource<S>{SnapSource<S>{snow, A, xb}, got, got2, nb, nb2}, G, P, x, y, f, g);
     const Macro<Real, DEV> m = macro<Real, DEV>(f, g, P);
-    collide_f<Real, DEV>(f, m, P);
-    collide_g<Real, DEV>(g, m, P);
+    collide_f<Real, DEV, UNIT>(f, m, P);
+    collide_g<Real, DEV, UNIT>(g, m, P);
     S v[14];
     round_node<S, Real>(f, g, key, uint32_t(y) * uint32_t(G.nx) + uint32_t(x), v);
     store_aa<S, ODD, NT, B32>(A, snext, G, x, y, v, xb);
