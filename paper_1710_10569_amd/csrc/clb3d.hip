@@ -274,8 +274,12 @@ __host__ __device__ __forceinline__ void inv_line(Real* K, int m, Real u, Real u
     K[m + 2 * ST] = Real(0.5) * (m2 + m1);
 }
 
-// D3Q27 collision in place: f (deviations) -> post-collision deviations.
-template <typename Real>
+// D3Q27 collision in place: f (deviations) -> post-collision deviations.  UNIT: s_b = s3 = s4 = s5 = s6
+// = 1 (the default rates), so the trace of the second-order diagonal and every moment of order 3 to 6
+// relax to their equilibrium (plus half the forcing) in one step: the central moments of those orders
+// are not needed, and the compiler drops the parts of the forward transform that only they use.  The
+// result agrees with the general form to rounding (K - (K - K^eq) against K^eq).
+template <typename Real, bool UNIT = false>
 __host__ __device__ __forceinline__ void collide27(Real K[NQ], const Macro3<Real>& m, const Par3<Real>& P)
 {
     const Real u2[3] = {m.u[0] * m.u[0], m.u[1] * m.u[1], m.u[2] * m.u[2]};
@@ -301,8 +305,9 @@ __host__ __device__ __forceinline__ void collide27(Real K[NQ], const Macro3<Real
         }
         if (o == 1) { K[i] += C; continue; }        // conserved: S = 0
         if (o == 2 && n1 == 0) continue;            // k~200, k~020, k~002 below
-        const Real s = o == 2 ? P.s_nu : (o == 3 ? P.s3 : (o == 4 ? P.s4 : (o == 5 ? P.s5 : P.s6)));
         const Real De = delta_eq<Real>(a, b, c, m.dr, m.u, u2);
+        if (UNIT && o >= 3) { K[i] = De + Real(0.5) * C; continue; }
+        const Real s = o == 2 ? P.s_nu : (o == 3 ? P.s3 : (o == 4 ? P.s4 : (o == 5 ? P.s5 : P.s6)));
         K[i] = (K[i] - s * (K[i] - De)) + (Real(1) - Real(0.5) * s) * C;
     }
     {
@@ -311,7 +316,7 @@ __host__ __device__ __forceinline__ void collide27(Real K[NQ], const Macro3<Real
                    Dz = delta_eq<Real>(0, 0, 2, m.dr, m.u, u2);
         const Real kt = (K[2] + K[6]) + K[18], Dt = (Dx + Dy) + Dz;
         const Real third = Real(1.0 / 3.0);
-        const Real tr = (kt - P.s_b * (kt - Dt)) * third;
+        const Real tr = (UNIT ? Dt : kt - P.s_b * (kt - Dt)) * third;
         const Real ax = K[2] - kt * third, ay = K[6] - kt * third, az = K[18] - kt * third;
         K[2] = tr + (ax - P.s_nu * (ax - (Dx - Dt * third)));
         K[6] = tr + (ay - P.s_nu * (ay - (Dy - Dt * third)));
@@ -404,7 +409,7 @@ __host__ __device__ __forceinline__ int wall_of(const Geo3& G, int z)
 // the 34 post-collision populations are left in f, g.  WALL: 1 the node lies on a wall plane,
 // 0 it does not, -1 test at run time.  (The step launches the wall planes and the others
 // separately, so that the interior kernel carries none of the wall step's registers.)
-template <int WALL, typename S, typename Real>
+template <int WALL, bool UNIT = false, typename S, typename Real>
 __host__ __device__ __forceinline__ void update_node3(const S* __restrict__ src, const Geo3& G, const Par3<Real>& P, int x, int y,
                                                       int z, Real f[NQ], Real g[NTQ])
 {
@@ -414,7 +419,7 @@ __host__ __device__ __forceinline__ void update_node3(const S* __restrict__ src,
         if (WALL == 1 || w >= 0) wall_step3(src, G, P, x, y, z, w, f, g);
     }
     const Macro3<Real> m = macro3(f, g, P);
-    collide27(f, m, P);
+    collide27<Real, UNIT>(f, m, P);
     collide7(g, m, P);
 }
 
@@ -436,15 +441,16 @@ __host__ __device__ __forceinline__ void moments_node3(const S* __restrict__ src
     out[4 * n + k] = double(P.TR) + double(m.dT);
 }
 
-// One step over the planes of Z; WALL: Z is the two wall planes (1) or planes without walls (0).
-template <typename S, typename Real, int WALL>
+// One step over the planes of Z; WALL: Z is the two wall planes (1) or planes without walls (0);
+// UNIT: the unit-rate collision (collide27).
+template <typename S, typename Real, int WALL, bool UNIT = false>
 __global__ __launch_bounds__(BNT3) void step3_kernel(const S* __restrict__ src, S* __restrict__ dst, Geo3 G, Par3<Real> P,
                                                     Planes Z, uint32_t key)
 {
     int x, y, z;
     if (!node_of(G, Z, x, y, z)) return;
     Real f[NQ], g[NTQ];
-    update_node3<WALL>(src, G, P, x, y, z, f, g);
+    update_node3<WALL, UNIT>(src, G, P, x, y, z, f, g);
     store3<S, Real>(dst, row_base(G, y, z) + col_of(x), f, g, key, uint32_t(((long long)z * G.ny + y) * G.nx + x));
 }
 
@@ -690,17 +696,20 @@ int launch_step(clb3d_lattice* h, long long n)
     // step); periodic z: every plane in one launch
     const Planes Zw = planes(G, 0, 2, 1);
     const Planes Zi = G.walls ? planes(G, 1, G.nz - 2, 0) : all_planes(G);
+    const bool unit = h->s_b == 1.0 && h->s3 == 1.0 && h->s4 == 1.0 && h->s5 == 1.0 && h->s6 == 1.0;
+    constexpr size_t lds = occupancy_lds3<S, Real>();
     for (long long s = 0; s < n; ++s) {
         const S* src = static_cast<const S*>(h->buf[h->cur]);
         S* dst = static_cast<S*>(h->buf[h->cur ^ 1]);
         const uint32_t key = step_key(uint32_t(h->steps));
         if (G.walls) {
-            hipLaunchKernelGGL((step3_kernel<S, Real, 1>), dim3(grid_of(Zw)), dim3(BNT3), 0, h->stream, src, dst, G, P, Zw, key);
+            if (unit) hipLaunchKernelGGL((step3_kernel<S, Real, 1, true>), dim3(grid_of(Zw)), dim3(BNT3), 0, h->stream, src, dst, G, P, Zw, key);
+            else hipLaunchKernelGGL((step3_kernel<S, Real, 1>), dim3(grid_of(Zw)), dim3(BNT3), 0, h->stream, src, dst, G, P, Zw, key);
             CLB_HIP(hipGetLastError());
         }
         if (Zi.count > 0) {
-            constexpr size_t lds = occupancy_lds3<S, Real>();
-            hipLaunchKernelGGL((step3_kernel<S, Real, 0>), dim3(grid_of(Zi)), dim3(BNT3), lds, h->stream, src, dst, G, P, Zi, key);
+            if (unit) hipLaunchKernelGGL((step3_kernel<S, Real, 0, true>), dim3(grid_of(Zi)), dim3(BNT3), lds, h->stream, src, dst, G, P, Zi, key);
+            else hipLaunchKernelGGL((step3_kernel<S, Real, 0>), dim3(grid_of(Zi)), dim3(BNT3), lds, h->stream, src, dst, G, P, Zi, key);
             CLB_HIP(hipGetLastError());
         }
         h->cur ^= 1;
