@@ -140,6 +140,44 @@ def test_walls_at_rest_form_equals_general_form(gpu, precision):
         b.close()
 
 
+RATES = dict(s_b=1.2, s3=1.1, s4=0.9, lambda2=1.3)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_sr"])
+@pytest.mark.parametrize("in_place", [False, True])
+def test_rate_and_wall_forms_equal_general_step(gpu, precision, in_place):
+    """The batch step's compile-time forms -- unit rates with walls at rest, unit rates, general rates --
+    for two-buffer and in-place lattices (the in-place batch kernel takes them too): a batch of cavities
+    at rest, then the same with a moving-wall lattice added, then with a lattice whose rates are away
+    from 1 added.  Every lattice matches its run alone (the single-lattice step in its general form,
+    with the same rates) bitwise after an odd number of steps."""
+    clb = _clb()
+    base = [W.cavity(64, Ra=1e5, seed=4), W.cavity(97, Ra=3e4, seed=5),
+            W.random_walled(70, 45, seed=6, kinds=("adiabatic", "dirichlet", "adiabatic", "dirichlet"), g_beta=2e-3)]
+    moving = W.random_walled(50, 30, seed=8, wall_u=0.02)
+    rated = W.random_walled(45, 40, seed=9, kinds=("dirichlet", "adiabatic", "adiabatic", "dirichlet"), g_beta=2e-3)
+    for extra in ([], [(moving, None)], [(moving, None), (rated, RATES)]):
+        items = [(w, None) for w in base] + extra
+        b = clb.Batch(8, precision, budget_bytes=256 << 20)
+        slots = []
+        for w, rates in items:
+            s = b.add_workload(w, in_place=in_place)
+            if rates:
+                b.set_relaxation(s, **rates)
+            slots.append(s)
+        print(f"[batch] forms {precision} in_place={in_place} extra={len(extra)}", flush=True)
+        b.step(37)
+        for (w, rates), s in zip(items, slots):
+            g = clb.lattice_from_workload(w, precision)
+            if rates:
+                g.set_relaxation(**rates)
+            g.step(37)
+            for a, r in zip(b.moments(s), g.moments()):
+                assert np.array_equal(a, r), (w["name"], precision, in_place, len(extra))
+            g.close()
+        b.close()
+
+
 def test_admission_refuses_buffers_of_4_gib(gpu):
     """The grouped step addresses a batch lattice's buffers with 32-bit byte offsets: a lattice whose
     population buffer needs 4 GiB or more (16384 x 16384 in FP32: 15 GB) is refused with CLB_EINVAL
