@@ -182,7 +182,10 @@ class Lattice:
             self._h = None
 
     def __del__(self):
-        self.close()
+        # at interpreter exit the module's globals may already be cleared; the process
+        # releases the device memory then anyway
+        if _lib is not None:
+            self.close()
 
     def __enter__(self):
         return self
@@ -391,7 +394,10 @@ class Batch:
             self._h = None
 
     def __del__(self):
-        self.close()
+        # at interpreter exit the module's globals may already be cleared; the process
+        # releases the device memory then anyway
+        if _lib is not None:
+            self.close()
 
     def add(self, nx, ny, edges=None, T0=0.0, tau_nu=1.0, tau_alpha=1.0, g_beta=0.0, Ma=0.0, in_place=False):
         d = make_desc(nx, ny, self.precision, edges, T0, in_place=in_place)

@@ -107,7 +107,10 @@ class Lattice3D:
             self._h = None
 
     def __del__(self):
-        self.close()
+        # at interpreter exit the module's globals may already be cleared; the process
+        # releases the device memory then anyway
+        if _lib is not None:
+            self.close()
 
     def set_params(self, tau_nu, tau_alpha, g_beta=0.0):
         _check(_lib.clb3d_set_params(self._h, tau_nu, tau_alpha, g_beta))
