@@ -370,9 +370,9 @@ def main():
                          "scaling hardware byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(independent lattices shard by lattice, one lattice would shard by slabs with a halo "
-              "exchange; neither is built here)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent lattices would shard by lattice, one lattice by slabs with a halo "
+              "exchange; neither is implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
