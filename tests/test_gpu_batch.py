@@ -352,7 +352,7 @@ def _serve_against_oracle(precision, cases, step_cap):
 
 
 def test_served_fp32_matches_fp64_oracle(gpu):
-    """North-star accuracy of the served form: FP32 deviation storage (FP64 collision, stochastic
+    """Accuracy bar of the served form: FP32 deviation storage (FP64 collision, stochastic
     rounding on store), served through the batch to a near-steady state (30000 steps), against the
     FP64 oracle run for the same number of steps -- max-norm error of u (relative to the convective
     scale Ma c_s) and of T (relative to max |T - T0|) within 1e-5.  With round-to-nearest FP32
