@@ -366,6 +366,39 @@ def test_served_fp32_matches_fp64_oracle(gpu):
         assert max(e["u"], e["T"]) * 10 < max(e0["u"], e0["T"]), (e, e0)
 
 
+def test_served_largest_sides_against_oracle(gpu):
+    """The largest cavities the served mix draws (side 1024 at Ra = 1e6, the top of both ranges, and
+    the mix's own largest request, side 864) batched with two small ones whose rows end in partial
+    storage chunks, FP32 storage with stochastic rounding, one grouped launch per step, two-buffer
+    and in place: after 200 steps every node of the large cavities against the FP64 oracle, u and
+    T within 1e-5 (relative to max |u_ref| and max |T_ref - T0|)."""
+    clb = _clb()
+    reqs = W.serving_requests(n=32, lam=1.0, seed=5)
+    big = max(reqs, key=lambda r: r["L"])
+    small = sorted(reqs, key=lambda r: r["L"])[:2]
+    cases = [(1024, 1e6, 31), (big["L"], big["Ra"], big["noise_seed"])] + [(r["L"], r["Ra"], r["noise_seed"]) for r in small]
+    steps = 200
+    ref = {}
+    for L, Ra, sd in cases[:2]:
+        o = oracle_from_workload(W.cavity(L, Ra=Ra, seed=sd))
+        o.step(steps)
+        ref[L] = o.moments()
+        o.close()
+    for in_place in (False, True):
+        budget = sum(clb.footprint(L, L, "fp32_sr", in_place=in_place) for L, _, _ in cases) + (64 << 20)
+        b = clb.Batch(len(cases), "fp32_sr", budget_bytes=budget)
+        slots = [b.add_workload(W.cavity(L, Ra=Ra, seed=sd), in_place=in_place) for L, Ra, sd in cases]
+        b.step(steps, "grouped")
+        b.check()
+        assert not any(v[2] for v in b.residuals().values())
+        for (L, Ra, sd), slot in zip(cases[:2], slots):
+            w = W.cavity(L, Ra=Ra, seed=sd)
+            e = field_errors(b.moments(slot), ref[L], w["T0"], w["u_scale"])
+            print(f"[batch] served side {L} Ra={Ra:.3g} in_place={in_place}: {e}", flush=True)
+            assert e["u"] < 1e-5 and e["T"] < 1e-5, (L, in_place, e)
+        b.close()
+
+
 def test_full_batch_sampled_against_oracle(gpu):
     """The 512-cavity batch in the launch configuration the benchmark times (one grouped launch
     per step over all cavities, autotuned tile mappings and store form), 2000 steps, FP32 storage
