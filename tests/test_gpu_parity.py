@@ -4,7 +4,8 @@ collision and stochastic rounding to 1e-5 relative in u and T; plain FP32 (FP32 
 round-to-nearest storage, not the accuracy-qualified mode) is held to 3e-5.  Velocity errors are
 relative to max |u_ref|, temperature errors to max |T_ref - T0|, density errors to max |rho_ref|
 (tests/helpers.py).  Sizes span several 64 x 4 workgroup tiles with ragged tails; the full-size
-case is the 2048 x 1024 Rayleigh-Benard cell in the launch configuration the benchmark times."""
+cases are the 2048 x 1024 Rayleigh-Benard cell and the 8192 x 4096 control lattice in the launch
+configuration the benchmark times."""
 import numpy as np
 import pytest
 
@@ -95,24 +96,10 @@ def test_cavity_256_fp64(gpu):
         assert worst(e) < FP64_TOL, e
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_RN_TOL), ("fp32_sr", FP32_TOL)])
-def test_rayleigh_benard_full_size(gpu, precision, tol):
-    """2048 x 1024 Rayleigh-Benard at Ra = 1e6, Ma = 0.3 in the benchmark's launch configuration,
-    started from convection rolls at half the convective velocity, 1000 steps: 1024 sampled nodes
-    and two full columns against the oracle's state stored by
-    tests/golden/make_rb2048_reference.py, errors relative to the whole field's max |u|,
-    max |T - T0| and max |rho|."""
-    import json
-    import os
-    clb = _clb()
-    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rb2048_rolls_1000_oracle.json")))
-    w = W.rayleigh_benard(rolls=0.5)
-    assert ref["workload"] == w["name"]
-    print(f"[parity] {w['name']} {precision} steps={ref['steps']}", flush=True)
-    g = clb.lattice_from_workload(w, precision)
-    g.step(ref["steps"])
-    rho, ux, uy, T = g.moments()
-    g.close()
+def _against_stored_samples(ref, moments):
+    """Errors of GPU fields at a stored oracle state's sampled nodes and full columns, relative to
+    the whole oracle field's max |u|, max |T - T0| and max |rho - 1| ("rho" is absolute)."""
+    rho, ux, uy, T = moments
     ys, xs = np.array(ref["samples"]["y"]), np.array(ref["samples"]["x"])
     cols = ref["columns"]["x"]
     U = max(ref["scale"]["ux"], ref["scale"]["uy"])
@@ -121,8 +108,53 @@ def test_rayleigh_benard_full_size(gpu, precision, tol):
              np.abs(uy[:, cols].T - np.array(ref["columns"]["uy"])).max())
     dT = max(np.abs(T[ys, xs] - ref["samples"]["T"]).max(), np.abs(T[:, cols].T - np.array(ref["columns"]["T"])).max())
     dr = max(np.abs(rho[ys, xs] - ref["samples"]["rho"]).max(), np.abs(rho[:, cols].T - np.array(ref["columns"]["rho"])).max())
-    e = {"u": du / U, "T": dT / ref["scale"]["T"], "rho": dr, "rho_p12": dr / ref["scale"]["rho"]}
+    return {"u": du / U, "T": dT / ref["scale"]["T"], "rho": dr, "rho_p12": dr / ref["scale"]["rho"]}
+
+
+def _stored(name):
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", name)))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_RN_TOL), ("fp32_sr", FP32_TOL)])
+def test_rayleigh_benard_full_size(gpu, precision, tol):
+    """2048 x 1024 Rayleigh-Benard at Ra = 1e6, Ma = 0.3 in the benchmark's launch configuration,
+    started from convection rolls at half the convective velocity, 1000 steps: 1024 sampled nodes
+    and two full columns against the oracle's state stored by
+    tests/golden/make_rb2048_reference.py, errors relative to the whole field's max |u|,
+    max |T - T0| and max |rho|."""
+    clb = _clb()
+    ref = _stored("rb2048_rolls_1000_oracle.json")
+    w = W.rayleigh_benard(rolls=0.5)
+    assert ref["workload"] == w["name"]
+    print(f"[parity] {w['name']} {precision} steps={ref['steps']}", flush=True)
+    g = clb.lattice_from_workload(w, precision)
+    g.step(ref["steps"])
+    e = _against_stored_samples(ref, g.moments())
+    g.close()
     print(f"[parity]   {precision}: {e}", flush=True)
+    assert e["u"] < tol and e["T"] < tol and e["rho"] < tol, e
+
+
+@pytest.mark.parametrize("precision,tol,in_place", [("fp64", FP64_TOL, False), ("fp32", FP32_RN_TOL, False),
+                                                    ("fp32_sr", FP32_TOL, False), ("fp32", FP32_RN_TOL, True)])
+def test_rayleigh_benard_control_size(gpu, precision, tol, in_place):
+    """8192 x 4096 Rayleigh-Benard (3.8 GB in FP32, far beyond the Infinity Cache: the lattice the
+    benchmark takes its single-lattice roofline on) in the benchmark's launch configuration, two
+    buffers in three precisions and in place in FP32, started from convection rolls, 100 steps:
+    1024 sampled nodes and two full columns against the oracle's state stored by
+    tests/golden/make_rb8192_reference.py."""
+    clb = _clb()
+    ref = _stored("rb8192_rolls_100_oracle.json")
+    w = W.rayleigh_benard(nx=8192, ny=4096, rolls=0.5)
+    assert ref["workload"] == w["name"]
+    print(f"[parity] {w['name']} {precision} in_place={in_place} steps={ref['steps']}", flush=True)
+    g = clb.lattice_from_workload(w, precision, in_place=in_place)
+    g.step(ref["steps"])
+    e = _against_stored_samples(ref, g.moments())
+    g.close()
+    print(f"[parity]   {precision} in_place={in_place}: {e}", flush=True)
     assert e["u"] < tol and e["T"] < tol and e["rho"] < tol, e
 
 
