@@ -137,6 +137,38 @@ def test_rayleigh_benard_3d_full_size(gpu):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "fp32_sr", "fp32"])
+def test_rayleigh_benard_3d_stored_state(gpu, precision):
+    """The benchmark's layer in its launch configuration, 50 steps from crossed rolls: 1024 sampled
+    nodes and two wall-to-wall columns against the oracle's state stored by
+    tests/golden/make_rb3d_reference.py; u relative to the whole field's max |u| (over the three
+    components), T to max |T - T0|, rho absolute."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rb3d_rolls_50_oracle.json")))
+    w = W.rayleigh_benard_3d(256, 256, 129, Ra=1e5, Ma=0.1, seed=3, rolls=0.5)
+    assert ref["workload"] == w["name"]
+    print(f"[3d] stored state {precision} steps={ref['steps']}", flush=True)
+    G = gpu_lattice(w, precision)
+    G.step(ref["steps"])
+    rho, u, T = G.moments()
+    G.close()
+    s, c = ref["samples"], ref["columns"]
+    zs, ys, xs = (np.array(s[k]) for k in ("z", "y", "x"))
+    comps = tuple(zip(u, ("ux", "uy", "uz")))
+    du = max(np.abs(a[zs, ys, xs] - s[k]).max() for a, k in comps)
+    dT = np.abs(T[zs, ys, xs] - s["T"]).max()
+    dr = np.abs(rho[zs, ys, xs] - s["rho"]).max()
+    for i, (x, y) in enumerate(c["xy"]):
+        du = max(du, max(np.abs(a[:, y, x] - np.array(c[k][i])).max() for a, k in comps))
+        dT = max(dT, np.abs(T[:, y, x] - np.array(c["T"][i])).max())
+        dr = max(dr, np.abs(rho[:, y, x] - np.array(c["rho"][i])).max())
+    e = {"u": float(du / ref["scale"]["u"]), "T": float(dT / ref["scale"]["T"]), "rho": float(dr)}
+    print(f"[3d]   {precision}: {e}", flush=True)
+    assert max(e.values()) < TOL[precision], (precision, e)
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("precision", ["fp64", "fp32_sr"])
 def test_closed_layer_conserves_mass_at_full_size(gpu, precision):
     """Walls on z = 0 and z = nz - 1 and buoyancy: the total mass stays constant (FP64: to rounding
