@@ -402,9 +402,10 @@ def test_served_largest_sides_against_oracle(gpu):
 def test_full_batch_sampled_against_oracle(gpu):
     """The 512-cavity batch in the launch configuration the benchmark times (one grouped launch
     per step over all cavities, autotuned tile mappings and store form), 2000 steps, FP32 storage
-    with stochastic rounding and plain FP32: a sample of cavities of sides 64 to 256 compared node
-    by node with the oracle, u and T within 1e-5 (stochastic rounding) and 3e-5 (plain FP32,
-    round-to-nearest), errors relative to max |u_ref| and max |T_ref - T0|; every cavity finite."""
+    with stochastic rounding and plain FP32, and plain FP32 in place (the benchmark's in-place
+    batch): a sample of cavities of sides 64 to 256 compared node by node with the oracle, u and T
+    within 1e-5 (stochastic rounding) and 3e-5 (plain FP32, round-to-nearest), errors relative to
+    max |u_ref| and max |T_ref - T0|; every cavity finite."""
     clb = _clb()
     specs = W.batch_cavity_specs()
     picked = []
@@ -418,10 +419,10 @@ def test_full_batch_sampled_against_oracle(gpu):
         o.step(steps)
         ref[i] = o.moments()
         o.close()
-    for precision, tol in (("fp32_sr", 1e-5), ("fp32", 3e-5)):
-        budget = sum(clb.footprint(L, L, precision) for L, _, _ in specs) + (64 << 20)
+    for precision, tol, in_place in (("fp32_sr", 1e-5, False), ("fp32", 3e-5, False), ("fp32", 3e-5, True)):
+        budget = sum(clb.footprint(L, L, precision, in_place=in_place) for L, _, _ in specs) + (64 << 20)
         b = clb.Batch(len(specs), precision, budget_bytes=budget)
-        slots = [b.add_workload(W.cavity(L, Ra=Ra, seed=sd)) for L, Ra, sd in specs]
+        slots = [b.add_workload(W.cavity(L, Ra=Ra, seed=sd), in_place=in_place) for L, Ra, sd in specs]
         assert all(s is not None for s in slots)
         b.autotune(2)          # leaves the state untouched
         b.step(steps, "grouped")
@@ -432,8 +433,8 @@ def test_full_batch_sampled_against_oracle(gpu):
             L, Ra, sd = specs[i]
             w = W.cavity(L, Ra=Ra, seed=sd)
             e = field_errors(b.moments(slots[i]), ref[i], w["T0"], w["u_scale"])
-            print(f"[batch] full batch {precision} cavity {i} L={L} Ra={Ra:.3g}: {e}", flush=True)
-            assert e["u"] < tol and e["T"] < tol, (precision, i, e)
+            print(f"[batch] full batch {precision} in_place={in_place} cavity {i} L={L} Ra={Ra:.3g}: {e}", flush=True)
+            assert e["u"] < tol and e["T"] < tol, (precision, in_place, i, e)
         b.close()
 
 
