@@ -304,7 +304,7 @@ def measured_traffic_3d(precision, sites):
     return t.get("precisions", {}).get(precision, {}).get("bytes_per_step")
 
 
-def run_3d(W, steps=200, warmup=10, error_steps=2000, precisions=("fp32", "fp32_sr", "fp64"), stream=None):
+def run_3d(W, steps=200, warmup=50, error_steps=2000, precisions=("fp32", "fp32_sr", "fp64"), stream=None):
     """The 3D path on a 256 x 256 x 129 Rayleigh-Benard layer (Ra = 1e5, started from convection
     rolls): steps per precision timed with HIP events, and the FP32 / SR fields against FP64 after
     error_steps steps."""
