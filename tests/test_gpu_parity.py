@@ -158,6 +158,42 @@ def test_rayleigh_benard_control_size(gpu, precision, tol, in_place):
     assert e["u"] < tol and e["T"] < tol and e["rho"] < tol, e
 
 
+def test_lattice_beyond_2_31_elements_equals_its_period(gpu):
+    """Maximum size: a periodic 16384 x 10240 lattice (168 M nodes, 2.35e9 population elements, so
+    element offsets pass 2^31 and byte offsets 2^32; 37.6 GB of populations in FP64) initialised
+    with the 64 x 64 Taylor-Green fields tiled 256 x 160 times.  The field has period 64, so every
+    64 x 64 tile must evolve exactly as the 64 x 64 lattice does: after 50 steps each tile equals it
+    bitwise in FP64 and in plain FP32 (round-to-nearest, so the rounding does not depend on the
+    node), and the 64 x 64 lattice agrees with the oracle."""
+    clb = _clb()
+    small = W.taylor_green(64)
+    rx, ry, steps = 256, 160, 50
+    big = dict(small, name="taylor_green_64x64_tiled", nx=64 * rx, ny=64 * ry,
+               fields={k: np.tile(v, (ry, rx)) for k, v in small["fields"].items()})
+    assert 14 * big["nx"] * big["ny"] > 2 ** 31
+    o = oracle_from_workload(small)
+    o.step(steps)
+    ref = o.moments()
+    o.close()
+    for precision in ("fp64", "fp32"):
+        g = clb.lattice_from_workload(small, precision)
+        g.step(steps)
+        ms = g.moments()
+        g.close()
+        e = field_errors(ms, ref, small["T0"])
+        print(f"[parity] taylor_green 64x64 {precision} vs oracle: {e}", flush=True)
+        assert e["u"] < (FP64_TOL if precision == "fp64" else FP32_RN_TOL), e
+        print(f"[parity] {big['nx']}x{big['ny']} {precision}: {steps} steps", flush=True)
+        G = clb.lattice_from_workload(big, precision)
+        G.step(steps)
+        mb = G.moments()
+        G.close()
+        for a, b in zip(mb, ms):
+            tiles = a.reshape(ry, 64, rx, 64)
+            assert np.array_equal(tiles, np.broadcast_to(b[None, :, None, :], tiles.shape)), precision
+        del mb
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", FP32_RN_TOL), ("fp32_sr", FP32_TOL)])
 def test_fp32_taylor_green(gpu, precision, tol):
     """Taylor-Green 64 x 64, 1000 steps: u against the decayed amplitude (max |u_ref| = 0.145 U0)."""
