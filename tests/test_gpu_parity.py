@@ -194,6 +194,34 @@ def test_lattice_beyond_2_31_elements_equals_its_period(gpu):
         del mb
 
 
+@pytest.mark.parametrize("nx,ny", [(64, 1 << 18), (1 << 20, 64), (1 << 14, 1 << 16)])
+def test_lattice_at_the_size_limits_equals_its_period(gpu, nx, ny):
+    """The largest lattices clb_create admits: the tallest (ny = 2^18, the initialisation and moment
+    kernels' grid then holds 65536 workgroups along y), the widest (nx = 2^20) and the most nodes
+    (2^30 in a 16384 x 65536 lattice: 120 GB of FP32 populations), each periodic and initialised
+    with the 64 x 64 Taylor-Green fields tiled; after 20 steps in plain FP32 every 64 x 64 tile
+    equals the 64 x 64 lattice bitwise."""
+    clb = _clb()
+    small = W.taylor_green(64)
+    steps = 20
+    g = clb.lattice_from_workload(small, "fp32")
+    g.step(steps)
+    ms = g.moments()
+    g.close()
+    rx, ry = nx // 64, ny // 64
+    big = dict(small, name=f"taylor_green_64x64_tiled_{nx}x{ny}", nx=nx, ny=ny,
+               fields={k: np.tile(v, (ry, rx)) for k, v in small["fields"].items()})
+    print(f"[parity] {nx}x{ny} fp32: {steps} steps", flush=True)
+    G = clb.lattice_from_workload(big, "fp32")
+    del big
+    G.step(steps)
+    mb = G.moments()
+    G.close()
+    for a, b in zip(mb, ms):
+        tiles = a.reshape(ry, 64, rx, 64)
+        assert np.array_equal(tiles, np.broadcast_to(b[None, :, None, :], tiles.shape))
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", FP32_RN_TOL), ("fp32_sr", FP32_TOL)])
 def test_fp32_taylor_green(gpu, precision, tol):
     """Taylor-Green 64 x 64, 1000 steps: u against the decayed amplitude (max |u_ref| = 0.145 U0)."""
