@@ -193,6 +193,39 @@ def test_admission_refuses_buffers_of_4_gib(gpu):
     b.close()
 
 
+@pytest.mark.parametrize("in_place", [False, True])
+def test_batch_lattice_just_under_4_gib_equals_its_period(gpu, in_place):
+    """The largest batch lattices: 8192 x 9344 in FP32, whose population buffer (4,286,578,688 B) is
+    8.4 MB short of the 4 GiB the grouped step's 32-bit byte offsets can address, periodic and
+    initialised with the 64 x 64 Taylor-Green fields tiled, batched with a small cavity, 20 grouped
+    steps: every 64 x 64 tile equals the 64 x 64 lattice run alone bitwise (plain FP32), two-buffer
+    and in place."""
+    clb = _clb()
+    small = W.taylor_green(64)
+    steps = 20
+    ref = alone(small, "fp32", steps)
+    nx, ny = 8192, 9344
+    big = dict(small, name="taylor_green_64x64_tiled_8192x9344", nx=nx, ny=ny,
+               fields={k: np.tile(v, (ny // 64, nx // 64)) for k, v in small["fields"].items()})
+    cav = W.cavity(64, Ra=1e5, seed=2)
+    budget = clb.footprint(nx, ny, "fp32", in_place=in_place) + clb.footprint(64, 64, "fp32", in_place=in_place) + (64 << 20)
+    b = clb.Batch(4, "fp32", budget_bytes=budget)
+    s_big = b.add_workload(big, in_place=in_place)
+    s_cav = b.add_workload(cav, in_place=in_place)
+    assert s_big is not None and s_cav is not None
+    del big
+    print(f"[batch] {nx}x{ny} fp32 in_place={in_place}: {steps} grouped steps", flush=True)
+    b.step(steps, "grouped")
+    b.check()
+    mb = b.moments(s_big)
+    for a, r in zip(mb, ref):
+        tiles = a.reshape(ny // 64, 64, nx // 64, 64)
+        assert np.array_equal(tiles, np.broadcast_to(r[None, :, None, :], tiles.shape)), in_place
+    for a, r in zip(b.moments(s_cav), alone(cav, "fp32", steps)):
+        assert np.array_equal(a, r)
+    b.close()
+
+
 def test_external_torch_pool(gpu):
     import torch
     clb = _clb()
