@@ -169,6 +169,42 @@ def test_rayleigh_benard_3d_stored_state(gpu, precision):
 
 
 @pytest.mark.gpu
+def test_3d_beyond_2_31_elements_equals_its_period(gpu):
+    """A periodic 512 x 512 x 256 layer (67 M nodes, 2.28e9 population elements, so element offsets
+    pass 2^31) initialised with random 64^3 periodic fields (density, velocity, temperature;
+    buoyancy and a body force act) tiled 8 x 8 x 4 times: after 20 steps every 64^3 block equals the
+    64^3 lattice bitwise in FP64 and plain FP32, and the 64^3 lattice agrees with the oracle."""
+    small = W.random_3d(64, 64, 64, seed=17)
+    steps = 20
+    rx, ry, rz = 8, 8, 4
+    fl = small["fields"]
+    tile = lambda a: np.tile(a, (rz, ry, rx))
+    big = dict(small, name="random_3d_64^3_tiled", nx=64 * rx, ny=64 * ry, nz=64 * rz,
+               fields={"rho": tile(fl["rho"]), "u": tuple(tile(c) for c in fl["u"]), "T": tile(fl["T"])})
+    assert 34 * big["nx"] * big["ny"] * big["nz"] > 2 ** 31
+    L = oracle_lattice(small)
+    L.step(steps)
+    ref = L.moments()
+    L.close()
+    for precision in ("fp64", "fp32"):
+        G = gpu_lattice(small, precision)
+        G.step(steps)
+        ms = G.moments()
+        G.close()
+        e = errors3(ms, ref, small["T0"])
+        print(f"[3d] random 64^3 {precision} vs oracle: {e}", flush=True)
+        assert max(e.values()) < TOL[precision], e
+        print(f"[3d] {big['nx']}x{big['ny']}x{big['nz']} {precision}: {steps} steps", flush=True)
+        B = gpu_lattice(big, precision)
+        B.step(steps)
+        rho, u, T = B.moments()
+        B.close()
+        for a, r in zip((rho, *u, T), (ms[0], *ms[1], ms[2])):
+            blocks = a.reshape(rz, 64, ry, 64, rx, 64)
+            assert np.array_equal(blocks, np.broadcast_to(r[None, :, None, :, None, :], blocks.shape)), precision
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("precision", ["fp64", "fp32_sr"])
 def test_closed_layer_conserves_mass_at_full_size(gpu, precision):
     """Walls on z = 0 and z = nz - 1 and buoyancy: the total mass stays constant (FP64: to rounding
