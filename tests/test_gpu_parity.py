@@ -164,7 +164,7 @@ def test_lattice_beyond_2_31_elements_equals_its_period(gpu):
     with the 64 x 64 Taylor-Green fields tiled 256 x 160 times.  The field has period 64, so every
     64 x 64 tile must evolve exactly as the 64 x 64 lattice does: after 50 steps each tile equals it
     bitwise in FP64 and in plain FP32 (round-to-nearest, so the rounding does not depend on the
-    node), and the 64 x 64 lattice agrees with the oracle."""
+    node; FP32 also in place), and the 64 x 64 lattice agrees with the oracle."""
     clb = _clb()
     small = W.taylor_green(64)
     rx, ry, steps = 256, 160, 50
@@ -183,15 +183,16 @@ def test_lattice_beyond_2_31_elements_equals_its_period(gpu):
         e = field_errors(ms, ref, small["T0"])
         print(f"[parity] taylor_green 64x64 {precision} vs oracle: {e}", flush=True)
         assert e["u"] < (FP64_TOL if precision == "fp64" else FP32_RN_TOL), e
-        print(f"[parity] {big['nx']}x{big['ny']} {precision}: {steps} steps", flush=True)
-        G = clb.lattice_from_workload(big, precision)
-        G.step(steps)
-        mb = G.moments()
-        G.close()
-        for a, b in zip(mb, ms):
-            tiles = a.reshape(ry, 64, rx, 64)
-            assert np.array_equal(tiles, np.broadcast_to(b[None, :, None, :], tiles.shape)), precision
-        del mb
+        for in_place in ((False, True) if precision == "fp32" else (False,)):
+            print(f"[parity] {big['nx']}x{big['ny']} {precision} in_place={in_place}: {steps} steps", flush=True)
+            G = clb.lattice_from_workload(big, precision, in_place=in_place)
+            G.step(steps)
+            mb = G.moments()
+            G.close()
+            for a, b in zip(mb, ms):
+                tiles = a.reshape(ry, 64, rx, 64)
+                assert np.array_equal(tiles, np.broadcast_to(b[None, :, None, :], tiles.shape)), (precision, in_place)
+            del mb
 
 
 @pytest.mark.parametrize("nx,ny", [(64, 1 << 18), (1 << 20, 64), (1 << 14, 1 << 16)])
