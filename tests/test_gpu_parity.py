@@ -223,6 +223,65 @@ def test_lattice_at_the_size_limits_equals_its_period(gpu, nx, ny):
         assert np.array_equal(tiles, np.broadcast_to(b[None, :, None, :], tiles.shape))
 
 
+def _rest_cavity(L=48, T0=0.3):
+    """A closed cavity at rest at its reference temperature, buoyancy on (Dirichlet walls at T0)."""
+    w = W.cavity(L, Ra=1e5, seed=2, noise=0.0, T_hot=T0, T_cold=T0)
+    return dict(w, name="rest_cavity", T0=T0, taus={"tau_nu": 0.7, "tau_alpha": 0.8, "g_beta": 1e-3},
+                fields={"rho": None, "ux": None, "uy": None, "T": np.full((L, L), T0)})
+
+
+def _conduction(nx=40, ny=33):
+    """Pure conduction between a hot south and a cold north wall, linear T, no buoyancy."""
+    w = W.rayleigh_benard(nx=nx, ny=ny, amp=0.0)
+    return dict(w, name="conduction", taus={"tau_nu": 0.8, "tau_alpha": 0.7, "g_beta": 0.0})
+
+
+def _check_steady(name, ms, w, precision):
+    rho, ux, uy, T = ms
+    T_init = w["fields"]["T"]
+    dev = precision != "fp64"          # populations stored as deviations from the rest equilibrium
+    assert np.all(rho == 1.0), (name, precision)
+    if name == "conduction" or dev:
+        # no force acts on the flow populations: they stay exactly at the rest equilibrium
+        assert np.all(ux == 0.0) and np.all(uy == 0.0), (name, precision)
+    else:
+        assert max(np.abs(ux).max(), np.abs(uy).max()) < 1e-18, (name, precision)
+    dT = np.abs(T - T_init).max()
+    if name == "rest" and precision == "fp32":
+        # the FP32 collision carries T0 rounded to FP32; every node holds exactly that value
+        assert np.all(T == float(np.float32(w["T0"]))), (name, precision)
+    elif name == "rest" and dev:
+        assert dT == 0.0, (name, precision)
+    elif precision in ("fp64", "fp64_dev"):
+        assert dT < 1e-15, (name, precision, dT)
+    else:
+        # FP32 storage: within two spacings of FP32 at the largest |T - T0| (0.5), 1.2e-7
+        assert dT < 2.0 ** -23, (name, precision, dT)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp64_dev", "fp32", "fp32_sr"])
+def test_steady_states_stay_steady(gpu, precision):
+    """Degenerate cases of the method: a closed cavity at rest at its reference temperature with
+    buoyancy on, and pure conduction (linear T between Dirichlet walls, no buoyancy) stay steady
+    over 1000 steps, single lattice two-buffer and in place and in one grouped batch: rho = 1 and,
+    where no force acts on the flow, u = 0 exactly; T to roundoff (exactly where the storage is
+    the deviation from T0 at rest)."""
+    clb = _clb()
+    cases = {"rest": _rest_cavity(), "conduction": _conduction()}
+    for name, w in cases.items():
+        for in_place in (False, True):
+            g = clb.lattice_from_workload(w, precision, in_place=in_place)
+            g.step(1000)
+            _check_steady(name, g.moments(), w, precision)
+            g.close()
+    b = clb.Batch(4, precision, budget_bytes=64 << 20)
+    slots = {name: b.add_workload(w) for name, w in cases.items()}
+    b.step(1000, "grouped")
+    for name, w in cases.items():
+        _check_steady(name, b.moments(slots[name]), w, precision)
+    b.close()
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", FP32_RN_TOL), ("fp32_sr", FP32_TOL)])
 def test_fp32_taylor_green(gpu, precision, tol):
     """Taylor-Green 64 x 64, 1000 steps: u against the decayed amplitude (max |u_ref| = 0.145 U0)."""
