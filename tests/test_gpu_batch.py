@@ -226,6 +226,38 @@ def test_batch_lattice_just_under_4_gib_equals_its_period(gpu, in_place):
     b.close()
 
 
+def test_empty_batch_and_zero_steps(gpu):
+    """Empty inputs: stepping a batch with no resident lattice (before any admission and after the
+    last removal) in every schedule does nothing and succeeds; zero steps leave a resident
+    lattice's state and step count bitwise unchanged; a negative count is refused."""
+    clb = _clb()
+    b = clb.Batch(4, "fp32_sr", budget_bytes=64 << 20)
+    for mode in ("grouped", "each", "persistent"):
+        b.step(10, mode)
+    b.check()
+    assert b.residuals() == {}
+    s = b.add_workload(W.cavity(48, Ra=1e4, seed=3))
+    t = b.add_workload(W.cavity(40, Ra=1e5, seed=4), in_place=True)
+    b.step(5)
+    before = {k: b.moments(k) for k in (s, t)}
+    for mode in ("grouped", "each", "persistent"):
+        b.step(0, mode)
+    for k in (s, t):
+        for a, r in zip(b.moments(k), before[k]):
+            assert np.array_equal(a, r)
+        assert b.diagnostics(k)["step"] == 5
+    with pytest.raises(clb.CLBError) as e:
+        b.step(-1)
+    assert e.value.code == clb.CLB_EINVAL
+    b.remove(s)
+    b.remove(t)
+    for mode in ("grouped", "each", "persistent"):
+        b.step(10, mode)
+    b.check()
+    assert b.residuals() == {} and b.info()["used_bytes"] == 0
+    b.close()
+
+
 def test_external_torch_pool(gpu):
     import torch
     clb = _clb()
