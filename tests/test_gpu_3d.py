@@ -206,6 +206,27 @@ def test_3d_beyond_2_31_elements_equals_its_period(gpu):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("precision", ["fp64", "fp32_sr"])
+def test_3d_zero_and_negative_steps(gpu, precision):
+    """Zero steps leave a walled 3D lattice's state and step count bitwise unchanged; a negative
+    count is refused with CLB_EINVAL and changes nothing either."""
+    from paper_1710_10569_amd import clb
+    w = W.random_3d(9, 7, 8, seed=5, walls=WALLS_A)
+    G = gpu_lattice(w, precision)
+    G.step(3)
+    before = G.moments()
+    G.step(0)
+    with pytest.raises(clb.CLBError) as e:
+        G.step(-2)
+    assert e.value.code == clb.CLB_EINVAL
+    after = G.moments()
+    assert np.array_equal(after[0], before[0]) and np.array_equal(after[2], before[2])
+    assert all(np.array_equal(a, b) for a, b in zip(after[1], before[1]))
+    assert G.diagnostics()["step"] == 3
+    G.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "fp32_sr"])
 def test_closed_layer_conserves_mass_at_full_size(gpu, precision):
     """Walls on z = 0 and z = nz - 1 and buoyancy: the total mass stays constant (FP64: to rounding
     of the sums; FP32 storage: to the stochastic rounding's unbiased jitter)."""
